@@ -1,0 +1,785 @@
+// gfx950 kernels of the streaming tensor-ring tracker.
+//
+// Notation (0-based, mode N-1 temporal): a TR-core G_k has lateral slices
+// G_k(i) of size R_k x R_{k+1} (Sec. 1).  For mode n the subchain slice of a
+// column k = l + L*rr of X_[n] is
+//     S(k) = G_{n+1}(i_{n+1}) ... G_{N-1}(i_{N-1}) G_0(i_0) ... G_{n-1}(i_{n-1})
+// (Def. subchain tensor) and G^{!=n}_[2][k, r + R_n*s] = S(k)[s, r]
+// (the mode-2 unfolding of Sec. 2).  The per-batch products of Alg. 4 are
+// P_n += X_[n] G^{!=n}_[2] (the MTTKRP-like product) and the Gram chain of
+// Prop. subchain Gram.
+
+#include <hip/hip_runtime.h>
+#include <hip/hip_bf16.h>
+#include <stdint.h>
+
+#include "tr_internal.h"
+
+namespace trk {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+// Accumulator type and the row held by register v of `lane` in a 16x16
+// MFMA result block (column lane % 16): the FP64 16x16x4 instruction keeps
+// rows lane/16 + 4v, the FP32 one rows 4(lane/16) + v.
+template <typename T> struct Acc;
+template <> struct Acc<double> {
+  typedef double type;
+  typedef d4 vec;
+  static __device__ inline int row(int lane, int v) { return (lane >> 4) + 4 * v; }
+};
+template <> struct Acc<float> {
+  typedef float type;
+  typedef f4 vec;
+  static __device__ inline int row(int lane, int v) { return 4 * (lane >> 4) + v; }
+};
+
+__device__ inline d4 mfma16(double a, double b, d4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+__device__ inline f4 mfma16(float a, float b, f4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+Geom make_geom(int N, const int64_t* I, const int* R, int n) {
+  Geom g;
+  g.N = N;
+  g.n = n;
+  for (int k = 0; k < MAXN; ++k) {
+    g.I[k] = k < N ? I[k] : 1;
+    g.R[k] = k < N ? R[k] : 1;
+  }
+  g.L = 1;
+  for (int k = 0; k < n; ++k) g.L *= I[k];
+  g.In = I[n];
+  g.Rr = 1;
+  for (int k = n + 1; k < N; ++k) g.Rr *= I[k];
+  g.d = R[n] * R[(n + 1) % N];
+  return g;
+}
+
+static int pad16(int64_t x) { return (int)((x + 15) / 16) * 16; }
+
+MttkrpPlan plan_mttkrp(const Geom& g, int xdtype) {
+  MttkrpPlan p;
+  const int NB = (g.d + 15) / 16;
+  int MT = pad16(g.In);
+  if (MT > 64) MT = 64;
+  while (MT > 16 && (MT / 16) * NB > 64) MT -= 16;
+  p.MT = MT;
+  p.mtiles = (int)((g.In + MT - 1) / MT);
+  p.psize = (xdtype == F64) ? 8 : 4;
+  const int64_t K = g.L * g.Rr;
+  const int64_t nchunks = (K + KC - 1) / KC;
+  const int64_t xbytes = K * g.In * (xdtype == F64 ? 8 : (xdtype == F32 ? 4 : 2));
+  int64_t ns = (512 + p.mtiles - 1) / p.mtiles;
+  const int64_t by_bytes = xbytes / ((int64_t)g.In * g.d * p.psize);
+  if (ns > by_bytes) ns = by_bytes;
+  if (ns > nchunks) ns = nchunks;
+  if (ns < 1) ns = 1;
+  if (const char* e = getenv("TRSTREAM_NSPLIT")) {
+    int64_t v = atoll(e);
+    if (v > 0) ns = v < nchunks ? v : nchunks;
+  }
+  int64_t per = (nchunks + ns - 1) / ns;
+  p.kchunk = per * KC;
+  p.nsplit = (int)((K + p.kchunk - 1) / p.kchunk);
+  return p;
+}
+
+size_t mttkrp_partial_bytes(const Geom& g, const MttkrpPlan& p) {
+  return (size_t)p.nsplit * (size_t)g.In * (size_t)g.d * (size_t)p.psize;
+}
+
+// ---------------------------------------------------------------------------
+// Subchain row: v = e_s^T S(k), i.e. row s of S(k), of length R_n.
+// idx holds i_q for every q != n of column k.
+// ---------------------------------------------------------------------------
+template <typename TC, int RM>
+__device__ inline void subchain_row(const Geom& g, const CoreView& cv, const int* idx, int s,
+                                    TC (&v)[RM]) {
+  const int N = g.N;
+  int q = g.n + 1 == N ? 0 : g.n + 1;
+  {
+    const TC* G = (const TC*)cv.ptr[q] + idx[q] * cv.si[q] + s * cv.sr[q];
+    const int Rq1 = g.R[q + 1 == N ? 0 : q + 1];
+    const int64_t ss = cv.ss[q];
+#pragma unroll
+    for (int b = 0; b < RM; ++b) v[b] = (b < Rq1) ? G[b * ss] : TC(0);
+  }
+  for (int j = 1; j < N - 1; ++j) {
+    q = q + 1 == N ? 0 : q + 1;
+    const TC* H = (const TC*)cv.ptr[q] + idx[q] * cv.si[q];
+    const int Rq = g.R[q];
+    const int Rq1 = g.R[q + 1 == N ? 0 : q + 1];
+    const int64_t sr = cv.sr[q], ss = cv.ss[q];
+    TC u[RM];
+#pragma unroll
+    for (int b = 0; b < RM; ++b) {
+      TC acc = TC(0);
+      if (b < Rq1) {
+#pragma unroll
+        for (int a = 0; a < RM; ++a)
+          if (a < Rq) acc += v[a] * H[a * sr + b * ss];
+      }
+      u[b] = acc;
+    }
+#pragma unroll
+    for (int b = 0; b < RM; ++b) v[b] = u[b];
+  }
+}
+
+// Decode column k of X_[n] into its X offset (without the i_n term) and the
+// multi-index of every other mode.
+__device__ inline int64_t decode_column(const Geom& g, int64_t k, int* idx) {
+  int64_t l = k % g.L, rr = k / g.L;
+  const int64_t off = l + g.L * g.In * rr;
+  for (int q = 0; q < g.n; ++q) {
+    idx[q] = (int)(l % g.I[q]);
+    l /= g.I[q];
+  }
+  for (int q = g.n + 1; q < g.N; ++q) {
+    idx[q] = (int)(rr % g.I[q]);
+    rr /= g.I[q];
+  }
+  idx[g.n] = 0;
+  return off;
+}
+
+// ---------------------------------------------------------------------------
+// MTTKRP: part[split][m][c] = sum over this split's columns k of
+//   X_[n][m, k] * G^{!=n}_[2][k, c]
+// One workgroup (4 waves) owns an MT x d tile and a contiguous K range.
+// Per chunk of KC columns: decode, build the KC subchain rows into LDS (B),
+// stage the MT x KC block of X (A), then 16x16x4 MFMAs; each wave owns the
+// 16x16 output blocks b = wave, wave+4, ...
+// ---------------------------------------------------------------------------
+template <typename T, typename TC, int RM, int MAXB>
+__global__ __launch_bounds__(256) void k_mttkrp(Geom g, int MT, int64_t kchunk,
+                                                const T* __restrict__ X, CoreView cv,
+                                                typename Acc<T>::type* __restrict__ part) {
+  typedef typename Acc<T>::type A;
+  typedef typename Acc<T>::vec V;
+  constexpr int KCP = KC + 1;
+  const int tid = threadIdx.x;
+  const int d = g.d;
+  const int NB = (d + 15) >> 4;
+  const int NTP = NB * 16;
+  extern __shared__ __align__(16) char smem[];
+  int64_t* xoff = (int64_t*)smem;                       // [KC]
+  int* idx = (int*)(xoff + KC);                          // [KC][MAXN]
+  T* Bs = (T*)(idx + KC * MAXN);                         // [KC][NTP]
+  T* As = Bs + KC * NTP;                                 // [MT][KCP]
+
+  const int split = blockIdx.x;
+  const int64_t m0 = (int64_t)blockIdx.y * MT;
+  const int64_t K = g.L * g.Rr;
+  const int64_t kbeg = (int64_t)split * kchunk;
+  const int64_t kend = kbeg + kchunk < K ? kbeg + kchunk : K;
+  const int wave = tid >> 6, lane = tid & 63;
+  const int nblk = (MT >> 4) * NB;
+  const int Rn = g.R[g.n];
+  const int Rn1 = g.R[g.n + 1 == g.N ? 0 : g.n + 1];
+
+  V acc[MAXB];
+#pragma unroll
+  for (int bi = 0; bi < MAXB; ++bi) acc[bi] = V{0, 0, 0, 0};
+
+  for (int64_t kb = kbeg; kb < kend; kb += KC) {
+    if (tid < KC) {
+      const int64_t k = kb + tid;
+      if (k < kend) {
+        xoff[tid] = decode_column(g, k, idx + tid * MAXN);
+      } else {
+        xoff[tid] = -1;
+      }
+    }
+    __syncthreads();
+    // subchain rows (kk, s) -> Bs[kk][r + Rn*s]
+    for (int w = tid; w < KC * Rn1; w += 256) {
+      const int kk = w / Rn1, s = w - kk * Rn1;
+      if (xoff[kk] >= 0) {
+        TC v[RM];
+        subchain_row<TC, RM>(g, cv, idx + kk * MAXN, s, v);
+#pragma unroll
+        for (int r = 0; r < RM; ++r)
+          if (r < Rn) Bs[kk * NTP + r + Rn * s] = (T)v[r];
+      } else {
+        for (int r = 0; r < Rn; ++r) Bs[kk * NTP + r + Rn * s] = T(0);
+      }
+    }
+    for (int w = tid; w < KC * (NTP - d); w += 256) {
+      const int kk = w / (NTP - d), c = d + (w - kk * (NTP - d));
+      Bs[kk * NTP + c] = T(0);
+    }
+    // X block -> As[m][kk]
+    if (g.L == 1) {
+      for (int e = tid; e < MT * KC; e += 256) {
+        const int m = e % MT, kk = e / MT;
+        const int64_t mg = m0 + m;
+        T val = T(0);
+        if (mg < g.In && xoff[kk] >= 0) val = X[xoff[kk] + mg];
+        As[m * KCP + kk] = val;
+      }
+    } else {
+      for (int e = tid; e < MT * KC; e += 256) {
+        const int kk = e % KC, m = e / KC;
+        const int64_t mg = m0 + m;
+        T val = T(0);
+        if (mg < g.In && xoff[kk] >= 0) val = X[xoff[kk] + g.L * mg];
+        As[m * KCP + kk] = val;
+      }
+    }
+    __syncthreads();
+    const int ar = lane & 15, ak = lane >> 4;
+#pragma unroll 2
+    for (int k0 = 0; k0 < KC; k0 += 4) {
+#pragma unroll
+      for (int bi = 0; bi < MAXB; ++bi) {
+        const int b = wave + 4 * bi;
+        if (b < nblk) {
+          const int rb = b / NB, cb = b - rb * NB;
+          const T a = As[(rb * 16 + ar) * KCP + k0 + ak];
+          const T bv = Bs[(k0 + ak) * NTP + cb * 16 + ar];
+          acc[bi] = mfma16(a, bv, acc[bi]);
+        }
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int bi = 0; bi < MAXB; ++bi) {
+    const int b = wave + 4 * bi;
+    if (b < nblk) {
+      const int rb = b / NB, cb = b - rb * NB;
+      const int col = cb * 16 + (lane & 15);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int64_t mg = m0 + rb * 16 + Acc<T>::row(lane, v);
+        if (mg < g.In && col < d) part[((size_t)split * g.In + mg) * d + col] = acc[bi][v];
+      }
+    }
+  }
+}
+
+template <typename T, typename TC, int RM, int MAXB>
+static hipError_t launch_mttkrp_t(const Geom& g, const MttkrpPlan& p, const void* X,
+                                  const CoreView& cv, void* part, hipStream_t st) {
+  const int NTP = ((g.d + 15) / 16) * 16;
+  const size_t lds = KC * sizeof(int64_t) + KC * MAXN * sizeof(int) +
+                     (size_t)KC * NTP * sizeof(T) + (size_t)p.MT * (KC + 1) * sizeof(T);
+  auto fn = k_mttkrp<T, TC, RM, MAXB>;
+  if (lds > 65536) {
+    hipError_t e = hipFuncSetAttribute((const void*)fn,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  dim3 grid(p.nsplit, p.mtiles);
+  hipLaunchKernelGGL(fn, grid, dim3(256), lds, st, g, p.MT, p.kchunk, (const T*)X, cv,
+                     (typename Acc<T>::type*)part);
+  return hipGetLastError();
+}
+
+template <typename T, typename TC, int RM>
+static hipError_t launch_mttkrp_r(const Geom& g, const MttkrpPlan& p, const void* X,
+                                  const CoreView& cv, void* part, hipStream_t st) {
+  const int nblk = (p.MT / 16) * ((g.d + 15) / 16);
+  const int per = (nblk + 3) / 4;
+  if (per <= 4) return launch_mttkrp_t<T, TC, RM, 4>(g, p, X, cv, part, st);
+  if (per <= 8) return launch_mttkrp_t<T, TC, RM, 8>(g, p, X, cv, part, st);
+  return launch_mttkrp_t<T, TC, RM, 16>(g, p, X, cv, part, st);
+}
+
+template <typename T, typename TC>
+static hipError_t launch_mttkrp_c(const Geom& g, const MttkrpPlan& p, const void* X,
+                                  const CoreView& cv, void* part, hipStream_t st) {
+  int rmax = 1;
+  for (int k = 0; k < g.N; ++k) rmax = g.R[k] > rmax ? g.R[k] : rmax;
+  if (rmax <= 4) return launch_mttkrp_r<T, TC, 4>(g, p, X, cv, part, st);
+  if (rmax <= 8) return launch_mttkrp_r<T, TC, 8>(g, p, X, cv, part, st);
+  return launch_mttkrp_r<T, TC, 16>(g, p, X, cv, part, st);
+}
+
+hipError_t launch_mttkrp(const Geom& g, const MttkrpPlan& p, const void* X, int xdt,
+                         const CoreView& cv, int cdt, void* part, hipStream_t st) {
+  if (xdt == F64 && cdt == F64) return launch_mttkrp_c<double, double>(g, p, X, cv, part, st);
+  if (xdt == F32 && cdt == F64) return launch_mttkrp_c<float, double>(g, p, X, cv, part, st);
+  if (xdt == F32 && cdt == F32) return launch_mttkrp_c<float, float>(g, p, X, cv, part, st);
+  return hipErrorInvalidValue;
+}
+
+// ---------------------------------------------------------------------------
+// Split-K reduction (fixed order), P accumulation and the right-multiply by
+// Q_n^{-1}: G_{n(2)} = P_n Q_n^dagger (Alg. 4).  16 rows per workgroup.
+// ---------------------------------------------------------------------------
+template <typename PT>
+__global__ __launch_bounds__(256) void k_reduce_solve(const PT* __restrict__ part, int nsplit,
+                                                      int64_t In, int d, double* P,
+                                                      int accumulate,
+                                                      const double* __restrict__ Minv,
+                                                      double* __restrict__ out) {
+  __shared__ double prow[16 * 257];
+  const int tid = threadIdx.x;
+  const int64_t r0 = (int64_t)blockIdx.x * 16;
+  for (int e = tid; e < 16 * d; e += 256) {
+    const int rr = e / d, c = e - rr * d;
+    const int64_t row = r0 + rr;
+    double sum = 0.0;
+    if (row < In) {
+      for (int sp = 0; sp < nsplit; ++sp) sum += (double)part[((size_t)sp * In + row) * d + c];
+      if (P) {
+        if (accumulate) sum += P[row * d + c];
+        P[row * d + c] = sum;
+      }
+    }
+    prow[rr * 257 + c] = sum;
+  }
+  if (!Minv) return;
+  __syncthreads();
+  for (int e = tid; e < 16 * d; e += 256) {
+    const int rr = e / d, c2 = e - rr * d;
+    const int64_t row = r0 + rr;
+    if (row >= In) continue;
+    double gsum = 0.0;
+    for (int c = 0; c < d; ++c) gsum += prow[rr * 257 + c] * Minv[c * d + c2];
+    out[row * d + c2] = gsum;
+  }
+}
+
+hipError_t launch_reduce_solve(const void* part, int psize, int nsplit, int64_t In, int d,
+                               double* P, int accumulate, const double* Minv, double* out,
+                               hipStream_t st) {
+  dim3 grid((unsigned)((In + 15) / 16));
+  if (psize == 8)
+    hipLaunchKernelGGL(k_reduce_solve<double>, grid, dim3(256), 0, st, (const double*)part,
+                       nsplit, In, d, P, accumulate, Minv, out);
+  else
+    hipLaunchKernelGGL(k_reduce_solve<float>, grid, dim3(256), 0, st, (const float*)part,
+                       nsplit, In, d, P, accumulate, Minv, out);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Gram matrices of core slices in the "transfer" layout:
+//   E[(a + Ra*a'), (b + Rb*b')] = sum_i G(i)[a,b] G(i)[a',b'].
+// E_k holds the same numbers as the paper's Gram tensor Z_k (Alg. 2),
+// Z_k[b, a, b', a'] = E_k[(a, a'), (b, b')]; products of E's in ring order
+// give the Gram chain of Prop. subchain Gram.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_gram_E(const double* __restrict__ G, int64_t rows,
+                                                int Ra, int Rb, double* __restrict__ E) {
+  const int dr = Ra * Ra, dc = Rb * Rb;
+  const int e = blockIdx.x * 256 + threadIdx.x;
+  if (e >= dr * dc) return;
+  const int rho = e / dc, kap = e - rho * dc;
+  const int a = rho % Ra, a2 = rho / Ra, b = kap % Rb, b2 = kap / Rb;
+  const int o1 = a + Ra * b, o2 = a2 + Ra * b2;
+  const int dd = Ra * Rb;
+  double s = 0.0;
+  for (int64_t i = 0; i < rows; ++i) s += G[i * dd + o1] * G[i * dd + o2];
+  E[e] = s;
+}
+
+hipError_t launch_gram_E(const double* G, int64_t rows, int Ra, int Rb, double* E,
+                         hipStream_t st) {
+  const int n = Ra * Ra * Rb * Rb;
+  hipLaunchKernelGGL(k_gram_E, dim3((n + 255) / 256), dim3(256), 0, st, G, rows, Ra, Rb, E);
+  return hipGetLastError();
+}
+
+// C = A * B (row-major FP64), one output per thread, 16x16 tiles through LDS.
+__global__ __launch_bounds__(256) void k_matmul(const double* __restrict__ A,
+                                                const double* __restrict__ B,
+                                                double* __restrict__ C, int d1, int d2, int d3) {
+  __shared__ double As[16][17], Bs[16][17];
+  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+  const int row = blockIdx.y * 16 + ty, col = blockIdx.x * 16 + tx;
+  double s = 0.0;
+  for (int k0 = 0; k0 < d2; k0 += 16) {
+    As[ty][tx] = (row < d1 && k0 + tx < d2) ? A[(size_t)row * d2 + k0 + tx] : 0.0;
+    Bs[ty][tx] = (k0 + ty < d2 && col < d3) ? B[(size_t)(k0 + ty) * d3 + col] : 0.0;
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < 16; ++k) s += As[ty][k] * Bs[k][tx];
+    __syncthreads();
+  }
+  if (row < d1 && col < d3) C[(size_t)row * d3 + col] = s;
+}
+
+hipError_t launch_matmul(const double* A, const double* B, double* C, int d1, int d2, int d3,
+                         hipStream_t st) {
+  dim3 grid((d3 + 15) / 16, (d1 + 15) / 16);
+  hipLaunchKernelGGL(k_matmul, grid, dim3(256), 0, st, A, B, C, d1, d2, d3);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Q-layout assembly and in-place Gauss-Jordan inverse (no pivoting: the
+// normal-equation matrices are symmetric positive definite).  One workgroup
+// of 1024 threads keeps the d x d matrix in registers, SLOTS elements each;
+// pivot row and column are exchanged through LDS, two barriers per pivot.
+// M is Rb^2 x Ra^2 (row-major) and
+//   Q[r + Ra*s, r' + Ra*s'] = M[s + Rb*s', r + Ra*r']
+// ---------------------------------------------------------------------------
+template <int SLOTS>
+__global__ __launch_bounds__(1024) void k_invert_spd(const double* __restrict__ M, int Ra,
+                                                     int Rb, double* Q, int accumulate,
+                                                     int store_Q, double* __restrict__ Qinv,
+                                                     int* status) {
+  __shared__ double rowk[256], colk[256];
+  __shared__ double sh_tol;
+  const int tid = threadIdx.x;
+  const int d = Ra * Rb;
+  const int dd = d * d;
+  double a[SLOTS];
+#pragma unroll
+  for (int s = 0; s < SLOTS; ++s) {
+    const int e = tid + 1024 * s;
+    double v = 0.0;
+    if (e < dd) {
+      const int i = e / d, j = e - i * d;
+      if (M) {
+        const int r = i % Ra, s1 = i / Ra, r2 = j % Ra, s2 = j / Ra;
+        v = M[(size_t)(s1 + Rb * s2) * (Ra * Ra) + (r + Ra * r2)];
+      }
+      if (Q && accumulate) v += Q[e];
+      if (Q && store_Q) Q[e] = v;
+    }
+    a[s] = v;
+  }
+  if (!Qinv) return;
+  // tolerance d * eps * max diagonal
+#pragma unroll
+  for (int s = 0; s < SLOTS; ++s) {
+    const int e = tid + 1024 * s;
+    if (e < dd) {
+      const int i = e / d, j = e - i * d;
+      if (i == j) colk[i] = a[s];
+    }
+  }
+  __syncthreads();
+  if (tid == 0) {
+    double mx = 0.0;
+    for (int i = 0; i < d; ++i) mx = colk[i] > mx ? colk[i] : mx;
+    sh_tol = (double)d * 2.220446049250313e-16 * mx;
+  }
+  __syncthreads();
+  const double tol = sh_tol;
+  bool bad = false;
+  for (int k = 0; k < d; ++k) {
+#pragma unroll
+    for (int s = 0; s < SLOTS; ++s) {
+      const int e = tid + 1024 * s;
+      if (e < dd) {
+        const int i = e / d, j = e - i * d;
+        if (i == k) rowk[j] = a[s];
+        if (j == k) colk[i] = a[s];
+      }
+    }
+    __syncthreads();
+    const double p = colk[k];
+    if (!(p > tol)) bad = true;
+    const double ip = 1.0 / p;
+#pragma unroll
+    for (int s = 0; s < SLOTS; ++s) {
+      const int e = tid + 1024 * s;
+      if (e < dd) {
+        const int i = e / d, j = e - i * d;
+        if (i == k) {
+          a[s] = (j == k) ? ip : a[s] * ip;
+        } else {
+          const double f = colk[i];
+          a[s] = (j == k) ? -f * ip : a[s] - f * (rowk[j] * ip);
+        }
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int s = 0; s < SLOTS; ++s) {
+    const int e = tid + 1024 * s;
+    if (e < dd) Qinv[e] = a[s];
+  }
+  if (bad && tid == 0 && status) status[0] = 1;
+}
+
+hipError_t launch_invert_spd(const double* M, int Ra, int Rb, double* Q, int accumulate,
+                             int store_Q, double* Qinv, int* status, hipStream_t st) {
+  const int d = Ra * Rb;
+  const int slots = (d * d + 1023) / 1024;
+  if (d > 256) return hipErrorInvalidValue;
+#define TRK_INV(S)                                                                      \
+  hipLaunchKernelGGL(k_invert_spd<S>, dim3(1), dim3(1024), 0, st, M, Ra, Rb, Q, accumulate, \
+                     store_Q, Qinv, status)
+  if (slots <= 1)
+    TRK_INV(1);
+  else if (slots <= 4)
+    TRK_INV(4);
+  else if (slots <= 8)
+    TRK_INV(8);
+  else if (slots <= 16)
+    TRK_INV(16);
+  else if (slots <= 32)
+    TRK_INV(32);
+  else
+    TRK_INV(64);
+#undef TRK_INV
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// dtype conversion, fills, finite check
+// ---------------------------------------------------------------------------
+__device__ inline double load_as_double(const void* p, int dt, int64_t i) {
+  if (dt == F64) return ((const double*)p)[i];
+  if (dt == F32) return (double)((const float*)p)[i];
+  return (double)__bfloat162float(((const __hip_bfloat16*)p)[i]);
+}
+
+__global__ void k_cast(const void* src, int sdt, void* dst, int ddt, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    if (sdt == F64 && ddt == F32) {
+      ((float*)dst)[i] = (float)((const double*)src)[i];
+    } else if (ddt == BF16) {
+      const float f = sdt == F64 ? (float)((const double*)src)[i] : ((const float*)src)[i];
+      ((__hip_bfloat16*)dst)[i] = __float2bfloat16(f);
+    } else if (ddt == F64) {
+      ((double*)dst)[i] = load_as_double(src, sdt, i);
+    } else if (ddt == F32) {
+      ((float*)dst)[i] = (float)load_as_double(src, sdt, i);
+    }
+  }
+}
+
+hipError_t launch_cast(const void* src, int sdt, void* dst, int ddt, int64_t n, hipStream_t st) {
+  int64_t blocks = (n + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL(k_cast, dim3((unsigned)blocks), dim3(256), 0, st, src, sdt, dst, ddt, n);
+  return hipGetLastError();
+}
+
+__global__ void k_fill(double* y, double v, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    y[i] = v;
+}
+
+hipError_t launch_fill(double* y, double v, int64_t n, hipStream_t st) {
+  int64_t blocks = (n + 255) / 256;
+  if (blocks > 1024) blocks = 1024;
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL(k_fill, dim3((unsigned)blocks), dim3(256), 0, st, y, v, n);
+  return hipGetLastError();
+}
+
+__global__ void k_check_finite(const void* x, int dt, int64_t n, int* flag) {
+  bool bad = false;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const double v = load_as_double(x, dt, i);
+    if (!isfinite(v)) bad = true;
+  }
+  if (bad) flag[0] = 1;
+}
+
+hipError_t launch_check_finite(const void* x, int dt, int64_t n, int* flag, hipStream_t st) {
+  int64_t blocks = (n + 255) / 256;
+  if (blocks > 2048) blocks = 2048;
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL(k_check_finite, dim3((unsigned)blocks), dim3(256), 0, st, x, dt, n, flag);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Reconstruction error: per workgroup, JT columns j of the temporal-mode
+// unfolding X_[N] (j = lin(i_0..i_{N-2})), all T slices:
+//   Xhat[j, t] = sum_c G_{N(2)}[t, c] G^{!=N}_[2][j, c]
+// (the identity X_[N] = G_{N(2)} (G^{!=N}_[2])^T of eq. tr_als).
+// ---------------------------------------------------------------------------
+template <typename TX, typename TC, int RM>
+__global__ __launch_bounds__(256) void k_recon_err(Geom g, int JT, const TX* __restrict__ X,
+                                                   CoreView cv, double* __restrict__ wg_out) {
+  extern __shared__ __align__(16) char smem[];
+  double* Bt = (double*)smem;                        // [JT][d+1]
+  int* idx = (int*)(Bt + (size_t)JT * (g.d + 1));    // [JT][MAXN]
+  __shared__ double red[2][256];
+  const int tid = threadIdx.x;
+  const int d = g.d;
+  const int Rn = g.R[g.n], Rn1 = g.R[0];
+  const int64_t J = g.L;                             // columns of X_[N]
+  const int64_t j0 = (int64_t)blockIdx.x * JT;
+  for (int jj = tid; jj < JT; jj += 256) {
+    const int64_t j = j0 + jj;
+    if (j < J) decode_column(g, j, idx + jj * MAXN);
+  }
+  __syncthreads();
+  for (int w = tid; w < JT * Rn1; w += 256) {
+    const int jj = w / Rn1, s = w - jj * Rn1;
+    if (j0 + jj < J) {
+      TC v[RM];
+      subchain_row<TC, RM>(g, cv, idx + jj * MAXN, s, v);
+#pragma unroll
+      for (int r = 0; r < RM; ++r)
+        if (r < Rn) Bt[jj * (d + 1) + r + Rn * s] = (double)v[r];
+    }
+  }
+  __syncthreads();
+  const int jl = tid % JT, tq = tid / JT, TQ = 256 / JT;
+  const int64_t j = j0 + jl;
+  double err = 0.0, nrm = 0.0;
+  const TC* GN = (const TC*)cv.ptr[g.n];
+  const int64_t sr = cv.sr[g.n], si = cv.si[g.n], ss = cv.ss[g.n];
+  if (j < J) {
+    for (int64_t t = tq; t < g.In; t += TQ) {
+      double xh = 0.0;
+      for (int s = 0; s < Rn1; ++s)
+        for (int r = 0; r < Rn; ++r)
+          xh += Bt[jl * (d + 1) + r + Rn * s] * (double)GN[r * sr + t * si + s * ss];
+      const double x = (double)X[j + J * t];
+      const double e = x - xh;
+      err += e * e;
+      nrm += x * x;
+    }
+  }
+  red[0][tid] = err;
+  red[1][tid] = nrm;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (tid < w) {
+      red[0][tid] += red[0][tid + w];
+      red[1][tid] += red[1][tid + w];
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    wg_out[2 * blockIdx.x] = red[0][0];
+    wg_out[2 * blockIdx.x + 1] = red[1][0];
+  }
+}
+
+static int recon_jt(int d) { return d <= 64 ? 64 : (d <= 128 ? 32 : 16); }
+
+int recon_err_blocks(const Geom& g) {
+  const int JT = recon_jt(g.d);
+  return (int)((g.L + JT - 1) / JT);
+}
+
+template <typename TX, typename TC>
+static hipError_t launch_recon_t(const Geom& g, const void* X, const CoreView& cv,
+                                 double* wg_out, int* nwg, hipStream_t st) {
+  const int JT = recon_jt(g.d);
+  const int blocks = recon_err_blocks(g);
+  const size_t lds = (size_t)JT * (g.d + 1) * sizeof(double) + (size_t)JT * MAXN * sizeof(int);
+  int rmax = 1;
+  for (int k = 0; k < g.N; ++k) rmax = g.R[k] > rmax ? g.R[k] : rmax;
+  if (rmax <= 8)
+    hipLaunchKernelGGL((k_recon_err<TX, TC, 8>), dim3(blocks), dim3(256), lds, st, g, JT,
+                       (const TX*)X, cv, wg_out);
+  else
+    hipLaunchKernelGGL((k_recon_err<TX, TC, 16>), dim3(blocks), dim3(256), lds, st, g, JT,
+                       (const TX*)X, cv, wg_out);
+  *nwg = blocks;
+  return hipGetLastError();
+}
+
+hipError_t launch_recon_err(const Geom& g, const void* X, int xdt, const CoreView& cv, int cdt,
+                            double* wg_out, int* nwg, hipStream_t st) {
+  if (xdt == F64 && cdt == F64) return launch_recon_t<double, double>(g, X, cv, wg_out, nwg, st);
+  if (xdt == F32 && cdt == F32) return launch_recon_t<float, float>(g, X, cv, wg_out, nwg, st);
+  if (xdt == F32 && cdt == F64) return launch_recon_t<float, double>(g, X, cv, wg_out, nwg, st);
+  return hipErrorInvalidValue;
+}
+
+__global__ void k_sum_pairs(const double* __restrict__ w, int n, double* out) {
+  __shared__ double red[2][256];
+  const int tid = threadIdx.x;
+  double a = 0.0, b = 0.0;
+  for (int i = tid; i < n; i += 256) {
+    a += w[2 * i];
+    b += w[2 * i + 1];
+  }
+  red[0][tid] = a;
+  red[1][tid] = b;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (tid < s) {
+      red[0][tid] += red[0][tid + s];
+      red[1][tid] += red[1][tid + s];
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    out[0] = red[0][0];
+    out[1] = red[1][0];
+  }
+}
+
+hipError_t launch_sum_pairs(const double* wg_out, int nwg, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_sum_pairs, dim3(1), dim3(256), 0, st, wg_out, nwg, out);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Fit-loss gradient assembly: out = scale * (G_(2) Q - P) in the caller's
+// core layout (strides sr, si, ss) and dtype.
+// ---------------------------------------------------------------------------
+template <typename TC>
+__global__ __launch_bounds__(256) void k_grad_combine(const TC* __restrict__ G, int64_t sr,
+                                                      int64_t si, int64_t ss, int64_t In,
+                                                      int Ra, int Rb,
+                                                      const double* __restrict__ Q,
+                                                      const double* __restrict__ P,
+                                                      double scale, TC* __restrict__ out) {
+  const int d = Ra * Rb;
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= In * d) return;
+  const int64_t i = e / d;
+  const int c2 = (int)(e - i * d);
+  double s = 0.0;
+  for (int c = 0; c < d; ++c) {
+    const int r = c % Ra, q = c / Ra;
+    s += (double)G[r * sr + i * si + q * ss] * Q[(size_t)c * d + c2];
+  }
+  s -= P[i * d + c2];
+  const int r2 = c2 % Ra, q2 = c2 / Ra;
+  out[r2 * sr + i * si + q2 * ss] = (TC)(scale * s);
+}
+
+hipError_t launch_grad_combine(const void* Gsrc, int cdt, int64_t sr, int64_t si, int64_t ss,
+                               int64_t In, int Ra, int Rb, const double* Q, const double* P,
+                               double scale, void* out, hipStream_t st) {
+  const int64_t n = In * Ra * Rb;
+  dim3 grid((unsigned)((n + 255) / 256));
+  if (cdt == F64)
+    hipLaunchKernelGGL(k_grad_combine<double>, grid, dim3(256), 0, st, (const double*)Gsrc, sr,
+                       si, ss, In, Ra, Rb, Q, P, scale, (double*)out);
+  else
+    hipLaunchKernelGGL(k_grad_combine<float>, grid, dim3(256), 0, st, (const float*)Gsrc, sr, si,
+                       ss, In, Ra, Rb, Q, P, scale, (float*)out);
+  return hipGetLastError();
+}
+
+__global__ void k_core_to_slices(const void* src, int cdt, int64_t sr, int64_t si, int64_t ss,
+                                 int64_t I, int Ra, int Rb, double* dst) {
+  const int d = Ra * Rb;
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= I * d) return;
+  const int64_t i = e / d;
+  const int c = (int)(e - i * d);
+  const int r = c % Ra, s = c / Ra;
+  const int64_t off = r * sr + i * si + s * ss;
+  dst[e] = cdt == F64 ? ((const double*)src)[off] : (double)((const float*)src)[off];
+}
+
+hipError_t launch_core_to_slices(const void* src, int cdt, int64_t sr, int64_t si, int64_t ss,
+                                 int64_t I, int Ra, int Rb, double* dst, hipStream_t st) {
+  const int64_t n = I * Ra * Rb;
+  hipLaunchKernelGGL(k_core_to_slices, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, src,
+                     cdt, sr, si, ss, I, Ra, Rb, dst);
+  return hipGetLastError();
+}
+
+}  // namespace trk

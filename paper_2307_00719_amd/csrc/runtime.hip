@@ -1,0 +1,804 @@
+// Host runtime and C ABI of the gfx950 streaming tensor-ring tracker.
+//
+// The handle keeps the streaming state of Alg. 4 on the device in FP64:
+//   G[k]   cores k < N-1 as slice-major rows (row i = G_{k(2)}[i, :], the
+//          column index r + R_k*s of Sec. 2's mode-2 unfolding);
+//   G[N-1] the temporal core, all slices seen so far (capacity `cap`);
+//   E[k]   Gram matrices of the cores in transfer layout (Z_k of Alg. 4);
+//   E[N-1] the Gram matrix of the newest temporal rows (Z_N^new);
+//   P[n], Q[n] the complementary matrices of Sec. 3.1 (row-major).
+// One time step (Alg. 4, update stage) is, per mode: the Gram chain and
+// the inverse of the normal-equation matrix, the MTTKRP-like product split
+// over K, the fixed-order split reduction fused with P += and the solve,
+// and the Gram refresh of the updated core.
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "tr_internal.h"
+#include "tr_stream.h"
+
+using namespace trk;
+
+struct tr_stream {
+  int N = 0;
+  int64_t I[MAXN] = {};  // I[0..N-2]; I[N-1] is the current batch size when used
+  int R[MAXN] = {};
+  int dt = F64;
+  int sketch = 0;
+  int64_t m = 0;
+  int rescale = 1, temporal_literal = 0, check_finite = 0;
+  uint64_t seed = 0;
+  int device = 0;
+  hipStream_t st = nullptr;
+  bool own_stream = false;
+  int64_t t_total = 0, cap = 0;
+  double* G[MAXN] = {};
+  double* E[MAXN] = {};
+  double* P[MAXN] = {};
+  double* Q[MAXN] = {};
+  double* Minv = nullptr;
+  double* chain[2] = {};
+  void* xcast = nullptr;
+  size_t xcast_bytes = 0;
+  double* xf64 = nullptr;
+  size_t xf64_bytes = 0;
+  void* part = nullptr;
+  size_t part_bytes = 0;
+  double* wg = nullptr;
+  size_t wg_n = 0;
+  double* pair = nullptr;
+  int* dstatus = nullptr;
+  double* hpinned = nullptr;
+  size_t hpinned_bytes = 0;
+  hipEvent_t copy_done = nullptr;
+  bool copy_pending = false;
+  std::string err;
+  tr_status poisoned = TR_OK;
+  // event profiling (tr_stream_profile)
+  bool prof = false;
+  std::vector<hipEvent_t> ev_pool;
+  size_t ev_used = 0;
+  std::vector<int> rec_kind;
+  std::vector<size_t> rec_ev;
+
+  int d(int k) const { return R[k] * R[(k + 1) % N]; }
+};
+
+namespace {
+
+tr_status fail(tr_stream* s, tr_status code, const std::string& msg) {
+  if (s) s->err = msg;
+  return code;
+}
+
+tr_status poison(tr_stream* s, tr_status code, const std::string& msg) {
+  s->err = msg;
+  s->poisoned = TR_ERR_STATE;
+  return code;
+}
+
+#define TR_HIP(call)                                                                   \
+  do {                                                                                 \
+    hipError_t e_ = (call);                                                            \
+    if (e_ != hipSuccess)                                                              \
+      return poison(s, TR_ERR_DEVICE, std::string(#call ": ") + hipGetErrorString(e_)); \
+  } while (0)
+
+template <typename T>
+hipError_t dev_alloc(T** p, size_t count) {
+  *p = nullptr;
+  if (count == 0) count = 1;
+  return hipMalloc((void**)p, count * sizeof(T));
+}
+
+hipError_t ensure(void** p, size_t* have, size_t need) {
+  if (need <= *have && *p) return hipSuccess;
+  if (*p) {
+    hipError_t e = hipFree(*p);
+    if (e != hipSuccess) return e;
+    *p = nullptr;
+  }
+  size_t n = std::max(need, (size_t)256);
+  hipError_t e = hipMalloc(p, n);
+  if (e == hipSuccess) *have = n;
+  return e;
+}
+
+CoreView state_view(const tr_stream* s, const double* temporal) {
+  CoreView v;
+  for (int k = 0; k < MAXN; ++k) {
+    v.ptr[k] = nullptr;
+    v.sr[k] = v.si[k] = v.ss[k] = 0;
+  }
+  for (int k = 0; k < s->N; ++k) {
+    v.ptr[k] = (k == s->N - 1) ? (const void*)temporal : (const void*)s->G[k];
+    v.sr[k] = 1;
+    v.si[k] = s->d(k);
+    v.ss[k] = s->R[k];
+  }
+  return v;
+}
+
+CoreView colmajor_view(int N, const int64_t* dims, const int* R, const void* const* cores) {
+  CoreView v;
+  for (int k = 0; k < MAXN; ++k) {
+    v.ptr[k] = nullptr;
+    v.sr[k] = v.si[k] = v.ss[k] = 0;
+  }
+  for (int k = 0; k < N; ++k) {
+    v.ptr[k] = cores[k];
+    v.sr[k] = 1;
+    v.si[k] = R[k];
+    v.ss[k] = (int64_t)R[k] * dims[k];
+  }
+  return v;
+}
+
+// Product of the transfer-layout Gram matrices E_{n+1} ... E_{n-1} in ring
+// order (the Gram chain of Alg. 4 / Prop. subchain Gram), with `temporal`
+// standing for the temporal factor.  Returns the device pointer holding
+// the R_{n+1}^2 x R_n^2 product.
+const double* chain_product(tr_stream* s, int n, const double* temporal, hipError_t* err) {
+  const int N = s->N;
+  std::vector<int> order;
+  for (int j = 1; j < N; ++j) order.push_back((n + j) % N);
+  auto fac = [&](int q) -> const double* { return q == N - 1 ? temporal : s->E[q]; };
+  const double* cur = fac(order[0]);
+  int rows = s->R[order[0]] * s->R[order[0]];
+  int cols = s->R[(order[0] + 1) % N] * s->R[(order[0] + 1) % N];
+  int pp = 0;
+  *err = hipSuccess;
+  for (size_t j = 1; j < order.size(); ++j) {
+    const int q = order[j];
+    const int c2 = s->R[(q + 1) % N] * s->R[(q + 1) % N];
+    *err = launch_matmul(cur, fac(q), s->chain[pp], rows, cols, c2, s->st);
+    if (*err != hipSuccess) return nullptr;
+    cur = s->chain[pp];
+    pp ^= 1;
+    cols = c2;
+  }
+  return cur;
+}
+
+int dtype_size(int dt) { return dt == F64 ? 8 : (dt == F32 ? 4 : 2); }
+
+tr_status check_host_finite(tr_stream* s, const void* x, int dt, int64_t n) {
+  if (dt == F64) {
+    const double* p = (const double*)x;
+    for (int64_t i = 0; i < n; ++i)
+      if (!std::isfinite(p[i])) return fail(s, TR_ERR_NONFINITE, "input holds NaN or Inf");
+  } else if (dt == F32) {
+    const float* p = (const float*)x;
+    for (int64_t i = 0; i < n; ++i)
+      if (!std::isfinite(p[i])) return fail(s, TR_ERR_NONFINITE, "input holds NaN or Inf");
+  }
+  return TR_OK;
+}
+
+// Brings a batch (host or device, any supported dtype) to the device in the
+// compute dtype; returns the device pointer through *out.
+tr_status stage_batch(tr_stream* s, const void* X, int xdt, int64_t n, int x_is_device,
+                      const void** out) {
+  const size_t bytes = (size_t)n * dtype_size(xdt);
+  const void* dsrc = X;
+  if (!x_is_device) {
+    tr_status c = check_host_finite(s, X, xdt, n);
+    if (c != TR_OK) return c;
+    if (s->copy_pending) {
+      TR_HIP(hipEventSynchronize(s->copy_done));
+      s->copy_pending = false;
+    }
+    if (bytes > s->hpinned_bytes) {
+      if (s->hpinned) TR_HIP(hipHostFree(s->hpinned));
+      s->hpinned = nullptr;
+      TR_HIP(hipHostMalloc((void**)&s->hpinned, bytes, hipHostMallocDefault));
+      s->hpinned_bytes = bytes;
+    }
+    std::memcpy(s->hpinned, X, bytes);
+    TR_HIP(ensure((void**)&s->xf64, &s->xf64_bytes, bytes));
+    TR_HIP(hipMemcpyAsync(s->xf64, s->hpinned, bytes, hipMemcpyHostToDevice, s->st));
+    TR_HIP(hipEventRecord(s->copy_done, s->st));
+    s->copy_pending = true;
+    dsrc = s->xf64;
+  } else if (s->check_finite) {
+    TR_HIP(hipMemsetAsync(s->dstatus + 1, 0, sizeof(int), s->st));
+    TR_HIP(launch_check_finite(X, xdt, n, s->dstatus + 1, s->st));
+    int flag = 0;
+    TR_HIP(hipMemcpyAsync(&flag, s->dstatus + 1, sizeof(int), hipMemcpyDeviceToHost, s->st));
+    TR_HIP(hipStreamSynchronize(s->st));
+    if (flag) return fail(s, TR_ERR_NONFINITE, "input holds NaN or Inf");
+  }
+  if (xdt == s->dt) {
+    *out = dsrc;
+    return TR_OK;
+  }
+  TR_HIP(ensure(&s->xcast, &s->xcast_bytes, (size_t)n * dtype_size(s->dt)));
+  TR_HIP(launch_cast(dsrc, xdt, s->xcast, s->dt, n, s->st));
+  *out = s->xcast;
+  return TR_OK;
+}
+
+tr_status ensure_partials(tr_stream* s, const Geom& g, const MttkrpPlan& p) {
+  TR_HIP(ensure(&s->part, &s->part_bytes, mttkrp_partial_bytes(g, p)));
+  return TR_OK;
+}
+
+tr_status grow_temporal(tr_stream* s, int64_t need) {
+  if (need <= s->cap) return TR_OK;
+  int64_t ncap = std::max(need, 2 * s->cap);
+  const int dN = s->d(s->N - 1);
+  double* nb = nullptr;
+  TR_HIP(dev_alloc(&nb, (size_t)ncap * dN));
+  TR_HIP(hipMemcpyAsync(nb, s->G[s->N - 1], (size_t)s->t_total * dN * sizeof(double),
+                        hipMemcpyDeviceToDevice, s->st));
+  TR_HIP(hipStreamSynchronize(s->st));
+  TR_HIP(hipFree(s->G[s->N - 1]));
+  s->G[s->N - 1] = nb;
+  s->cap = ncap;
+  return TR_OK;
+}
+
+enum { PK_MTT_T = 0, PK_MTT_N = 1, PK_CHAIN = 2, PK_SOLVE = 3, PK_GRAM = 4, PK_STEP = 5 };
+
+// Starts a profiled region of `kind`; returns its record index or -1.
+long prof_begin(tr_stream* s, int kind) {
+  if (!s->prof) return -1;
+  while (s->ev_used + 2 > s->ev_pool.size()) {
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return -1;
+    s->ev_pool.push_back(e);
+  }
+  const size_t a = s->ev_used;
+  s->ev_used += 2;
+  if (hipEventRecord(s->ev_pool[a], s->st) != hipSuccess) return -1;
+  s->rec_kind.push_back(kind);
+  s->rec_ev.push_back(a);
+  return (long)s->rec_kind.size() - 1;
+}
+
+void prof_end(tr_stream* s, long rec) {
+  if (rec < 0) return;
+  (void)hipEventRecord(s->ev_pool[s->rec_ev[rec] + 1], s->st);
+}
+
+tr_status read_status(tr_stream* s) {
+  int st[2] = {0, 0};
+  TR_HIP(hipMemcpyAsync(st, s->dstatus, sizeof(int), hipMemcpyDeviceToHost, s->st));
+  TR_HIP(hipStreamSynchronize(s->st));
+  if (st[0]) return poison(s, TR_ERR_SINGULAR, "a normal-equation matrix was not positive definite");
+  return TR_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+tr_status tr_stream_init(const tr_config* cfg, const double* X_init, int64_t t_init,
+                         int32_t x_is_device, const double* const* cores_init,
+                         int32_t cores_on_device, tr_stream** out) {
+  if (!cfg || !out || !X_init || !cores_init) return TR_ERR_ARG;
+  *out = nullptr;
+  const int N = cfg->order;
+  if (N < 3 || N > MAXN || !cfg->dims || !cfg->ranks) return TR_ERR_ARG;
+  if (t_init < 1) return TR_ERR_SHAPE;
+  for (int k = 0; k < N - 1; ++k)
+    if (cfg->dims[k] < 1) return TR_ERR_SHAPE;
+  for (int k = 0; k < N; ++k)
+    if (cfg->ranks[k] < 1) return TR_ERR_SHAPE;
+  for (int k = 0; k < N; ++k)
+    if (cfg->ranks[k] > RMAXC) return TR_ERR_UNSUPPORTED;
+  if (cfg->compute_dtype != TR_F64 && cfg->compute_dtype != TR_F32) return TR_ERR_UNSUPPORTED;
+  if (cfg->sketch != TR_SKETCH_NONE) return TR_ERR_UNSUPPORTED;
+  for (int k = 0; k < N; ++k)
+    if (cfg->ranks[k] * cfg->ranks[(k + 1) % N] > 256) return TR_ERR_UNSUPPORTED;
+
+  tr_stream* s = new tr_stream();
+  s->N = N;
+  for (int k = 0; k < N - 1; ++k) s->I[k] = cfg->dims[k];
+  for (int k = 0; k < N; ++k) s->R[k] = cfg->ranks[k];
+  s->dt = cfg->compute_dtype;
+  s->sketch = cfg->sketch;
+  s->m = cfg->sketch_size;
+  s->rescale = cfg->rescale;
+  s->temporal_literal = cfg->temporal_literal;
+  s->seed = cfg->seed;
+  s->check_finite = cfg->check_finite;
+  s->device = cfg->device;
+  *out = s;
+
+  TR_HIP(hipSetDevice(s->device));
+  if (cfg->hip_stream) {
+    s->st = (hipStream_t)cfg->hip_stream;
+  } else {
+    TR_HIP(hipStreamCreateWithFlags(&s->st, hipStreamNonBlocking));
+    s->own_stream = true;
+  }
+  TR_HIP(hipEventCreateWithFlags(&s->copy_done, hipEventDisableTiming));
+
+  int dmax = 0;
+  for (int k = 0; k < N; ++k) dmax = std::max(dmax, s->d(k));
+  s->cap = std::max<int64_t>(cfg->max_slices, t_init + 1024);
+  for (int k = 0; k < N - 1; ++k) {
+    TR_HIP(dev_alloc(&s->G[k], (size_t)s->I[k] * s->d(k)));
+    TR_HIP(dev_alloc(&s->P[k], (size_t)s->I[k] * s->d(k)));
+    TR_HIP(dev_alloc(&s->Q[k], (size_t)s->d(k) * s->d(k)));
+  }
+  TR_HIP(dev_alloc(&s->G[N - 1], (size_t)s->cap * s->d(N - 1)));
+  for (int k = 0; k < N; ++k) {
+    const int rk = s->R[k], rk1 = s->R[(k + 1) % N];
+    TR_HIP(dev_alloc(&s->E[k], (size_t)rk * rk * rk1 * rk1));
+  }
+  TR_HIP(dev_alloc(&s->Minv, (size_t)dmax * dmax));
+  int emax = 0;
+  for (int k = 0; k < N; ++k) emax = std::max(emax, s->R[k] * s->R[k]);
+  TR_HIP(dev_alloc(&s->chain[0], (size_t)emax * emax));
+  TR_HIP(dev_alloc(&s->chain[1], (size_t)emax * emax));
+  TR_HIP(dev_alloc(&s->pair, 2));
+  TR_HIP(dev_alloc(&s->dstatus, 4));
+  TR_HIP(hipMemsetAsync(s->dstatus, 0, 4 * sizeof(int), s->st));
+
+  // cores: column-major FP64 (host or device) -> slice-major state
+  std::vector<int64_t> dims(N);
+  for (int k = 0; k < N - 1; ++k) dims[k] = s->I[k];
+  dims[N - 1] = t_init;
+  size_t maxcore = 0;
+  for (int k = 0; k < N; ++k) maxcore = std::max(maxcore, (size_t)dims[k] * s->d(k));
+  double* tmp = nullptr;
+  if (!cores_on_device) TR_HIP(dev_alloc(&tmp, maxcore));
+  for (int k = 0; k < N; ++k) {
+    const size_t cnt = (size_t)dims[k] * s->d(k);
+    const double* src = cores_init[k];
+    if (!src) return poison(s, TR_ERR_ARG, "null core pointer");
+    if (!cores_on_device) {
+      TR_HIP(hipMemcpyAsync(tmp, src, cnt * sizeof(double), hipMemcpyHostToDevice, s->st));
+      src = tmp;
+    }
+    TR_HIP(launch_core_to_slices(src, F64, 1, s->R[k], (int64_t)s->R[k] * dims[k], dims[k],
+                                 s->R[k], s->R[(k + 1) % N], s->G[k], s->st));
+    if (!cores_on_device) TR_HIP(hipStreamSynchronize(s->st));
+  }
+  if (tmp) TR_HIP(hipFree(tmp));
+  s->t_total = t_init;
+
+  // Gram matrices (Alg. 4 initialisation; Z_N over the initial temporal rows)
+  for (int k = 0; k < N; ++k) {
+    const int64_t rows = k == N - 1 ? t_init : s->I[k];
+    TR_HIP(launch_gram_E(s->G[k], rows, s->R[k], s->R[(k + 1) % N], s->E[k], s->st));
+  }
+  // X_init on the device in the compute dtype
+  int64_t J = 1;
+  for (int k = 0; k < N - 1; ++k) J *= s->I[k];
+  const void* Xd = nullptr;
+  tr_status c = stage_batch(s, X_init, F64, J * t_init, x_is_device, &Xd);
+  if (c != TR_OK) return c;
+
+  std::vector<int64_t> gd(dims);
+  const CoreView cv = state_view(s, s->G[N - 1]);
+  for (int n = 0; n < N - 1; ++n) {
+    Geom g = make_geom(N, gd.data(), s->R, n);
+    MttkrpPlan p = plan_mttkrp(g, s->dt);
+    c = ensure_partials(s, g, p);
+    if (c != TR_OK) return c;
+    TR_HIP(launch_mttkrp(g, p, Xd, s->dt, cv, F64, s->part, s->st));
+    TR_HIP(launch_reduce_solve(s->part, p.psize, p.nsplit, g.In, g.d, s->P[n], 0, nullptr,
+                               nullptr, s->st));
+    hipError_t he;
+    const double* M = chain_product(s, n, s->E[N - 1], &he);
+    TR_HIP(he);
+    TR_HIP(launch_invert_spd(M, s->R[n], s->R[(n + 1) % N], s->Q[n], 0, 1, nullptr, nullptr,
+                             s->st));
+  }
+  TR_HIP(hipStreamSynchronize(s->st));
+  s->copy_pending = false;
+  return TR_OK;
+}
+
+tr_status tr_stream_update(tr_stream* s, const void* X_new, int32_t x_dtype, int64_t t_new,
+                           int32_t x_is_device) {
+  if (!s) return TR_ERR_ARG;
+  if (s->poisoned != TR_OK) return s->poisoned;
+  if (!X_new) return fail(s, TR_ERR_ARG, "null batch");
+  if (t_new < 1) return fail(s, TR_ERR_SHAPE, "t_new must be positive");
+  if (x_dtype != TR_F64 && x_dtype != TR_F32) return fail(s, TR_ERR_UNSUPPORTED, "batch dtype");
+  const int N = s->N;
+  TR_HIP(hipSetDevice(s->device));
+  int64_t J = 1;
+  for (int k = 0; k < N - 1; ++k) J *= s->I[k];
+  tr_status c = grow_temporal(s, s->t_total + t_new);
+  if (c != TR_OK) return c;
+  const void* Xd = nullptr;
+  c = stage_batch(s, X_new, x_dtype, J * t_new, x_is_device, &Xd);
+  if (c != TR_OK) return c;
+
+  std::vector<int64_t> gd(N);
+  for (int k = 0; k < N - 1; ++k) gd[k] = s->I[k];
+  gd[N - 1] = t_new;
+  const int dN = s->d(N - 1);
+  double* Gnew = s->G[N - 1] + (size_t)s->t_total * dN;
+  hipError_t he;
+
+  const long pstep = prof_begin(s, PK_STEP);
+  long pr;
+  // temporal mode: G_N^new = X_[N]^new G^{!=N}_[2] (H^{!=N}_<2>)^+ (Alg. 4)
+  {
+    pr = prof_begin(s, PK_CHAIN);
+    const double* M = chain_product(s, N - 1, s->E[N - 1], &he);
+    TR_HIP(he);
+    TR_HIP(launch_invert_spd(M, s->R[N - 1], s->R[0], nullptr, 0, 0, s->Minv, s->dstatus,
+                             s->st));
+    prof_end(s, pr);
+    Geom g = make_geom(N, gd.data(), s->R, N - 1);
+    MttkrpPlan p = plan_mttkrp(g, s->dt);
+    c = ensure_partials(s, g, p);
+    if (c != TR_OK) return c;
+    const CoreView cv = state_view(s, Gnew);
+    pr = prof_begin(s, PK_MTT_T);
+    TR_HIP(launch_mttkrp(g, p, Xd, s->dt, cv, F64, s->part, s->st));
+    prof_end(s, pr);
+    pr = prof_begin(s, PK_SOLVE);
+    TR_HIP(launch_reduce_solve(s->part, p.psize, p.nsplit, g.In, g.d, nullptr, 0, s->Minv, Gnew,
+                               s->st));
+    prof_end(s, pr);
+    pr = prof_begin(s, PK_GRAM);
+    TR_HIP(launch_gram_E(Gnew, t_new, s->R[N - 1], s->R[0], s->E[N - 1], s->st));
+    prof_end(s, pr);
+  }
+  // non-temporal modes, in order (Alg. 4)
+  for (int n = 0; n < N - 1; ++n) {
+    pr = prof_begin(s, PK_CHAIN);
+    const double* M = chain_product(s, n, s->E[N - 1], &he);
+    TR_HIP(he);
+    TR_HIP(launch_invert_spd(M, s->R[n], s->R[(n + 1) % N], s->Q[n], 1, 1, s->Minv, s->dstatus,
+                             s->st));
+    prof_end(s, pr);
+    Geom g = make_geom(N, gd.data(), s->R, n);
+    MttkrpPlan p = plan_mttkrp(g, s->dt);
+    c = ensure_partials(s, g, p);
+    if (c != TR_OK) return c;
+    const CoreView cv = state_view(s, Gnew);
+    pr = prof_begin(s, PK_MTT_N);
+    TR_HIP(launch_mttkrp(g, p, Xd, s->dt, cv, F64, s->part, s->st));
+    prof_end(s, pr);
+    pr = prof_begin(s, PK_SOLVE);
+    TR_HIP(launch_reduce_solve(s->part, p.psize, p.nsplit, g.In, g.d, s->P[n], 1, s->Minv,
+                               s->G[n], s->st));
+    prof_end(s, pr);
+    pr = prof_begin(s, PK_GRAM);
+    TR_HIP(launch_gram_E(s->G[n], s->I[n], s->R[n], s->R[(n + 1) % N], s->E[n], s->st));
+    prof_end(s, pr);
+  }
+  prof_end(s, pstep);
+  s->t_total += t_new;
+  return TR_OK;
+}
+
+tr_status tr_stream_sync(tr_stream* s) {
+  if (!s) return TR_ERR_ARG;
+  if (s->poisoned != TR_OK) return s->poisoned;
+  TR_HIP(hipSetDevice(s->device));
+  TR_HIP(hipStreamSynchronize(s->st));
+  s->copy_pending = false;
+  return read_status(s);
+}
+
+tr_status tr_reconstruct_error(tr_stream* s, const double* X_all, int64_t t_all,
+                               int32_t x_is_device, double* rel_err) {
+  if (!s || !X_all || !rel_err) return TR_ERR_ARG;
+  if (s->poisoned != TR_OK) return s->poisoned;
+  if (t_all != s->t_total) return fail(s, TR_ERR_SHAPE, "t_all differs from the slices seen");
+  const int N = s->N;
+  TR_HIP(hipSetDevice(s->device));
+  tr_status c = read_status(s);
+  if (c != TR_OK) return c;
+  int64_t J = 1;
+  for (int k = 0; k < N - 1; ++k) J *= s->I[k];
+  const double* Xd = X_all;
+  double* tmp = nullptr;
+  if (!x_is_device) {
+    TR_HIP(dev_alloc(&tmp, (size_t)J * t_all));
+    TR_HIP(hipMemcpy(tmp, X_all, (size_t)J * t_all * sizeof(double), hipMemcpyHostToDevice));
+    Xd = tmp;
+  }
+  std::vector<int64_t> gd(N);
+  for (int k = 0; k < N - 1; ++k) gd[k] = s->I[k];
+  gd[N - 1] = t_all;
+  Geom g = make_geom(N, gd.data(), s->R, N - 1);
+  const int nwg = recon_err_blocks(g);
+  if ((size_t)nwg * 2 > s->wg_n) {
+    if (s->wg) TR_HIP(hipFree(s->wg));
+    TR_HIP(dev_alloc(&s->wg, (size_t)nwg * 2));
+    s->wg_n = (size_t)nwg * 2;
+  }
+  int got = 0;
+  TR_HIP(launch_recon_err(g, Xd, F64, state_view(s, s->G[N - 1]), F64, s->wg, &got, s->st));
+  TR_HIP(launch_sum_pairs(s->wg, got, s->pair, s->st));
+  double h[2];
+  TR_HIP(hipMemcpyAsync(h, s->pair, sizeof(h), hipMemcpyDeviceToHost, s->st));
+  TR_HIP(hipStreamSynchronize(s->st));
+  if (tmp) TR_HIP(hipFree(tmp));
+  *rel_err = h[1] > 0 ? std::sqrt(h[0] / h[1]) : std::sqrt(h[0]);
+  return TR_OK;
+}
+
+tr_status tr_stream_get_cores(tr_stream* s, double* const* cores_out) {
+  if (!s || !cores_out) return TR_ERR_ARG;
+  if (s->poisoned != TR_OK) return s->poisoned;
+  TR_HIP(hipSetDevice(s->device));
+  tr_status c = read_status(s);
+  if (c != TR_OK) return c;
+  const int N = s->N;
+  for (int k = 0; k < N; ++k) {
+    if (!cores_out[k]) return fail(s, TR_ERR_ARG, "null output core");
+    const int64_t I = k == N - 1 ? s->t_total : s->I[k];
+    const int Ra = s->R[k], Rb = s->R[(k + 1) % N], dk = Ra * Rb;
+    std::vector<double> h((size_t)I * dk);
+    TR_HIP(hipMemcpy(h.data(), s->G[k], h.size() * sizeof(double), hipMemcpyDeviceToHost));
+    double* o = cores_out[k];
+    for (int64_t i = 0; i < I; ++i)
+      for (int b = 0; b < Rb; ++b)
+        for (int a = 0; a < Ra; ++a) o[a + Ra * (i + I * b)] = h[(size_t)i * dk + a + Ra * b];
+  }
+  return TR_OK;
+}
+
+tr_status tr_stream_get_PQ(tr_stream* s, int32_t n, double* P, double* Q) {
+  if (!s) return TR_ERR_ARG;
+  if (s->poisoned != TR_OK) return s->poisoned;
+  if (n < 0 || n >= s->N - 1) return fail(s, TR_ERR_ARG, "mode out of range");
+  TR_HIP(hipSetDevice(s->device));
+  TR_HIP(hipStreamSynchronize(s->st));
+  const int dn = s->d(n);
+  if (P) TR_HIP(hipMemcpy(P, s->P[n], (size_t)s->I[n] * dn * sizeof(double), hipMemcpyDeviceToHost));
+  if (Q) TR_HIP(hipMemcpy(Q, s->Q[n], (size_t)dn * dn * sizeof(double), hipMemcpyDeviceToHost));
+  return TR_OK;
+}
+
+tr_status tr_stream_profile(tr_stream* s, int32_t enable) {
+  if (!s) return TR_ERR_ARG;
+  if (s->poisoned != TR_OK) return s->poisoned;
+  TR_HIP(hipSetDevice(s->device));
+  TR_HIP(hipStreamSynchronize(s->st));
+  if (enable) {
+    s->ev_used = 0;
+    s->rec_kind.clear();
+    s->rec_ev.clear();
+  }
+  s->prof = enable != 0;
+  return TR_OK;
+}
+
+tr_status tr_stream_profile_read(tr_stream* s, int32_t kind, double* total_ms,
+                                 int64_t* launches) {
+  if (!s || !total_ms || !launches) return TR_ERR_ARG;
+  if (s->poisoned != TR_OK) return s->poisoned;
+  TR_HIP(hipSetDevice(s->device));
+  TR_HIP(hipStreamSynchronize(s->st));
+  double tot = 0.0;
+  int64_t cnt = 0;
+  for (size_t r = 0; r < s->rec_kind.size(); ++r) {
+    const int k = s->rec_kind[r];
+    if (!(k == kind || (kind == 6 && (k == PK_MTT_T || k == PK_MTT_N)))) continue;
+    float ms = 0.f;
+    TR_HIP(hipEventElapsedTime(&ms, s->ev_pool[s->rec_ev[r]], s->ev_pool[s->rec_ev[r] + 1]));
+    tot += ms;
+    ++cnt;
+  }
+  *total_ms = tot;
+  *launches = cnt;
+  return TR_OK;
+}
+
+int64_t tr_stream_num_slices(const tr_stream* s) { return s ? s->t_total : -1; }
+
+const char* tr_last_error(const tr_stream* s) { return s ? s->err.c_str() : "null handle"; }
+
+void tr_stream_destroy(tr_stream* s) {
+  if (!s) return;
+  (void)hipSetDevice(s->device);
+  if (s->st) (void)hipStreamSynchronize(s->st);
+  for (int k = 0; k < MAXN; ++k) {
+    if (s->G[k]) (void)hipFree(s->G[k]);
+    if (s->E[k]) (void)hipFree(s->E[k]);
+    if (s->P[k]) (void)hipFree(s->P[k]);
+    if (s->Q[k]) (void)hipFree(s->Q[k]);
+  }
+  void* bufs[] = {s->Minv, s->chain[0], s->chain[1], s->xcast, s->xf64,
+                  s->part, s->wg,       s->pair,     s->dstatus};
+  for (void* b : bufs)
+    if (b) (void)hipFree(b);
+  for (hipEvent_t e : s->ev_pool) (void)hipEventDestroy(e);
+  if (s->hpinned) (void)hipHostFree(s->hpinned);
+  if (s->copy_done) (void)hipEventDestroy(s->copy_done);
+  if (s->own_stream && s->st) (void)hipStreamDestroy(s->st);
+  delete s;
+}
+
+// ---------------------------------------------------------------------------
+// Stateless entry points (fit loss and its pieces)
+// ---------------------------------------------------------------------------
+
+namespace {
+
+struct WsLayout {
+  size_t slices[MAXN];  // offsets of slice-major FP64 core copies
+  size_t E[MAXN];
+  size_t chain0, chain1, Q, P, part, wg, pair, total;
+};
+
+bool valid_shape(int32_t N, const int64_t* dims, const int32_t* ranks, int32_t dt) {
+  if (N < 3 || N > MAXN || !dims || !ranks) return false;
+  if (dt != TR_F64 && dt != TR_F32) return false;
+  for (int k = 0; k < N; ++k) {
+    if (dims[k] < 1 || ranks[k] < 1 || ranks[k] > RMAXC) return false;
+    if (ranks[k] * ranks[(k + 1) % N] > 256) return false;
+  }
+  return true;
+}
+
+WsLayout ws_layout(int32_t N, const int64_t* dims, const int32_t* ranks, int32_t dt) {
+  WsLayout w;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    size_t o = off;
+    off += (bytes + 255) / 256 * 256;
+    return o;
+  };
+  int dmax = 0, emax = 0;
+  size_t pmax = 0, partmax = 0;
+  for (int k = 0; k < N; ++k) {
+    const int dk = ranks[k] * ranks[(k + 1) % N];
+    dmax = std::max(dmax, dk);
+    emax = std::max(emax, ranks[k] * ranks[k]);
+    w.slices[k] = take((size_t)dims[k] * dk * 8);
+    w.E[k] = take((size_t)dk * dk * 8);
+    pmax = std::max(pmax, (size_t)dims[k] * dk * 8);
+    Geom g = make_geom(N, dims, ranks, k);
+    MttkrpPlan p = plan_mttkrp(g, dt);
+    partmax = std::max(partmax, mttkrp_partial_bytes(g, p));
+  }
+  w.chain0 = take((size_t)emax * emax * 8);
+  w.chain1 = take((size_t)emax * emax * 8);
+  w.Q = take((size_t)dmax * dmax * 8);
+  w.P = take(pmax);
+  w.part = take(partmax);
+  Geom gN = make_geom(N, dims, ranks, N - 1);
+  w.wg = take((size_t)recon_err_blocks(gN) * 2 * 8);
+  w.pair = take(16);
+  w.total = off;
+  return w;
+}
+
+__global__ void k_half_loss(const double* pair, double* loss) {
+  if (threadIdx.x == 0) loss[0] = 0.5 * pair[0];
+}
+
+}  // namespace
+
+size_t tr_workspace_bytes(int32_t N, const int64_t* dims, const int32_t* ranks, int32_t dt) {
+  if (!valid_shape(N, dims, ranks, dt)) return 0;
+  return ws_layout(N, dims, ranks, dt).total;
+}
+
+tr_status tr_mttkrp(int32_t N, const int64_t* dims, const int32_t* ranks, int32_t dt, int32_t n,
+                    const void* X, const void* const* cores, double* P_dev, int32_t accumulate,
+                    void* ws, size_t ws_bytes, void* hip_stream) {
+  if (!valid_shape(N, dims, ranks, dt) || !X || !cores || !P_dev || !ws) return TR_ERR_ARG;
+  if (n < 0 || n >= N) return TR_ERR_ARG;
+  WsLayout w = ws_layout(N, dims, ranks, dt);
+  if (ws_bytes < w.total) return TR_ERR_SHAPE;
+  hipStream_t st = (hipStream_t)hip_stream;
+  char* base = (char*)ws;
+  Geom g = make_geom(N, dims, ranks, n);
+  MttkrpPlan p = plan_mttkrp(g, dt);
+  CoreView cv = colmajor_view(N, dims, ranks, cores);
+  if (launch_mttkrp(g, p, X, dt, cv, dt, base + w.part, st) != hipSuccess) return TR_ERR_DEVICE;
+  if (launch_reduce_solve(base + w.part, p.psize, p.nsplit, g.In, g.d, P_dev, accumulate, nullptr,
+                          nullptr, st) != hipSuccess)
+    return TR_ERR_DEVICE;
+  return TR_OK;
+}
+
+static tr_status gram_chain_into(int32_t N, const int64_t* dims, const int32_t* ranks, int32_t dt,
+                                 int32_t n, const void* const* cores, double* Q_dev, char* base,
+                                 const WsLayout& w, hipStream_t st, bool grams_ready) {
+  if (!grams_ready) {
+    for (int k = 0; k < N; ++k) {
+      const int Ra = ranks[k], Rb = ranks[(k + 1) % N];
+      double* sl = (double*)(base + w.slices[k]);
+      if (launch_core_to_slices(cores[k], dt, 1, Ra, (int64_t)Ra * dims[k], dims[k], Ra, Rb, sl,
+                                st) != hipSuccess)
+        return TR_ERR_DEVICE;
+      if (launch_gram_E(sl, dims[k], Ra, Rb, (double*)(base + w.E[k]), st) != hipSuccess)
+        return TR_ERR_DEVICE;
+    }
+  }
+  double* cbuf[2] = {(double*)(base + w.chain0), (double*)(base + w.chain1)};
+  const double* cur = (const double*)(base + w.E[(n + 1) % N]);
+  int q0 = (n + 1) % N;
+  int rows = ranks[q0] * ranks[q0];
+  int cols = ranks[(q0 + 1) % N] * ranks[(q0 + 1) % N];
+  int pp = 0;
+  for (int j = 2; j < N; ++j) {
+    const int q = (n + j) % N;
+    const int c2 = ranks[(q + 1) % N] * ranks[(q + 1) % N];
+    if (launch_matmul(cur, (const double*)(base + w.E[q]), cbuf[pp], rows, cols, c2, st) !=
+        hipSuccess)
+      return TR_ERR_DEVICE;
+    cur = cbuf[pp];
+    pp ^= 1;
+    cols = c2;
+  }
+  if (launch_invert_spd(cur, ranks[n], ranks[(n + 1) % N], Q_dev, 0, 1, nullptr, nullptr, st) !=
+      hipSuccess)
+    return TR_ERR_DEVICE;
+  return TR_OK;
+}
+
+tr_status tr_gram_chain(int32_t N, const int64_t* dims, const int32_t* ranks, int32_t dt,
+                        int32_t n, const void* const* cores, double* Q_dev, void* ws,
+                        size_t ws_bytes, void* hip_stream) {
+  if (!valid_shape(N, dims, ranks, dt) || !cores || !Q_dev || !ws) return TR_ERR_ARG;
+  if (n < 0 || n >= N) return TR_ERR_ARG;
+  WsLayout w = ws_layout(N, dims, ranks, dt);
+  if (ws_bytes < w.total) return TR_ERR_SHAPE;
+  return gram_chain_into(N, dims, ranks, dt, n, cores, Q_dev, (char*)ws, w,
+                         (hipStream_t)hip_stream, false);
+}
+
+tr_status tr_fit_loss_fwd(int32_t N, const int64_t* dims, const int32_t* ranks, int32_t dt,
+                          const void* X, const void* const* cores, double* loss_dev, void* ws,
+                          size_t ws_bytes, void* hip_stream) {
+  if (!valid_shape(N, dims, ranks, dt) || !X || !cores || !loss_dev || !ws) return TR_ERR_ARG;
+  WsLayout w = ws_layout(N, dims, ranks, dt);
+  if (ws_bytes < w.total) return TR_ERR_SHAPE;
+  hipStream_t st = (hipStream_t)hip_stream;
+  char* base = (char*)ws;
+  Geom g = make_geom(N, dims, ranks, N - 1);
+  CoreView cv = colmajor_view(N, dims, ranks, cores);
+  int nwg = 0;
+  if (launch_recon_err(g, X, dt, cv, dt, (double*)(base + w.wg), &nwg, st) != hipSuccess)
+    return TR_ERR_DEVICE;
+  if (launch_sum_pairs((double*)(base + w.wg), nwg, (double*)(base + w.pair), st) != hipSuccess)
+    return TR_ERR_DEVICE;
+  hipLaunchKernelGGL(k_half_loss, dim3(1), dim3(64), 0, st, (const double*)(base + w.pair),
+                     loss_dev);
+  return hipGetLastError() == hipSuccess ? TR_OK : TR_ERR_DEVICE;
+}
+
+tr_status tr_fit_loss_bwd(int32_t N, const int64_t* dims, const int32_t* ranks, int32_t dt,
+                          const void* X, const void* const* cores, double grad_scale,
+                          void* const* grads, void* ws, size_t ws_bytes, void* hip_stream) {
+  if (!valid_shape(N, dims, ranks, dt) || !X || !cores || !grads || !ws) return TR_ERR_ARG;
+  WsLayout w = ws_layout(N, dims, ranks, dt);
+  if (ws_bytes < w.total) return TR_ERR_SHAPE;
+  hipStream_t st = (hipStream_t)hip_stream;
+  char* base = (char*)ws;
+  CoreView cv = colmajor_view(N, dims, ranks, cores);
+  double* Q = (double*)(base + w.Q);
+  double* P = (double*)(base + w.P);
+  for (int n = 0; n < N; ++n) {
+    tr_status c = gram_chain_into(N, dims, ranks, dt, n, cores, Q, base, w, st, n > 0);
+    if (c != TR_OK) return c;
+    Geom g = make_geom(N, dims, ranks, n);
+    MttkrpPlan p = plan_mttkrp(g, dt);
+    if (launch_mttkrp(g, p, X, dt, cv, dt, base + w.part, st) != hipSuccess) return TR_ERR_DEVICE;
+    if (launch_reduce_solve(base + w.part, p.psize, p.nsplit, g.In, g.d, P, 0, nullptr, nullptr,
+                            st) != hipSuccess)
+      return TR_ERR_DEVICE;
+    const int Ra = ranks[n], Rb = ranks[(n + 1) % N];
+    if (launch_grad_combine(cores[n], dt, 1, Ra, (int64_t)Ra * dims[n], dims[n], Ra, Rb, Q, P,
+                            grad_scale, grads[n], st) != hipSuccess)
+      return TR_ERR_DEVICE;
+  }
+  return TR_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,106 @@
+// Internal declarations shared by the kernel and runtime translation units
+// of the gfx950 streaming tensor-ring library.  Not part of the C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace trk {
+
+constexpr int MAXN = 8;     // maximum tensor order
+constexpr int RMAXC = 16;   // maximum TR-rank
+constexpr int KC = 32;      // K columns staged per MTTKRP chunk
+
+// Strided view of N TR-cores: element (r, i, s) of core k (r < R_k,
+// i < I_k, s < R_{k+1}) sits at ptr[k] + r*sr[k] + i*si[k] + s*ss[k].
+struct CoreView {
+  const void* ptr[MAXN];
+  int64_t sr[MAXN], si[MAXN], ss[MAXN];
+};
+
+// Geometry of one mode-n product: X has dims I[0..N-1] (column-major),
+// R[k] = R_k, R_{N} == R_0.  For mode n the columns of X_[n] are split as
+// k = l + L*rr with l = lin(i_0..i_{n-1}) and rr = lin(i_{n+1}..i_{N-1}).
+struct Geom {
+  int N, n;
+  int64_t I[MAXN];
+  int R[MAXN];
+  int64_t L, In, Rr;
+  int d;            // R_n * R_{n+1}
+};
+
+Geom make_geom(int N, const int64_t* I, const int* R, int n);
+
+enum DType { F64 = 0, F32 = 1, BF16 = 2 };
+
+struct MttkrpPlan {
+  int MT;        // rows per tile (multiple of 16)
+  int mtiles;    // ceil(In / MT)
+  int nsplit;    // K splits
+  int64_t kchunk;  // columns per split (multiple of KC)
+  int psize;     // bytes per partial element (8 f64 path, 4 f32/bf16 path)
+};
+
+MttkrpPlan plan_mttkrp(const Geom& g, int xdtype);
+size_t mttkrp_partial_bytes(const Geom& g, const MttkrpPlan& p);
+
+// ---- launchers (all asynchronous on `st`) --------------------------------
+
+// Partials part[split][m][c] of X_[n] * G^{!=n}_[2] for the cores in cv
+// (core dtype cdt: F64 or F32), X of dtype xdt.
+hipError_t launch_mttkrp(const Geom& g, const MttkrpPlan& p, const void* X, int xdt,
+                         const CoreView& cv, int cdt, void* part, hipStream_t st);
+
+// Sum the split partials (fixed order) into rows; optionally accumulate into
+// and store P; optionally multiply by Minv (d x d) and write rows of
+// out (row stride out_ld, dtype F64).
+hipError_t launch_reduce_solve(const void* part, int psize, int nsplit, int64_t In, int d,
+                               double* P, int accumulate, const double* Minv,
+                               double* out, hipStream_t st);
+
+// E_k[(a + Ra*a'), (b + Rb*b')] = sum_i G(i)[a,b] G(i)[a',b'] for rows
+// i in [0, rows) of a slice-major FP64 core (slice i at G + i*Ra*Rb).
+hipError_t launch_gram_E(const double* G, int64_t rows, int Ra, int Rb, double* E,
+                         hipStream_t st);
+
+// C (d1 x d3) = A (d1 x d2) * B (d2 x d3), row-major FP64.
+hipError_t launch_matmul(const double* A, const double* B, double* C, int d1, int d2, int d3,
+                         hipStream_t st);
+
+// Q-layout matrix from an E-layout chain product M (rows (s + Rb*s'),
+// columns (r + Ra*r')), optionally added to / stored in Q, then optionally
+// inverted in place by Gauss-Jordan into Qinv.  status[0] is set to 1 on a
+// non-positive or tiny pivot.
+hipError_t launch_invert_spd(const double* M, int Ra, int Rb, double* Q, int accumulate,
+                             int store_Q, double* Qinv, int* status, hipStream_t st);
+
+// Elementwise dtype conversion of n elements (round to nearest even).
+hipError_t launch_cast(const void* src, int sdt, void* dst, int ddt, int64_t n, hipStream_t st);
+
+// Per-workgroup sums of (X - Xhat)^2 and X^2 over a tensor whose last mode
+// has T slices, with Xhat from the cores in cv (temporal core slices are
+// the T rows of core N-1); writes nwg pairs into wg_out and returns nwg.
+hipError_t launch_recon_err(const Geom& gN, const void* X, int xdt, const CoreView& cv,
+                            int cdt, double* wg_out, int* nwg_out, hipStream_t st);
+int recon_err_blocks(const Geom& gN);
+
+// out[0..1] = fixed-order sums of the pairs in wg_out.
+hipError_t launch_sum_pairs(const double* wg_out, int nwg, double* out, hipStream_t st);
+
+// y[i] = alpha * y[i] + beta * x[i] for FP64 vectors (small helpers).
+hipError_t launch_fill(double* y, double v, int64_t n, hipStream_t st);
+
+// Finite check: flag[0] = 1 if any of the n elements is NaN/Inf.
+hipError_t launch_check_finite(const void* x, int dt, int64_t n, int* flag, hipStream_t st);
+
+// grads for the fit loss: out = scale * (G_(2) Q - P), written in the
+// core layout of view cv entry n with dtype cdt.
+hipError_t launch_grad_combine(const void* Gsrc, int cdt, int64_t sr, int64_t si, int64_t ss,
+                               int64_t In, int Ra, int Rb, const double* Q, const double* P,
+                               double scale, void* out, hipStream_t st);
+
+// Copy a strided core into slice-major FP64 rows and back.
+hipError_t launch_core_to_slices(const void* src, int cdt, int64_t sr, int64_t si, int64_t ss,
+                                 int64_t I, int Ra, int Rb, double* dst, hipStream_t st);
+
+}  // namespace trk

@@ -1,0 +1,71 @@
+"""Convenience wrapper around the streaming entry points of the C ABI."""
+
+import numpy as np
+
+from . import _lib
+
+
+class TRStream:
+    """Owns one ``tr_stream`` handle.
+
+    X_init and batches are (I_1, .., I_{N-1}, t) arrays (NumPy on the host, or
+    torch tensors on the device); cores are (R_n, I_n, R_{n+1}) arrays with the
+    temporal core holding t_init slices.
+    """
+
+    def __init__(self, X_init, cores_init, compute_dtype="f64", sketch=None, sketch_size=0,
+                 rescale=True, temporal_literal=False, seed=0, max_slices=0,
+                 check_finite=False, device=0, hip_stream=None):
+        self.dims = list(X_init.shape[:-1])
+        self.ranks = [int(G.shape[0]) for G in cores_init]
+        self.N = len(self.ranks)
+        self.handle = _lib.tr_stream_init(
+            X_init, cores_init, self.ranks, compute_dtype=compute_dtype, sketch=sketch,
+            sketch_size=sketch_size, rescale=rescale, temporal_literal=temporal_literal,
+            seed=seed, max_slices=max_slices, check_finite=check_finite, device=device,
+            hip_stream=hip_stream)
+        self._keep = None
+
+    def d(self, n):
+        return self.ranks[n] * self.ranks[(n + 1) % self.N]
+
+    def update(self, X_new):
+        self._keep = _lib.tr_stream_update(self.handle, X_new)
+
+    def sync(self):
+        _lib.tr_stream_sync(self.handle)
+
+    def profile(self, enable=True):
+        _lib.tr_stream_profile(self.handle, enable)
+
+    def profile_read(self, kind):
+        return _lib.tr_stream_profile_read(self.handle, kind)
+
+    def num_slices(self):
+        return _lib.tr_stream_num_slices(self.handle)
+
+    def reconstruct_error(self, X_all):
+        return _lib.tr_reconstruct_error(self.handle, X_all)
+
+    def cores(self):
+        return _lib.tr_stream_get_cores(self.handle, self.dims, self.ranks)
+
+    def PQ(self, n):
+        return _lib.tr_stream_get_PQ(self.handle, n, self.dims[n], self.d(n))
+
+    def close(self):
+        if self.handle:
+            _lib.tr_stream_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
