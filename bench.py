@@ -51,7 +51,9 @@ def run_gpu(w, X_dev, dtype, steps, warmup):
     import torch
     import paper_2307_00719_amd as P
 
-    stream = torch.cuda.current_stream()
+    # a dedicated (non-null, default-priority) stream shared by torch's events
+    # and the library, so the events bracket exactly the library's work
+    stream = torch.cuda.Stream()
     Xd = X_dev if dtype == "f64" else X_dev.float()
     nb = w.n_batches
     cap = w.t_init + (warmup + steps) * w.t_new

@@ -113,6 +113,11 @@ tr_status tr_stream_get_cores(tr_stream *s, double *const *cores_out);
  * (R_nR_{n+1} square), both row-major, column index r + R_n*s.           */
 tr_status tr_stream_get_PQ(tr_stream *s, int32_t n, double *P, double *Q);
 
+/* Test hook (randomized variants): host copy of the current sample indices,
+ * N x m int32 row-major (row q = the m indices into core q, the temporal
+ * row indexing the newest batch), as drawn by the counter-based generator. */
+tr_status tr_stream_get_samples(tr_stream *s, int32_t *idxs);
+
 /* Blocks until the handle's stream has finished all submitted work and
  * reports any device-side failure.                                        */
 tr_status tr_stream_sync(tr_stream *s);

@@ -69,6 +69,7 @@ def load():
         "tr_stream_get_cores": ([P, POINTER(c_void_p)], c_int32),
         "tr_stream_get_PQ": ([P, c_int32, P, P], c_int32),
         "tr_stream_sync": ([P], c_int32),
+        "tr_stream_get_samples": ([P, P], c_int32),
         "tr_stream_num_slices": ([P], c_int64),
         "tr_stream_profile": ([P, c_int32], c_int32),
         "tr_stream_profile_read": ([P, c_int32, POINTER(c_double), POINTER(c_int64)], c_int32),
@@ -219,6 +220,12 @@ def tr_stream_get_PQ(handle, n, In, d):
     Q = np.zeros((d, d))
     _check(lib.tr_stream_get_PQ(handle, n, P.ctypes.data, Q.ctypes.data), handle)
     return P, Q
+
+
+def tr_stream_get_samples(handle, N, m):
+    out = np.zeros((N, m), dtype=np.int32)
+    _check(load().tr_stream_get_samples(handle, out.ctypes.data), handle)
+    return out
 
 
 def tr_stream_sync(handle):

@@ -13,6 +13,8 @@
 #include <hip/hip_bf16.h>
 #include <stdint.h>
 
+#include <algorithm>
+
 #include "tr_internal.h"
 
 namespace trk {
@@ -70,21 +72,30 @@ MttkrpPlan plan_mttkrp(const Geom& g, int xdtype) {
   p.MT = MT;
   p.mtiles = (int)((g.In + MT - 1) / MT);
   p.psize = (xdtype == F64) ? 8 : 4;
-  const int64_t K = g.L * g.Rr;
-  const int64_t nchunks = (K + KC - 1) / KC;
-  const int64_t xbytes = K * g.In * (xdtype == F64 ? 8 : (xdtype == F32 ? 4 : 2));
+  p.f = g.n == 0 ? 1 : 0;
+  const int64_t If = g.I[p.f];
+  p.nch = (int)((If + KC - 1) / KC);
+  p.Kout = g.L * g.Rr / If;
+  if (g.n == 0) {
+    p.sf = g.I[0];      // X[m + I_0*(i_1 + I_1*o)]
+    p.sm = 1;
+  } else {
+    p.sf = 1;           // X[i_0 + I_0*l_hi + m*L + L*In*rr]
+    p.sm = g.L;
+  }
+  const int64_t units = p.Kout * p.nch;
+  const int64_t xbytes = g.L * g.Rr * g.In * (xdtype == F64 ? 8 : (xdtype == F32 ? 4 : 2));
   int64_t ns = (512 + p.mtiles - 1) / p.mtiles;
-  const int64_t by_bytes = xbytes / ((int64_t)g.In * g.d * p.psize);
+  const int64_t by_bytes = xbytes / (2 * (int64_t)g.In * g.d * p.psize);
   if (ns > by_bytes) ns = by_bytes;
-  if (ns > nchunks) ns = nchunks;
+  if (ns > units) ns = units;
   if (ns < 1) ns = 1;
   if (const char* e = getenv("TRSTREAM_NSPLIT")) {
     int64_t v = atoll(e);
-    if (v > 0) ns = v < nchunks ? v : nchunks;
+    if (v > 0) ns = v < units ? v : units;
   }
-  int64_t per = (nchunks + ns - 1) / ns;
-  p.kchunk = per * KC;
-  p.nsplit = (int)((K + p.kchunk - 1) / p.kchunk);
+  p.upw = (units + ns - 1) / ns;
+  p.nsplit = (int)((units + p.upw - 1) / p.upw);
   return p;
 }
 
@@ -94,7 +105,7 @@ size_t mttkrp_partial_bytes(const Geom& g, const MttkrpPlan& p) {
 
 // ---------------------------------------------------------------------------
 // Subchain row: v = e_s^T S(k), i.e. row s of S(k), of length R_n.
-// idx holds i_q for every q != n of column k.
+// idx holds i_q for every q != n of column k.  (Reconstruction kernel.)
 // ---------------------------------------------------------------------------
 template <typename TC, int RM>
 __device__ inline void subchain_row(const Geom& g, const CoreView& cv, const int* idx, int s,
@@ -147,103 +158,245 @@ __device__ inline int64_t decode_column(const Geom& g, int64_t k, int* idx) {
   return off;
 }
 
+// Outer index o of mode n -> X offset of (i_f = 0, i_n = 0) and the indices
+// of every mode other than n and f.
+__device__ inline int64_t decode_outer(const Geom& g, int64_t o, int* idx) {
+  if (g.n == 0) {
+    int64_t t = o;
+    for (int q = 2; q < g.N; ++q) {
+      idx[q] = (int)(t % g.I[q]);
+      t /= g.I[q];
+    }
+    return g.I[0] * g.I[1] * o;
+  }
+  const int64_t Lh = g.L / g.I[0];
+  const int64_t l_hi = o % Lh, rr = o / Lh;
+  int64_t t = l_hi;
+  for (int q = 1; q < g.n; ++q) {
+    idx[q] = (int)(t % g.I[q]);
+    t /= g.I[q];
+  }
+  t = rr;
+  for (int q = g.n + 1; q < g.N; ++q) {
+    idx[q] = (int)(t % g.I[q]);
+    t /= g.I[q];
+  }
+  return g.I[0] * l_hi + g.L * g.In * rr;
+}
+
+// Row `row` of the product G_{q0}(i_{q0}) G_{q0+1}(..) ... over nfac slices
+// in ring order, written to out[0..RM).
+template <typename TC, int RM>
+__device__ inline void chain_row(const Geom& g, const CoreView& cv, const int* idx, int q0,
+                                 int nfac, int row, TC* out) {
+  const int N = g.N;
+  int q = q0;
+  TC v[RM];
+  {
+    const TC* G = (const TC*)cv.ptr[q] + idx[q] * cv.si[q] + row * cv.sr[q];
+    const int Rq1 = g.R[q + 1 == N ? 0 : q + 1];
+#pragma unroll
+    for (int b = 0; b < RM; ++b) v[b] = (b < Rq1) ? G[b * cv.ss[q]] : TC(0);
+  }
+  for (int j = 1; j < nfac; ++j) {
+    q = q + 1 == N ? 0 : q + 1;
+    const TC* H = (const TC*)cv.ptr[q] + idx[q] * cv.si[q];
+    const int Rq = g.R[q], Rq1 = g.R[q + 1 == N ? 0 : q + 1];
+    TC u[RM];
+#pragma unroll
+    for (int b = 0; b < RM; ++b) {
+      TC acc = TC(0);
+      if (b < Rq1) {
+#pragma unroll
+        for (int a = 0; a < RM; ++a)
+          if (a < Rq) acc += v[a] * H[a * cv.sr[q] + b * cv.ss[q]];
+      }
+      u[b] = acc;
+    }
+#pragma unroll
+    for (int b = 0; b < RM; ++b) v[b] = u[b];
+  }
+#pragma unroll
+  for (int b = 0; b < RM; ++b) out[b] = v[b];
+}
+
 // ---------------------------------------------------------------------------
-// MTTKRP: part[split][m][c] = sum over this split's columns k of
-//   X_[n][m, k] * G^{!=n}_[2][k, c]
-// One workgroup (4 waves) owns an MT x d tile and a contiguous K range.
-// Per chunk of KC columns: decode, build the KC subchain rows into LDS (B),
-// stage the MT x KC block of X (A), then 16x16x4 MFMAs; each wave owns the
-// 16x16 output blocks b = wave, wave+4, ...
+// MTTKRP: part[split][m][c] = sum over the split's columns k of
+//   X_[n][m, k] * G^{!=n}_[2][k, c].
+// Column k = (o, i_f) has subchain S = U(o) G_f(i_f) V(o): U is the ring
+// product of the slices from mode n+1 up to f-1, V from f+1 up to n-1; both
+// are fixed within a unit.  Per unit (KC consecutive i_f of one o): stage
+// the KC slices of G_f and the MT x KC block of X in LDS, build the KC
+// subchain rows (B) in LDS with one or two small products per row, then
+// 16x16x4 MFMAs; wave w owns the output blocks w, w+4, ...
 // ---------------------------------------------------------------------------
 template <typename T, typename TC, int RM, int MAXB>
-__global__ __launch_bounds__(256) void k_mttkrp(Geom g, int MT, int64_t kchunk,
-                                                const T* __restrict__ X, CoreView cv,
+__global__ __launch_bounds__(256) void k_mttkrp(Geom g, MttkrpPlan p, const T* __restrict__ X,
+                                                CoreView cv,
                                                 typename Acc<T>::type* __restrict__ part) {
-  typedef typename Acc<T>::type A;
-  typedef typename Acc<T>::vec V;
+  typedef typename Acc<T>::vec V4;
   constexpr int KCP = KC + 1;
+  constexpr int RR = RM * RM;
   const int tid = threadIdx.x;
+  const int N = g.N, n = g.n, f = p.f;
   const int d = g.d;
   const int NB = (d + 15) >> 4;
   const int NTP = NB * 16;
+  const int MT = p.MT, MTP = p.MT + 1;
+  const int Rn = g.R[n], Rn1 = g.R[n + 1 == N ? 0 : n + 1];
+  const int Rf = g.R[f], Rf1 = g.R[f + 1 == N ? 0 : f + 1];
+  const int64_t If = g.I[f];
+  // U factors: ring positions n+1 .. f-1; V factors: f+1 .. n-1
+  const int nU = (f - (n + 1) + N) % N;
+  const int nV = (n - (f + 1) + N) % N;
+  const int qU = n + 1 == N ? 0 : n + 1;
+  const int qV = f + 1 == N ? 0 : f + 1;
+
   extern __shared__ __align__(16) char smem[];
-  int64_t* xoff = (int64_t*)smem;                       // [KC]
-  int* idx = (int*)(xoff + KC);                          // [KC][MAXN]
-  T* Bs = (T*)(idx + KC * MAXN);                         // [KC][NTP]
-  T* As = Bs + KC * NTP;                                 // [MT][KCP]
+  TC* Us = (TC*)smem;                                  // [RM][RM], zero padded
+  TC* Vs = Us + RR;                                    // [RM][RM], zero padded
+  TC* Gs = Vs + RR;                                    // [KC][RM][RM], zero padded
+  T* Bs = (T*)(Gs + KC * RR);                          // [KC][NTP]
+  T* As = Bs + KC * NTP;                               // [MT][KCP] or [KC][MTP]
+  __shared__ int oidx[MAXN];
+  __shared__ int64_t xb_sh;
 
   const int split = blockIdx.x;
   const int64_t m0 = (int64_t)blockIdx.y * MT;
-  const int64_t K = g.L * g.Rr;
-  const int64_t kbeg = (int64_t)split * kchunk;
-  const int64_t kend = kbeg + kchunk < K ? kbeg + kchunk : K;
-  const int wave = tid >> 6, lane = tid & 63;
+  const int64_t units = p.Kout * p.nch;
+  const int64_t u0 = (int64_t)split * p.upw;
+  const int64_t u1 = u0 + p.upw < units ? u0 + p.upw : units;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int lane = tid & 63;
   const int nblk = (MT >> 4) * NB;
-  const int Rn = g.R[g.n];
-  const int Rn1 = g.R[g.n + 1 == g.N ? 0 : g.n + 1];
-
-  V acc[MAXB];
+  const bool mfast = p.sm == 1;
+  const TC* Gf = (const TC*)cv.ptr[f];
+  const int64_t fsr = cv.sr[f], fsi = cv.si[f], fss = cv.ss[f];
+  const int ar = lane & 15, ak = lane >> 4;
+  // LDS offsets of this lane's A / B fragments for each owned block; blocks
+  // past nblk repeat the last one (computed, never stored)
+  const int sK = mfast ? MTP : 1;
+  int offA[MAXB], offB[MAXB];
 #pragma unroll
-  for (int bi = 0; bi < MAXB; ++bi) acc[bi] = V{0, 0, 0, 0};
+  for (int bi = 0; bi < MAXB; ++bi) {
+    int b = wave + 4 * bi;
+    b = b < nblk ? b : nblk - 1;
+    const int rb = b / NB, cb = b - rb * NB;
+    offA[bi] = mfast ? (rb * 16 + ar) + ak * MTP : (rb * 16 + ar) * KCP + ak;
+    offB[bi] = ak * NTP + cb * 16 + ar;
+  }
 
-  for (int64_t kb = kbeg; kb < kend; kb += KC) {
-    if (tid < KC) {
-      const int64_t k = kb + tid;
-      if (k < kend) {
-        xoff[tid] = decode_column(g, k, idx + tid * MAXN);
-      } else {
-        xoff[tid] = -1;
-      }
-    }
-    __syncthreads();
-    // subchain rows (kk, s) -> Bs[kk][r + Rn*s]
-    for (int w = tid; w < KC * Rn1; w += 256) {
-      const int kk = w / Rn1, s = w - kk * Rn1;
-      if (xoff[kk] >= 0) {
-        TC v[RM];
-        subchain_row<TC, RM>(g, cv, idx + kk * MAXN, s, v);
+  // identity U / V (zero padded) when there is no factor
+  for (int e = tid; e < RR; e += 256) {
+    const int r = e / RM, c = e - r * RM;
+    if (nU == 0) Us[e] = (r == c && r < Rn1) ? TC(1) : TC(0);
+    if (nV == 0) Vs[e] = (r == c && r < Rf1) ? TC(1) : TC(0);
+  }
+
+  V4 acc[MAXB];
 #pragma unroll
-        for (int r = 0; r < RM; ++r)
-          if (r < Rn) Bs[kk * NTP + r + Rn * s] = (T)v[r];
-      } else {
-        for (int r = 0; r < Rn; ++r) Bs[kk * NTP + r + Rn * s] = T(0);
+  for (int bi = 0; bi < MAXB; ++bi) acc[bi] = V4{0, 0, 0, 0};
+
+  int64_t cur_o = -1;
+  for (int64_t u = u0; u < u1; ++u) {
+    const int64_t o = u / p.nch;
+    const int64_t if0 = (u - o * p.nch) * KC;
+    const int kce = (int)(If - if0 < KC ? If - if0 : KC);
+    if (o != cur_o) {
+      if (tid == 0) xb_sh = decode_outer(g, o, oidx);
+      __syncthreads();
+      if (nU > 0 && tid < RM) {
+        TC row[RM];
+        if (tid < Rn1) {
+          chain_row<TC, RM>(g, cv, oidx, qU, nU, tid, row);
+        } else {
+#pragma unroll
+          for (int b = 0; b < RM; ++b) row[b] = TC(0);
+        }
+#pragma unroll
+        for (int b = 0; b < RM; ++b) Us[tid * RM + b] = b < Rf ? row[b] : TC(0);
       }
+      if (nV > 0 && tid >= 64 && tid < 64 + RM) {
+        const int r0 = tid - 64;
+        TC row[RM];
+        if (r0 < Rf1) {
+          chain_row<TC, RM>(g, cv, oidx, qV, nV, r0, row);
+        } else {
+#pragma unroll
+          for (int b = 0; b < RM; ++b) row[b] = TC(0);
+        }
+#pragma unroll
+        for (int b = 0; b < RM; ++b) Vs[r0 * RM + b] = b < Rn ? row[b] : TC(0);
+      }
+      cur_o = o;
     }
-    for (int w = tid; w < KC * (NTP - d); w += 256) {
-      const int kk = w / (NTP - d), c = d + (w - kk * (NTP - d));
-      Bs[kk * NTP + c] = T(0);
+    const int64_t xb = xb_sh;
+    // stage the KC slices of G_f: Gs[kk][a + RM*b], zero padded
+    for (int e = tid; e < KC * RR; e += 256) {
+      const int kk = e / RR, w = e - kk * RR;
+      const int a = w % RM, b = w / RM;
+      TC val = TC(0);
+      if (kk < kce && a < Rf && b < Rf1) val = Gf[a * fsr + (if0 + kk) * fsi + b * fss];
+      Gs[e] = val;
     }
-    // X block -> As[m][kk]
-    if (g.L == 1) {
+    // stage the X block
+    if (mfast) {
       for (int e = tid; e < MT * KC; e += 256) {
         const int m = e % MT, kk = e / MT;
         const int64_t mg = m0 + m;
         T val = T(0);
-        if (mg < g.In && xoff[kk] >= 0) val = X[xoff[kk] + mg];
-        As[m * KCP + kk] = val;
+        if (mg < g.In && kk < kce) val = X[xb + (if0 + kk) * p.sf + mg];
+        As[kk * MTP + m] = val;
       }
     } else {
       for (int e = tid; e < MT * KC; e += 256) {
         const int kk = e % KC, m = e / KC;
         const int64_t mg = m0 + m;
         T val = T(0);
-        if (mg < g.In && xoff[kk] >= 0) val = X[xoff[kk] + g.L * mg];
+        if (mg < g.In && kk < kce) val = X[xb + (if0 + kk) + mg * p.sm];
         As[m * KCP + kk] = val;
       }
     }
     __syncthreads();
-    const int ar = lane & 15, ak = lane >> 4;
-#pragma unroll 2
+    // subchain rows: B[kk][r + Rn*s] = (U[s,:] G_f(i_f) V)[r]
+    for (int w = tid; w < KC * Rn1; w += 256) {
+      const int kk = w / Rn1, s = w - kk * Rn1;
+      T* brow = Bs + kk * NTP;
+      const TC* Gk = Gs + kk * RR;
+      constexpr int UO = RM <= 8 ? RM : 2;
+      TC t[RM];
+#pragma unroll
+      for (int b = 0; b < RM; ++b) t[b] = TC(0);
+#pragma unroll UO
+      for (int a = 0; a < RM; ++a) {
+        const TC ua = Us[s * RM + a];
+#pragma unroll
+        for (int b = 0; b < RM; ++b) t[b] += ua * Gk[a + RM * b];
+      }
+      TC v[RM];
+#pragma unroll
+      for (int r = 0; r < RM; ++r) v[r] = TC(0);
+#pragma unroll UO
+      for (int b = 0; b < RM; ++b) {
+#pragma unroll
+        for (int r = 0; r < RM; ++r) v[r] += t[b] * Vs[b * RM + r];
+      }
+#pragma unroll
+      for (int r = 0; r < RM; ++r)
+        if (r < Rn) brow[r + Rn * s] = (T)v[r];
+    }
+    for (int w = tid; w < KC * (NTP - d); w += 256) {
+      const int kk = w / (NTP - d), c = d + (w - kk * (NTP - d));
+      Bs[kk * NTP + c] = T(0);
+    }
+    __syncthreads();
+#pragma unroll
     for (int k0 = 0; k0 < KC; k0 += 4) {
 #pragma unroll
       for (int bi = 0; bi < MAXB; ++bi) {
-        const int b = wave + 4 * bi;
-        if (b < nblk) {
-          const int rb = b / NB, cb = b - rb * NB;
-          const T a = As[(rb * 16 + ar) * KCP + k0 + ak];
-          const T bv = Bs[(k0 + ak) * NTP + cb * 16 + ar];
-          acc[bi] = mfma16(a, bv, acc[bi]);
-        }
+        const T a = As[offA[bi] + k0 * sK];
+        const T bv = Bs[offB[bi] + k0 * NTP];
+        acc[bi] = mfma16(a, bv, acc[bi]);
       }
     }
     __syncthreads();
@@ -267,8 +420,9 @@ template <typename T, typename TC, int RM, int MAXB>
 static hipError_t launch_mttkrp_t(const Geom& g, const MttkrpPlan& p, const void* X,
                                   const CoreView& cv, void* part, hipStream_t st) {
   const int NTP = ((g.d + 15) / 16) * 16;
-  const size_t lds = KC * sizeof(int64_t) + KC * MAXN * sizeof(int) +
-                     (size_t)KC * NTP * sizeof(T) + (size_t)p.MT * (KC + 1) * sizeof(T);
+  const size_t amax = std::max((size_t)p.MT * (KC + 1), (size_t)KC * (p.MT + 1));
+  const size_t lds = (size_t)(2 * RM * RM + KC * RM * RM) * sizeof(TC) +
+                     (size_t)KC * NTP * sizeof(T) + amax * sizeof(T);
   auto fn = k_mttkrp<T, TC, RM, MAXB>;
   if (lds > 65536) {
     hipError_t e = hipFuncSetAttribute((const void*)fn,
@@ -276,7 +430,7 @@ static hipError_t launch_mttkrp_t(const Geom& g, const MttkrpPlan& p, const void
     if (e != hipSuccess) return e;
   }
   dim3 grid(p.nsplit, p.mtiles);
-  hipLaunchKernelGGL(fn, grid, dim3(256), lds, st, g, p.MT, p.kchunk, (const T*)X, cv,
+  hipLaunchKernelGGL(fn, grid, dim3(256), lds, st, g, p, (const T*)X, cv,
                      (typename Acc<T>::type*)part);
   return hipGetLastError();
 }
@@ -286,6 +440,7 @@ static hipError_t launch_mttkrp_r(const Geom& g, const MttkrpPlan& p, const void
                                   const CoreView& cv, void* part, hipStream_t st) {
   const int nblk = (p.MT / 16) * ((g.d + 15) / 16);
   const int per = (nblk + 3) / 4;
+  if (per <= 2) return launch_mttkrp_t<T, TC, RM, 2>(g, p, X, cv, part, st);
   if (per <= 4) return launch_mttkrp_t<T, TC, RM, 4>(g, p, X, cv, part, st);
   if (per <= 8) return launch_mttkrp_t<T, TC, RM, 8>(g, p, X, cv, part, st);
   return launch_mttkrp_t<T, TC, RM, 16>(g, p, X, cv, part, st);
@@ -296,8 +451,8 @@ static hipError_t launch_mttkrp_c(const Geom& g, const MttkrpPlan& p, const void
                                   const CoreView& cv, void* part, hipStream_t st) {
   int rmax = 1;
   for (int k = 0; k < g.N; ++k) rmax = g.R[k] > rmax ? g.R[k] : rmax;
-  if (rmax <= 4) return launch_mttkrp_r<T, TC, 4>(g, p, X, cv, part, st);
   if (rmax <= 8) return launch_mttkrp_r<T, TC, 8>(g, p, X, cv, part, st);
+  if (rmax <= 12) return launch_mttkrp_r<T, TC, 12>(g, p, X, cv, part, st);
   return launch_mttkrp_r<T, TC, 16>(g, p, X, cv, part, st);
 }
 
@@ -310,53 +465,88 @@ hipError_t launch_mttkrp(const Geom& g, const MttkrpPlan& p, const void* X, int 
 }
 
 // ---------------------------------------------------------------------------
-// Split-K reduction (fixed order), P accumulation and the right-multiply by
-// Q_n^{-1}: G_{n(2)} = P_n Q_n^dagger (Alg. 4).  16 rows per workgroup.
+// Split reduction (fixed order), P accumulation and the right-multiply by
+// Q_n^{-1}: G_{n(2)} = P_n Q_n^dagger (Alg. 4).  RB rows per workgroup; TPO
+// consecutive lanes share one output, each summing every TPO-th split in
+// increasing order, then a fixed shuffle tree combines them.
 // ---------------------------------------------------------------------------
 template <typename PT>
 __global__ __launch_bounds__(256) void k_reduce_solve(const PT* __restrict__ part, int nsplit,
-                                                      int64_t In, int d, double* P,
+                                                      int64_t In, int d, int RB, double* P,
                                                       int accumulate,
                                                       const double* __restrict__ Minv,
                                                       double* __restrict__ out) {
-  __shared__ double prow[16 * 257];
+  extern __shared__ double prow[];                      // [RB][d+1]
   const int tid = threadIdx.x;
-  const int64_t r0 = (int64_t)blockIdx.x * 16;
-  for (int e = tid; e < 16 * d; e += 256) {
-    const int rr = e / d, c = e - rr * d;
-    const int64_t row = r0 + rr;
+  const int64_t r0 = (int64_t)blockIdx.x * RB;
+  const int rows = (int)(In - r0 < RB ? In - r0 : RB);
+  const int nout = rows * d;
+  int TPO = 1;
+  while (TPO < 16 && TPO * 2 * nout <= 256) TPO *= 2;
+  const int OPP = 256 / TPO;
+  const int lane = tid & (TPO - 1);
+  const size_t stride = (size_t)In * d;
+  for (int ob = 0; ob < nout; ob += OPP) {
+    const int o = ob + tid / TPO;
     double sum = 0.0;
-    if (row < In) {
-      for (int sp = 0; sp < nsplit; ++sp) sum += (double)part[((size_t)sp * In + row) * d + c];
-      if (P) {
-        if (accumulate) sum += P[row * d + c];
-        P[row * d + c] = sum;
+    int row = 0, c = 0;
+    if (o < nout) {
+      row = o / d;
+      c = o - row * d;
+      const PT* src = part + (size_t)(r0 + row) * d + c;
+      int sp = lane;
+      for (; sp + 3 * TPO < nsplit; sp += 4 * TPO) {
+        const double x0 = (double)src[(size_t)sp * stride];
+        const double x1 = (double)src[(size_t)(sp + TPO) * stride];
+        const double x2 = (double)src[(size_t)(sp + 2 * TPO) * stride];
+        const double x3 = (double)src[(size_t)(sp + 3 * TPO) * stride];
+        sum += x0;
+        sum += x1;
+        sum += x2;
+        sum += x3;
       }
+      for (; sp < nsplit; sp += TPO) sum += (double)src[(size_t)sp * stride];
     }
-    prow[rr * 257 + c] = sum;
+    for (int off = TPO >> 1; off > 0; off >>= 1) sum += __shfl_down(sum, off, TPO);
+    if (o < nout && lane == 0) {
+      if (P) {
+        const size_t pi = (size_t)(r0 + row) * d + c;
+        if (accumulate) sum += P[pi];
+        P[pi] = sum;
+      }
+      prow[row * (d + 1) + c] = sum;
+    }
   }
   if (!Minv) return;
   __syncthreads();
-  for (int e = tid; e < 16 * d; e += 256) {
-    const int rr = e / d, c2 = e - rr * d;
-    const int64_t row = r0 + rr;
-    if (row >= In) continue;
-    double gsum = 0.0;
-    for (int c = 0; c < d; ++c) gsum += prow[rr * 257 + c] * Minv[c * d + c2];
-    out[row * d + c2] = gsum;
+  for (int e = tid; e < nout; e += 256) {
+    const int row = e / d, c2 = e - row * d;
+    const double* pr = prow + row * (d + 1);
+    double g0 = 0.0, g1 = 0.0;
+    int c = 0;
+    for (; c + 1 < d; c += 2) {
+      g0 += pr[c] * Minv[(size_t)c * d + c2];
+      g1 += pr[c + 1] * Minv[(size_t)(c + 1) * d + c2];
+    }
+    if (c < d) g0 += pr[c] * Minv[(size_t)c * d + c2];
+    out[(size_t)(r0 + row) * d + c2] = g0 + g1;
   }
 }
 
 hipError_t launch_reduce_solve(const void* part, int psize, int nsplit, int64_t In, int d,
                                double* P, int accumulate, const double* Minv, double* out,
                                hipStream_t st) {
-  dim3 grid((unsigned)((In + 15) / 16));
+  int RB = (int)(In / 64);
+  if (RB < 1) RB = 1;
+  if (RB > 16) RB = 16;
+  dim3 grid((unsigned)((In + RB - 1) / RB));
+  const size_t lds = (size_t)RB * (d + 1) * sizeof(double);
   if (psize == 8)
-    hipLaunchKernelGGL(k_reduce_solve<double>, grid, dim3(256), 0, st, (const double*)part,
-                       nsplit, In, d, P, accumulate, Minv, out);
+    hipLaunchKernelGGL(k_reduce_solve<double>, grid, dim3(256), lds, st, (const double*)part,
+                       nsplit, In, d, RB, P, accumulate, Minv, out);
   else
-    hipLaunchKernelGGL(k_reduce_solve<float>, grid, dim3(256), 0, st, (const float*)part,
-                       nsplit, In, d, P, accumulate, Minv, out);
+    hipLaunchKernelGGL(k_reduce_solve<float>, grid, dim3(256), lds, st, (const float*)part,
+                       nsplit, In, d, RB, P, accumulate, Minv, out);
   return hipGetLastError();
 }
 
@@ -369,22 +559,39 @@ hipError_t launch_reduce_solve(const void* part, int psize, int nsplit, int64_t 
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_gram_E(const double* __restrict__ G, int64_t rows,
                                                 int Ra, int Rb, double* __restrict__ E) {
-  const int dr = Ra * Ra, dc = Rb * Rb;
-  const int e = blockIdx.x * 256 + threadIdx.x;
-  if (e >= dr * dc) return;
-  const int rho = e / dc, kap = e - rho * dc;
-  const int a = rho % Ra, a2 = rho / Ra, b = kap % Rb, b2 = kap / Rb;
-  const int o1 = a + Ra * b, o2 = a2 + Ra * b2;
+  // Gram[c1][c2] = sum_i G_(2)[i][c1] G_(2)[i][c2] on one 16x16 tile, rows
+  // staged 64 at a time; c = a + Ra*b, written to the transfer layout.
+  __shared__ double A1[64][17], A2[64][17];
   const int dd = Ra * Rb;
-  double s = 0.0;
-  for (int64_t i = 0; i < rows; ++i) s += G[i * dd + o1] * G[i * dd + o2];
-  E[e] = s;
+  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+  const int c1 = blockIdx.y * 16 + ty, c2 = blockIdx.x * 16 + tx;
+  double s0 = 0.0, s1 = 0.0;
+  for (int64_t i0 = 0; i0 < rows; i0 += 64) {
+    for (int e = threadIdx.x; e < 64 * 16; e += 256) {
+      const int r = e >> 4, c = e & 15;
+      const int64_t i = i0 + r;
+      const int ca = blockIdx.y * 16 + c, cb = blockIdx.x * 16 + c;
+      A1[r][c] = (i < rows && ca < dd) ? G[i * dd + ca] : 0.0;
+      A2[r][c] = (i < rows && cb < dd) ? G[i * dd + cb] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll 8
+    for (int r = 0; r < 64; r += 2) {
+      s0 += A1[r][ty] * A2[r][tx];
+      s1 += A1[r + 1][ty] * A2[r + 1][tx];
+    }
+    __syncthreads();
+  }
+  if (c1 < dd && c2 < dd) {
+    const int a1 = c1 % Ra, b1 = c1 / Ra, a2 = c2 % Ra, b2 = c2 / Ra;
+    E[(size_t)(a1 + Ra * a2) * (Rb * Rb) + (b1 + Rb * b2)] = s0 + s1;
+  }
 }
 
 hipError_t launch_gram_E(const double* G, int64_t rows, int Ra, int Rb, double* E,
                          hipStream_t st) {
-  const int n = Ra * Ra * Rb * Rb;
-  hipLaunchKernelGGL(k_gram_E, dim3((n + 255) / 256), dim3(256), 0, st, G, rows, Ra, Rb, E);
+  const int dd = Ra * Rb, tiles = (dd + 15) / 16;
+  hipLaunchKernelGGL(k_gram_E, dim3(tiles, tiles), dim3(256), 0, st, G, rows, Ra, Rb, E);
   return hipGetLastError();
 }
 
@@ -416,114 +623,154 @@ hipError_t launch_matmul(const double* A, const double* B, double* C, int d1, in
 
 // ---------------------------------------------------------------------------
 // Q-layout assembly and in-place Gauss-Jordan inverse (no pivoting: the
-// normal-equation matrices are symmetric positive definite).  One workgroup
-// of 1024 threads keeps the d x d matrix in registers, SLOTS elements each;
-// pivot row and column are exchanged through LDS, two barriers per pivot.
-// M is Rb^2 x Ra^2 (row-major) and
+// normal-equation matrices are symmetric positive definite).  A TG x TG grid
+// of threads keeps the d x d matrix in registers, thread (ty, tx) owning the
+// B x B block at rows ty*B.., columns tx*B...  Pivot k: the owners publish
+// row k and column k to LDS (alternating buffers: one barrier per pivot);
+// every element takes a -= f_i r_j with f, r zeroed on the pivot row /
+// column, then the pivot row becomes a_kj / p, the pivot column -a_ik / p
+// and the pivot 1 / p.  M is Rb^2 x Ra^2 (row-major) and
 //   Q[r + Ra*s, r' + Ra*s'] = M[s + Rb*s', r + Ra*r']
+// unless m_plain says M is already d x d in the Q layout.
 // ---------------------------------------------------------------------------
-template <int SLOTS>
-__global__ __launch_bounds__(1024) void k_invert_spd(const double* __restrict__ M, int Ra,
-                                                     int Rb, double* Q, int accumulate,
-                                                     int store_Q, double* __restrict__ Qinv,
-                                                     int* status) {
-  __shared__ double rowk[256], colk[256];
+template <int TG, int B>
+__global__ __launch_bounds__(TG* TG) void k_invert_spd(const double* __restrict__ M, int Ra,
+                                                       int Rb, double* Q, int accumulate,
+                                                       int store_Q, double* __restrict__ Qinv,
+                                                       int* status, int m_plain) {
+  __shared__ double rowk[2][TG * B], colk[2][TG * B];
   __shared__ double sh_tol;
   const int tid = threadIdx.x;
+  const int ty = tid / TG, tx = tid - (tid / TG) * TG;
   const int d = Ra * Rb;
-  const int dd = d * d;
-  double a[SLOTS];
+  double a[B][B];
 #pragma unroll
-  for (int s = 0; s < SLOTS; ++s) {
-    const int e = tid + 1024 * s;
-    double v = 0.0;
-    if (e < dd) {
-      const int i = e / d, j = e - i * d;
-      if (M) {
-        const int r = i % Ra, s1 = i / Ra, r2 = j % Ra, s2 = j / Ra;
-        v = M[(size_t)(s1 + Rb * s2) * (Ra * Ra) + (r + Ra * r2)];
+  for (int i = 0; i < B; ++i) {
+#pragma unroll
+    for (int j = 0; j < B; ++j) {
+      const int gi = ty * B + i, gj = tx * B + j;
+      double v = 0.0;
+      if (gi < d && gj < d) {
+        const int e = gi * d + gj;
+        if (M && m_plain) {
+          v = M[e];
+        } else if (M) {
+          const int r = gi % Ra, s1 = gi / Ra, r2 = gj % Ra, s2 = gj / Ra;
+          v = M[(size_t)(s1 + Rb * s2) * (Ra * Ra) + (r + Ra * r2)];
+        }
+        if (Q && accumulate) v += Q[e];
+        if (Q && store_Q) Q[e] = v;
       }
-      if (Q && accumulate) v += Q[e];
-      if (Q && store_Q) Q[e] = v;
+      a[i][j] = v;
     }
-    a[s] = v;
   }
   if (!Qinv) return;
   // tolerance d * eps * max diagonal
+  if (ty == tx) {
 #pragma unroll
-  for (int s = 0; s < SLOTS; ++s) {
-    const int e = tid + 1024 * s;
-    if (e < dd) {
-      const int i = e / d, j = e - i * d;
-      if (i == j) colk[i] = a[s];
-    }
+    for (int i = 0; i < B; ++i)
+      if (ty * B + i < d) colk[1][ty * B + i] = a[i][i];
   }
   __syncthreads();
-  if (tid == 0) {
+  if (tid < 64) {
     double mx = 0.0;
-    for (int i = 0; i < d; ++i) mx = colk[i] > mx ? colk[i] : mx;
-    sh_tol = (double)d * 2.220446049250313e-16 * mx;
+    for (int i = tid; i < d; i += 64) mx = fmax(mx, colk[1][i]);
+    for (int off = 32; off > 0; off >>= 1) mx = fmax(mx, __shfl_down(mx, off, 64));
+    if (tid == 0) sh_tol = (double)d * 2.220446049250313e-16 * mx;
   }
   __syncthreads();
   const double tol = sh_tol;
   bool bad = false;
   for (int k = 0; k < d; ++k) {
+    const int bs = k & 1;
+    const int kb = k / B, kr = k - (k / B) * B;
+    if (ty == kb) {
 #pragma unroll
-    for (int s = 0; s < SLOTS; ++s) {
-      const int e = tid + 1024 * s;
-      if (e < dd) {
-        const int i = e / d, j = e - i * d;
-        if (i == k) rowk[j] = a[s];
-        if (j == k) colk[i] = a[s];
-      }
-    }
-    __syncthreads();
-    const double p = colk[k];
-    if (!(p > tol)) bad = true;
-    const double ip = 1.0 / p;
+      for (int i = 0; i < B; ++i)
+        if (i == kr) {
 #pragma unroll
-    for (int s = 0; s < SLOTS; ++s) {
-      const int e = tid + 1024 * s;
-      if (e < dd) {
-        const int i = e / d, j = e - i * d;
-        if (i == k) {
-          a[s] = (j == k) ? ip : a[s] * ip;
-        } else {
-          const double f = colk[i];
-          a[s] = (j == k) ? -f * ip : a[s] - f * (rowk[j] * ip);
+          for (int j = 0; j < B; ++j) rowk[bs][tx * B + j] = a[i][j];
         }
-      }
+    }
+    if (tx == kb) {
+#pragma unroll
+      for (int j = 0; j < B; ++j)
+        if (j == kr) {
+#pragma unroll
+          for (int i = 0; i < B; ++i) colk[bs][ty * B + i] = a[i][j];
+        }
     }
     __syncthreads();
+    const double pv = colk[bs][k];
+    if (!(pv > tol)) bad = true;
+    const double ip = 1.0 / pv;
+    double fr[B], rr[B];
+#pragma unroll
+    for (int i = 0; i < B; ++i) {
+      const int gi = ty * B + i;
+      fr[i] = gi == k ? 0.0 : colk[bs][gi < d ? gi : 0];
+    }
+#pragma unroll
+    for (int j = 0; j < B; ++j) {
+      const int gj = tx * B + j;
+      rr[j] = gj == k ? 0.0 : rowk[bs][gj < d ? gj : 0] * ip;
+    }
+#pragma unroll
+    for (int i = 0; i < B; ++i) {
+#pragma unroll
+      for (int j = 0; j < B; ++j) a[i][j] -= fr[i] * rr[j];
+    }
+    if (ty == kb) {
+#pragma unroll
+      for (int i = 0; i < B; ++i)
+        if (i == kr) {
+#pragma unroll
+          for (int j = 0; j < B; ++j) a[i][j] = (tx * B + j == k) ? ip : a[i][j] * ip;
+        }
+    }
+    if (tx == kb) {
+#pragma unroll
+      for (int j = 0; j < B; ++j)
+        if (j == kr) {
+#pragma unroll
+          for (int i = 0; i < B; ++i)
+            if (ty * B + i != k) a[i][j] = -colk[bs][ty * B + i < d ? ty * B + i : 0] * ip;
+        }
+    }
   }
 #pragma unroll
-  for (int s = 0; s < SLOTS; ++s) {
-    const int e = tid + 1024 * s;
-    if (e < dd) Qinv[e] = a[s];
+  for (int i = 0; i < B; ++i) {
+#pragma unroll
+    for (int j = 0; j < B; ++j) {
+      const int gi = ty * B + i, gj = tx * B + j;
+      if (gi < d && gj < d) Qinv[gi * d + gj] = a[i][j];
+    }
   }
   if (bad && tid == 0 && status) status[0] = 1;
 }
 
 hipError_t launch_invert_spd(const double* M, int Ra, int Rb, double* Q, int accumulate,
-                             int store_Q, double* Qinv, int* status, hipStream_t st) {
+                             int store_Q, double* Qinv, int* status, hipStream_t st,
+                             int m_plain) {
   const int d = Ra * Rb;
-  const int slots = (d * d + 1023) / 1024;
   if (d > 256) return hipErrorInvalidValue;
-#define TRK_INV(S)                                                                      \
-  hipLaunchKernelGGL(k_invert_spd<S>, dim3(1), dim3(1024), 0, st, M, Ra, Rb, Q, accumulate, \
-                     store_Q, Qinv, status)
-  if (slots <= 1)
-    TRK_INV(1);
-  else if (slots <= 4)
-    TRK_INV(4);
-  else if (slots <= 8)
-    TRK_INV(8);
-  else if (slots <= 16)
-    TRK_INV(16);
-  else if (slots <= 32)
-    TRK_INV(32);
-  else
-    TRK_INV(64);
+#define TRK_INV(TG, B)                                                                    \
+  hipLaunchKernelGGL((k_invert_spd<TG, B>), dim3(1), dim3(TG * TG), 0, st, M, Ra, Rb, Q, \
+                     accumulate, store_Q, Qinv, status, m_plain)
+  const int B16 = (d + 15) / 16;
+  switch (B16) {
+    case 1: TRK_INV(16, 1); break;
+    case 2: TRK_INV(16, 2); break;
+    case 3: TRK_INV(16, 3); break;
+    case 4: TRK_INV(16, 4); break;
+    case 5: TRK_INV(16, 5); break;
+    case 6: TRK_INV(16, 6); break;
+    case 7: TRK_INV(16, 7); break;
+    case 8: TRK_INV(16, 8); break;
+    case 9: TRK_INV(16, 9); break;
+    case 10: TRK_INV(16, 10); break;
+    default: TRK_INV(32, 8); break;
+  }
 #undef TRK_INV
   return hipGetLastError();
 }

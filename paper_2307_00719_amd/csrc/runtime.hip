@@ -62,6 +62,18 @@ struct tr_stream {
   bool copy_pending = false;
   std::string err;
   tr_status poisoned = TR_OK;
+  // randomized variant state (rSTR-U / rSTR-L)
+  int64_t step = 0;          // time step counter (0 = initialisation)
+  int* idxs = nullptr;       // N x m sample indices
+  double* probs[MAXN] = {};  // leverage distributions (temporal: newest rows)
+  int64_t probs_cap_t = 0;
+  double** dprobs = nullptr; // device copy of probs[]
+  double* cdf = nullptr;
+  int64_t cdf_cap = 0;
+  double* SA = nullptr;      // m x dmax sampled subchain rows
+  double* Sw = nullptr;      // m weights
+  double* Zb = nullptr;      // dmax^2 (or I^2 <= 256^2) scratch Gram
+  double* Zi = nullptr;      // its inverse
   // event profiling (tr_stream_profile)
   bool prof = false;
   std::vector<hipEvent_t> ev_pool;
@@ -277,6 +289,160 @@ tr_status read_status(tr_stream* s) {
   return TR_OK;
 }
 
+int64_t prod_dims_except(const tr_stream* s, int skip) {
+  int64_t J = 1;
+  for (int k = 0; k < s->N - 1; ++k)
+    if (k != skip) J *= s->I[k];
+  return J;
+}
+
+// Leverage distribution (Lemma on leverage estimation) of `rows` slice-major
+// rows of core k into p.
+tr_status leverage_probs(tr_stream* s, int k, const double* rows, int64_t I, double* p) {
+  const int Ra = s->R[k], Rb = s->R[(k + 1) % s->N], d = Ra * Rb;
+  if (I > d) {
+    TR_HIP(launch_wgram(rows, nullptr, I, d, s->Zb, s->st));
+    TR_HIP(launch_invert_spd(s->Zb, Ra, Rb, nullptr, 0, 0, s->Zi, s->dstatus, s->st, 1));
+    TR_HIP(launch_leverage(rows, I, d, s->Zi, p, s->st));
+  } else {
+    if (I > 256) return poison(s, TR_ERR_UNSUPPORTED, "leverage rank check needs I <= 256");
+    TR_HIP(launch_row_gram(rows, I, d, s->Zb, s->st));
+    TR_HIP(launch_invert_spd(s->Zb, (int)I, 1, nullptr, 0, 0, s->Zi, s->dstatus, s->st, 1));
+    TR_HIP(launch_leverage(rows, I, d, nullptr, p, s->st));
+  }
+  return TR_OK;
+}
+
+// idxs(:, k) <- Randsample over [size] (uniform, or from probs[k]).
+tr_status draw_samples(tr_stream* s, int k, int64_t size) {
+  const uint64_t key = rng_key(s->seed, (uint64_t)s->step, (uint64_t)k, 0);
+  int* out = s->idxs + (size_t)k * s->m;
+  if (s->sketch == TR_SKETCH_LEVERAGE) {
+    if (size > s->cdf_cap) {
+      if (s->cdf) TR_HIP(hipFree(s->cdf));
+      TR_HIP(dev_alloc(&s->cdf, (size_t)size));
+      s->cdf_cap = size;
+    }
+    TR_HIP(launch_draw_dist(key, (int)s->m, size, s->probs[k], s->cdf, out, s->st));
+  } else {
+    TR_HIP(launch_draw_uniform(key, (int)s->m, size, out, s->st));
+  }
+  return TR_OK;
+}
+
+tr_status ensure_temporal_probs(tr_stream* s, int64_t t) {
+  if (s->sketch != TR_SKETCH_LEVERAGE || t <= s->probs_cap_t) return TR_OK;
+  const int N = s->N;
+  if (s->probs[N - 1]) {
+    TR_HIP(hipStreamSynchronize(s->st));
+    TR_HIP(hipFree(s->probs[N - 1]));
+  }
+  TR_HIP(dev_alloc(&s->probs[N - 1], (size_t)t));
+  s->probs_cap_t = t;
+  TR_HIP(hipMemcpyAsync(s->dprobs, s->probs, N * sizeof(double*), hipMemcpyHostToDevice, s->st));
+  return TR_OK;
+}
+
+// One sketched P/Q increment of mode n (Alg. 5: P_n += X_S G_S, Q_n += G_S^T G_S
+// with the rescaling of the sketch), X of `t` slices, temporal rows Gt.
+tr_status sketch_increment(tr_stream* s, int n, const void* Xd, int64_t t, const double* Gt,
+                           int accumulate, const double* Minv_solve) {
+  const int N = s->N;
+  std::vector<int64_t> gd(N);
+  for (int k = 0; k < N - 1; ++k) gd[k] = s->I[k];
+  gd[N - 1] = t;
+  Geom g = make_geom(N, gd.data(), s->R, n);
+  const CoreView cv = state_view(s, Gt);
+  const int m = (int)s->m;
+  double wconst = 1.0;
+  if (s->rescale) wconst = (double)prod_dims_except(s, n) * (double)t / (double)m;
+  const bool lev = s->sketch == TR_SKETCH_LEVERAGE && s->rescale;
+  TR_HIP(launch_sample_rows(g, cv, s->idxs, m, lev ? (const double* const*)s->dprobs : nullptr,
+                            wconst, s->SA, s->Sw, s->st));
+  TR_HIP(launch_wgram(s->SA, s->Sw, m, g.d, s->Zb, s->st));
+  TR_HIP(launch_invert_spd(s->Zb, s->R[n], s->R[(n + 1) % N], s->Q[n], accumulate, 1,
+                           Minv_solve ? s->Minv : nullptr, s->dstatus, s->st, 1));
+  SketchPlan sp = plan_sketch(g, m, s->dt);
+  const size_t pb = (size_t)sp.nsplit * g.In * g.d * sp.psize;
+  TR_HIP(ensure(&s->part, &s->part_bytes, pb));
+  TR_HIP(launch_sketch_gemm(g, sp, Xd, s->dt, s->idxs, m, s->SA, s->Sw, s->part, s->st));
+  TR_HIP(launch_reduce_solve(s->part, sp.psize, sp.nsplit, g.In, g.d, s->P[n], accumulate,
+                             Minv_solve ? s->Minv : nullptr, s->G[n], s->st));
+  return TR_OK;
+}
+
+tr_status sketch_init(tr_stream* s, const void* Xd, int64_t t_init) {
+  const int N = s->N;
+  s->step = 0;
+  if (s->sketch == TR_SKETCH_LEVERAGE) {
+    tr_status c = ensure_temporal_probs(s, t_init);
+    if (c != TR_OK) return c;
+    for (int k = 0; k < N; ++k) {
+      const int64_t I = k == N - 1 ? t_init : s->I[k];
+      c = leverage_probs(s, k, s->G[k], I, s->probs[k]);
+      if (c != TR_OK) return c;
+    }
+  }
+  for (int k = 0; k < N; ++k) {
+    tr_status c = draw_samples(s, k, k == N - 1 ? t_init : s->I[k]);
+    if (c != TR_OK) return c;
+  }
+  for (int n = 0; n < N - 1; ++n) {
+    tr_status c = sketch_increment(s, n, Xd, t_init, s->G[N - 1], 0, nullptr);
+    if (c != TR_OK) return c;
+  }
+  return TR_OK;
+}
+
+// One time step of rSTR-U / rSTR-L (Alg. 7 / Alg. 8).
+tr_status sketch_update(tr_stream* s, const void* Xd, int64_t t_new, double* Gnew) {
+  const int N = s->N;
+  s->step += 1;
+  std::vector<int64_t> gd(N);
+  for (int k = 0; k < N - 1; ++k) gd[k] = s->I[k];
+  gd[N - 1] = t_new;
+  const int m = (int)s->m;
+  const int dN = s->d(N - 1);
+  // temporal mode: G_N^new = (X_S D)((D G_S)^T)^+ through the normal equations
+  {
+    Geom g = make_geom(N, gd.data(), s->R, N - 1);
+    const CoreView cv = state_view(s, Gnew);
+    double wconst = 1.0;
+    if (s->rescale) wconst = (double)prod_dims_except(s, -1) / (double)m;
+    const bool lev = s->sketch == TR_SKETCH_LEVERAGE && s->rescale;
+    TR_HIP(launch_sample_rows(g, cv, s->idxs, m, lev ? (const double* const*)s->dprobs : nullptr,
+                              wconst, s->SA, s->Sw, s->st));
+    TR_HIP(launch_wgram(s->SA, s->Sw, m, dN, s->Zb, s->st));
+    TR_HIP(launch_invert_spd(s->Zb, s->R[N - 1], s->R[0], nullptr, 0, 0, s->Minv, s->dstatus,
+                             s->st, 1));
+    SketchPlan sp = plan_sketch(g, m, s->dt);
+    TR_HIP(ensure(&s->part, &s->part_bytes, (size_t)sp.nsplit * g.In * g.d * sp.psize));
+    TR_HIP(launch_sketch_gemm(g, sp, Xd, s->dt, s->idxs, m, s->SA, s->Sw, s->part, s->st));
+    TR_HIP(launch_reduce_solve(s->part, sp.psize, sp.nsplit, g.In, g.d, nullptr, 0, s->Minv, Gnew,
+                               s->st));
+  }
+  tr_status c;
+  if (s->sketch == TR_SKETCH_LEVERAGE) {
+    c = ensure_temporal_probs(s, t_new);
+    if (c != TR_OK) return c;
+    c = leverage_probs(s, N - 1, Gnew, t_new, s->probs[N - 1]);
+    if (c != TR_OK) return c;
+  }
+  c = draw_samples(s, N - 1, t_new);
+  if (c != TR_OK) return c;
+  for (int n = 0; n < N - 1; ++n) {
+    c = sketch_increment(s, n, Xd, t_new, Gnew, 1, s->Minv);
+    if (c != TR_OK) return c;
+    if (s->sketch == TR_SKETCH_LEVERAGE) {
+      c = leverage_probs(s, n, s->G[n], s->I[n], s->probs[n]);
+      if (c != TR_OK) return c;
+    }
+    c = draw_samples(s, n, s->I[n]);
+    if (c != TR_OK) return c;
+  }
+  return TR_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -296,7 +462,15 @@ tr_status tr_stream_init(const tr_config* cfg, const double* X_init, int64_t t_i
   for (int k = 0; k < N; ++k)
     if (cfg->ranks[k] > RMAXC) return TR_ERR_UNSUPPORTED;
   if (cfg->compute_dtype != TR_F64 && cfg->compute_dtype != TR_F32) return TR_ERR_UNSUPPORTED;
-  if (cfg->sketch != TR_SKETCH_NONE) return TR_ERR_UNSUPPORTED;
+  if (cfg->sketch != TR_SKETCH_NONE && cfg->sketch != TR_SKETCH_UNIFORM &&
+      cfg->sketch != TR_SKETCH_LEVERAGE)
+    return TR_ERR_UNSUPPORTED;
+  if (cfg->sketch != TR_SKETCH_NONE) {
+    if (cfg->sketch_size < 1 || cfg->sketch_size > (1 << 24)) return TR_ERR_ARG;
+    for (int k = 0; k < N; ++k)
+      if (cfg->sketch_size < (int64_t)cfg->ranks[k] * cfg->ranks[(k + 1) % N])
+        return TR_ERR_UNSUPPORTED;
+  }
   for (int k = 0; k < N; ++k)
     if (cfg->ranks[k] * cfg->ranks[(k + 1) % N] > 256) return TR_ERR_UNSUPPORTED;
 
@@ -344,6 +518,17 @@ tr_status tr_stream_init(const tr_config* cfg, const double* X_init, int64_t t_i
   TR_HIP(dev_alloc(&s->pair, 2));
   TR_HIP(dev_alloc(&s->dstatus, 4));
   TR_HIP(hipMemsetAsync(s->dstatus, 0, 4 * sizeof(int), s->st));
+  if (s->sketch != TR_SKETCH_NONE) {
+    TR_HIP(dev_alloc(&s->idxs, (size_t)N * s->m));
+    TR_HIP(dev_alloc(&s->SA, (size_t)s->m * dmax));
+    TR_HIP(dev_alloc(&s->Sw, (size_t)s->m));
+    TR_HIP(dev_alloc(&s->Zb, (size_t)256 * 256));
+    TR_HIP(dev_alloc(&s->Zi, (size_t)256 * 256));
+    TR_HIP(dev_alloc(&s->dprobs, (size_t)N));
+    if (s->sketch == TR_SKETCH_LEVERAGE)
+      for (int k = 0; k < N - 1; ++k) TR_HIP(dev_alloc(&s->probs[k], (size_t)s->I[k]));
+    TR_HIP(hipMemcpyAsync(s->dprobs, s->probs, N * sizeof(double*), hipMemcpyHostToDevice, s->st));
+  }
 
   // cores: column-major FP64 (host or device) -> slice-major state
   std::vector<int64_t> dims(N);
@@ -382,6 +567,13 @@ tr_status tr_stream_init(const tr_config* cfg, const double* X_init, int64_t t_i
 
   std::vector<int64_t> gd(dims);
   const CoreView cv = state_view(s, s->G[N - 1]);
+  if (s->sketch != TR_SKETCH_NONE) {
+    c = sketch_init(s, Xd, t_init);
+    if (c != TR_OK) return c;
+    TR_HIP(hipStreamSynchronize(s->st));
+    s->copy_pending = false;
+    return read_status(s);
+  }
   for (int n = 0; n < N - 1; ++n) {
     Geom g = make_geom(N, gd.data(), s->R, n);
     MttkrpPlan p = plan_mttkrp(g, s->dt);
@@ -425,6 +617,14 @@ tr_status tr_stream_update(tr_stream* s, const void* X_new, int32_t x_dtype, int
   double* Gnew = s->G[N - 1] + (size_t)s->t_total * dN;
   hipError_t he;
 
+  if (s->sketch != TR_SKETCH_NONE) {
+    const long pst = prof_begin(s, PK_STEP);
+    c = sketch_update(s, Xd, t_new, Gnew);
+    if (c != TR_OK) return c;
+    prof_end(s, pst);
+    s->t_total += t_new;
+    return TR_OK;
+  }
   const long pstep = prof_begin(s, PK_STEP);
   long pr;
   // temporal mode: G_N^new = X_[N]^new G^{!=N}_[2] (H^{!=N}_<2>)^+ (Alg. 4)
@@ -596,6 +796,16 @@ tr_status tr_stream_profile_read(tr_stream* s, int32_t kind, double* total_ms,
   return TR_OK;
 }
 
+tr_status tr_stream_get_samples(tr_stream* s, int32_t* idxs) {
+  if (!s || !idxs) return TR_ERR_ARG;
+  if (s->poisoned != TR_OK) return s->poisoned;
+  if (s->sketch == TR_SKETCH_NONE) return fail(s, TR_ERR_ARG, "no sketch configured");
+  TR_HIP(hipSetDevice(s->device));
+  TR_HIP(hipStreamSynchronize(s->st));
+  TR_HIP(hipMemcpy(idxs, s->idxs, (size_t)s->N * s->m * sizeof(int32_t), hipMemcpyDeviceToHost));
+  return TR_OK;
+}
+
 int64_t tr_stream_num_slices(const tr_stream* s) { return s ? s->t_total : -1; }
 
 const char* tr_last_error(const tr_stream* s) { return s ? s->err.c_str() : "null handle"; }
@@ -610,8 +820,11 @@ void tr_stream_destroy(tr_stream* s) {
     if (s->P[k]) (void)hipFree(s->P[k]);
     if (s->Q[k]) (void)hipFree(s->Q[k]);
   }
-  void* bufs[] = {s->Minv, s->chain[0], s->chain[1], s->xcast, s->xf64,
-                  s->part, s->wg,       s->pair,     s->dstatus};
+  for (int k = 0; k < MAXN; ++k)
+    if (s->probs[k]) (void)hipFree(s->probs[k]);
+  void* bufs[] = {s->Minv, s->chain[0], s->chain[1], s->xcast, s->xf64, s->part,
+                  s->wg,   s->pair,     s->dstatus,  s->idxs,  s->SA,   s->Sw,
+                  s->Zb,   s->Zi,       s->dprobs,   s->cdf};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
   for (hipEvent_t e : s->ev_pool) (void)hipEventDestroy(e);

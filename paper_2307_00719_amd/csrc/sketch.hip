@@ -1,0 +1,424 @@
+// gfx950 kernels of the randomized variant (rSTR, Alg. 5 with the uniform
+// and leverage-score sketches of Algs. 7 and 8, and the sampled subchain /
+// fibres of Alg. 3).
+//
+// Sample draws use a counter-based generator built on the SplitMix64 output
+// function (Steele, Lea & Flood, OOPSLA 2014):
+//   key(seed, step, core, kind) = mix(seed ^ mix((step<<32)|(core<<16)|kind))
+//   word s = mix(key + s),  u = (word >> 11) * 2^-53,
+//   uniform index = floor(u * I),  index from p = min{i : cdf[i] > u}
+// with cdf summed left to right in FP64 and its last entry set to 1.
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "tr_internal.h"
+
+namespace trk {
+
+__host__ __device__ inline uint64_t mix64(uint64_t x) {
+  uint64_t z = x + 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+uint64_t rng_key(uint64_t seed, uint64_t step, uint64_t core, uint64_t kind) {
+  const uint64_t tag = (step << 32) | (core << 16) | kind;
+  return mix64(seed ^ mix64(tag));
+}
+
+__device__ inline double rng_uniform(uint64_t key, uint64_t s) {
+  return (double)(mix64(key + s) >> 11) * 0x1.0p-53;
+}
+
+// Randsample(I, m) with replacement, uniform (Alg. 7).
+__global__ void k_draw_uniform(uint64_t key, int m, int64_t I, int* __restrict__ idx) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= m) return;
+  const double u = rng_uniform(key, (uint64_t)s);
+  const double x = u * (double)I;
+  idx[s] = (int)floor(x);
+}
+
+hipError_t launch_draw_uniform(uint64_t key, int m, int64_t I, int* idx, hipStream_t st) {
+  hipLaunchKernelGGL(k_draw_uniform, dim3((m + 255) / 256), dim3(256), 0, st, key, m, I, idx);
+  return hipGetLastError();
+}
+
+// Randsample(I, m, true, p) (Alg. 8): thread 0 forms the cdf left to right,
+// then every thread inverts its uniform by binary search.
+__global__ __launch_bounds__(256) void k_draw_dist(uint64_t key, int m, int64_t I,
+                                                   const double* __restrict__ p,
+                                                   double* __restrict__ cdf,
+                                                   int* __restrict__ idx) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    double c = 0.0;
+    for (int64_t i = 0; i < I; ++i) {
+      c += p[i];
+      cdf[i] = c;
+    }
+    cdf[I - 1] = 1.0;
+  }
+  __syncthreads();
+  for (int s = threadIdx.x; s < m; s += blockDim.x) {
+    const double u = rng_uniform(key, (uint64_t)s);
+    int64_t lo = 0, hi = I - 1;
+    while (lo < hi) {
+      const int64_t mid = (lo + hi) >> 1;
+      if (cdf[mid] > u)
+        hi = mid;
+      else
+        lo = mid + 1;
+    }
+    idx[s] = (int)lo;
+  }
+}
+
+hipError_t launch_draw_dist(uint64_t key, int m, int64_t I, const double* p, double* cdf,
+                            int* idx, hipStream_t st) {
+  hipLaunchKernelGGL(k_draw_dist, dim3(1), dim3(256), 0, st, key, m, I, p, cdf, idx);
+  return hipGetLastError();
+}
+
+// Leverage-based distribution of a core (Lemma on leverage estimation,
+// Def. leverage scores): p_i = l_i / sum_j l_j with
+//   l_i = g_i Zinv g_i^T   (I > d: Zinv = (G_(2)^T G_(2))^{-1}),
+//   l_i = 1                (I <= d: G_(2) has full row rank, checked by the
+//                            caller through the row-Gram inverse).
+__global__ __launch_bounds__(256) void k_leverage(const double* __restrict__ G, int64_t I, int d,
+                                                  const double* __restrict__ Zinv,
+                                                  double* __restrict__ p) {
+  __shared__ double red[256];
+  const int tid = threadIdx.x;
+  double part = 0.0;
+  for (int64_t i = tid; i < I; i += 256) {
+    double l = 1.0;
+    if (Zinv) {
+      const double* g = G + i * d;
+      l = 0.0;
+      for (int c = 0; c < d; ++c) {
+        double t = 0.0;
+        for (int c2 = 0; c2 < d; ++c2) t += Zinv[(size_t)c * d + c2] * g[c2];
+        l += g[c] * t;
+      }
+    }
+    p[i] = l;
+    part += l;
+  }
+  red[tid] = part;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (tid < w) red[tid] += red[tid + w];
+    __syncthreads();
+  }
+  const double tot = red[0];
+  for (int64_t i = tid; i < I; i += 256) p[i] = p[i] / tot;
+}
+
+hipError_t launch_leverage(const double* G, int64_t I, int d, const double* Zinv, double* p,
+                           hipStream_t st) {
+  hipLaunchKernelGGL(k_leverage, dim3(1), dim3(256), 0, st, G, I, d, Zinv, p);
+  return hipGetLastError();
+}
+
+// Sampled subchain rows (Alg. 3): for sample s of mode n, row s of
+// G^{!=n}_S[2] is the subchain row at the multi-index (idx_q[s])_{q != n}:
+//   A[s][r + R_n*srow] = (G_{n+1}(.) ... G_{n-1}(.))[srow, r]
+// and its weight w[s] (the diagonal of D_n^2): wconst for the uniform sketch,
+// 1 / (m prod_{q != n} p_q[idx_q[s]]) when `probs` is given.
+template <int RM>
+__global__ __launch_bounds__(256) void k_sample_rows(Geom g, CoreView cv,
+                                                     const int* __restrict__ idxs, int m,
+                                                     const double* const* probs, double wconst,
+                                                     double* __restrict__ A,
+                                                     double* __restrict__ w) {
+  const int Rn = g.R[g.n], Rn1 = g.R[g.n + 1 == g.N ? 0 : g.n + 1];
+  const int d = g.d;
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= m * Rn1) return;
+  const int s = e / Rn1, srow = e - s * Rn1;
+  int idx[MAXN];
+  for (int q = 0; q < g.N; ++q) idx[q] = q == g.n ? 0 : idxs[(size_t)q * m + s];
+  double v[RM];
+  // row srow of G_{n+1}(.) ... G_{n-1}(.)
+  {
+    const int N = g.N;
+    int q = g.n + 1 == N ? 0 : g.n + 1;
+    const double* G0 = (const double*)cv.ptr[q] + idx[q] * cv.si[q] + srow * cv.sr[q];
+    const int Rq1 = g.R[q + 1 == N ? 0 : q + 1];
+#pragma unroll
+    for (int b = 0; b < RM; ++b) v[b] = (b < Rq1) ? G0[b * cv.ss[q]] : 0.0;
+    for (int j = 1; j < N - 1; ++j) {
+      q = q + 1 == N ? 0 : q + 1;
+      const double* H = (const double*)cv.ptr[q] + idx[q] * cv.si[q];
+      const int Rq = g.R[q], Rq2 = g.R[q + 1 == N ? 0 : q + 1];
+      double u[RM];
+#pragma unroll
+      for (int b = 0; b < RM; ++b) {
+        double acc = 0.0;
+        if (b < Rq2) {
+#pragma unroll
+          for (int a = 0; a < RM; ++a)
+            if (a < Rq) acc += v[a] * H[a * cv.sr[q] + b * cv.ss[q]];
+        }
+        u[b] = acc;
+      }
+#pragma unroll
+      for (int b = 0; b < RM; ++b) v[b] = u[b];
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < RM; ++r)
+    if (r < Rn) A[(size_t)s * d + r + Rn * srow] = v[r];
+  if (srow == 0) {
+    double ws = wconst;
+    if (probs) {
+      double q = 1.0;
+      for (int k = 0; k < g.N; ++k)
+        if (k != g.n) q *= probs[k][idx[k]];
+      ws = 1.0 / ((double)m * q);
+    }
+    w[s] = ws;
+  }
+}
+
+hipError_t launch_sample_rows(const Geom& g, const CoreView& cv, const int* idxs, int m,
+                              const double* const* probs, double wconst, double* A, double* w,
+                              hipStream_t st) {
+  int rmax = 1;
+  for (int k = 0; k < g.N; ++k) rmax = g.R[k] > rmax ? g.R[k] : rmax;
+  const int Rn1 = g.R[g.n + 1 == g.N ? 0 : g.n + 1];
+  const int nthr = m * Rn1;
+  dim3 grid((nthr + 255) / 256);
+  if (rmax <= 8)
+    hipLaunchKernelGGL(k_sample_rows<8>, grid, dim3(256), 0, st, g, cv, idxs, m, probs, wconst,
+                       A, w);
+  else
+    hipLaunchKernelGGL(k_sample_rows<16>, grid, dim3(256), 0, st, g, cv, idxs, m, probs, wconst,
+                       A, w);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Sketched product: part[split][i][c] = sum over the split's samples s of
+//   X_S[i][s] * w[s] * A[s][c],
+// X_S[:, s] the mode-n fibre of X at the sampled indices (Alg. 3, read as m
+// fibres).  Same tiling as the MTTKRP: KC samples per chunk staged in LDS,
+// 16x16x4 MFMAs, each wave owning output blocks wave, wave+4, ...
+// ---------------------------------------------------------------------------
+typedef double d4s __attribute__((ext_vector_type(4)));
+typedef float f4s __attribute__((ext_vector_type(4)));
+
+__device__ inline d4s mfma_s(double a, double b, d4s c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+__device__ inline f4s mfma_s(float a, float b, f4s c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+template <typename T> struct SAcc;
+template <> struct SAcc<double> {
+  typedef double type;
+  typedef d4s vec;
+  static __device__ inline int row(int lane, int v) { return (lane >> 4) + 4 * v; }
+};
+template <> struct SAcc<float> {
+  typedef float type;
+  typedef f4s vec;
+  static __device__ inline int row(int lane, int v) { return 4 * (lane >> 4) + v; }
+};
+
+template <typename T, int MAXB>
+__global__ __launch_bounds__(256) void k_sketch_gemm(Geom g, int MT, int cpw, const T* __restrict__ X,
+                                                     const int* __restrict__ idxs, int m,
+                                                     const double* __restrict__ A,
+                                                     const double* __restrict__ w,
+                                                     typename SAcc<T>::type* __restrict__ part) {
+  typedef typename SAcc<T>::vec V4;
+  constexpr int KCP = KC + 1;
+  extern __shared__ __align__(16) char smem[];
+  const int d = g.d;
+  const int NB = (d + 15) >> 4, NTP = NB * 16;
+  int64_t* off = (int64_t*)smem;                       // [KC]
+  T* Bs = (T*)(off + KC);                              // [KC][NTP]
+  T* As = Bs + KC * NTP;                               // [MT][KCP]
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int split = blockIdx.x;
+  const int64_t m0 = (int64_t)blockIdx.y * MT;
+  const int nblk = (MT >> 4) * NB;
+  const int s_beg = split * cpw * KC;
+  const int s_end = s_beg + cpw * KC < m ? s_beg + cpw * KC : m;
+  // X strides of every mode
+  int64_t stride[MAXN];
+  {
+    int64_t acc = 1;
+    for (int q = 0; q < g.N; ++q) {
+      stride[q] = acc;
+      acc *= g.I[q];
+    }
+  }
+  V4 acc[MAXB];
+#pragma unroll
+  for (int bi = 0; bi < MAXB; ++bi) acc[bi] = V4{0, 0, 0, 0};
+  for (int sb = s_beg; sb < s_end; sb += KC) {
+    if (tid < KC) {
+      const int s = sb + tid;
+      int64_t o = -1;
+      if (s < s_end) {
+        o = 0;
+        for (int q = 0; q < g.N; ++q)
+          if (q != g.n) o += (int64_t)idxs[(size_t)q * m + s] * stride[q];
+      }
+      off[tid] = o;
+    }
+    __syncthreads();
+    for (int e = tid; e < KC * NTP; e += 256) {
+      const int kk = e / NTP, c = e - kk * NTP;
+      const int s = sb + kk;
+      T val = T(0);
+      if (s < s_end && c < d) val = (T)(w[s] * A[(size_t)s * d + c]);
+      Bs[e] = val;
+    }
+    for (int e = tid; e < MT * KC; e += 256) {
+      const int kk = e % KC, mm = e / KC;
+      const int64_t mg = m0 + mm;
+      T val = T(0);
+      if (mg < g.In && off[kk] >= 0) val = X[off[kk] + mg * stride[g.n]];
+      As[mm * KCP + kk] = val;
+    }
+    __syncthreads();
+    const int ar = lane & 15, ak = lane >> 4;
+    for (int k0 = 0; k0 < KC; k0 += 4) {
+#pragma unroll
+      for (int bi = 0; bi < MAXB; ++bi) {
+        const int b = wave + 4 * bi;
+        if (b < nblk) {
+          const int rb = b / NB, cb = b - rb * NB;
+          acc[bi] = mfma_s(As[(rb * 16 + ar) * KCP + k0 + ak], Bs[(k0 + ak) * NTP + cb * 16 + ar],
+                           acc[bi]);
+        }
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int bi = 0; bi < MAXB; ++bi) {
+    const int b = wave + 4 * bi;
+    if (b < nblk) {
+      const int rb = b / NB, cb = b - rb * NB;
+      const int col = cb * 16 + (lane & 15);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int64_t mg = m0 + rb * 16 + SAcc<T>::row(lane, v);
+        if (mg < g.In && col < d) part[((size_t)split * g.In + mg) * d + col] = acc[bi][v];
+      }
+    }
+  }
+}
+
+SketchPlan plan_sketch(const Geom& g, int m, int xdtype) {
+  SketchPlan p;
+  const int NB = (g.d + 15) / 16;
+  int MT = (int)((g.In + 15) / 16) * 16;
+  if (MT > 64) MT = 64;
+  while (MT > 16 && (MT / 16) * NB > 64) MT -= 16;
+  p.MT = MT;
+  p.mtiles = (int)((g.In + MT - 1) / MT);
+  const int chunks = (m + KC - 1) / KC;
+  p.cpw = 1;
+  p.nsplit = chunks;
+  p.psize = xdtype == F64 ? 8 : 4;
+  return p;
+}
+
+template <typename T, int MAXB>
+static hipError_t launch_sketch_t(const Geom& g, const SketchPlan& p, const void* X,
+                                  const int* idxs, int m, const double* A, const double* w,
+                                  void* part, hipStream_t st) {
+  const int NTP = ((g.d + 15) / 16) * 16;
+  const size_t lds = KC * sizeof(int64_t) + (size_t)KC * NTP * sizeof(T) +
+                     (size_t)p.MT * (KC + 1) * sizeof(T);
+  auto fn = k_sketch_gemm<T, MAXB>;
+  if (lds > 65536) {
+    hipError_t e = hipFuncSetAttribute((const void*)fn,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(fn, dim3(p.nsplit, p.mtiles), dim3(256), lds, st, g, p.MT, p.cpw,
+                     (const T*)X, idxs, m, A, w, (typename SAcc<T>::type*)part);
+  return hipGetLastError();
+}
+
+hipError_t launch_sketch_gemm(const Geom& g, const SketchPlan& p, const void* X, int xdt,
+                              const int* idxs, int m, const double* A, const double* w,
+                              void* part, hipStream_t st) {
+  const int nblk = (p.MT / 16) * ((g.d + 15) / 16);
+  const int per = (nblk + 3) / 4;
+  if (xdt == F64) {
+    if (per <= 4) return launch_sketch_t<double, 4>(g, p, X, idxs, m, A, w, part, st);
+    if (per <= 8) return launch_sketch_t<double, 8>(g, p, X, idxs, m, A, w, part, st);
+    return launch_sketch_t<double, 16>(g, p, X, idxs, m, A, w, part, st);
+  }
+  if (xdt == F32) {
+    if (per <= 4) return launch_sketch_t<float, 4>(g, p, X, idxs, m, A, w, part, st);
+    if (per <= 8) return launch_sketch_t<float, 8>(g, p, X, idxs, m, A, w, part, st);
+    return launch_sketch_t<float, 16>(g, p, X, idxs, m, A, w, part, st);
+  }
+  return hipErrorInvalidValue;
+}
+
+// out[c1*d + c2] = sum_s w[s] A[s][c1] A[s][c2] (w == nullptr: weights 1),
+// 16x16 output tile per workgroup, rows staged 64 at a time.
+__global__ __launch_bounds__(256) void k_wgram(const double* __restrict__ A,
+                                               const double* __restrict__ w, int64_t rows, int d,
+                                               double* __restrict__ out) {
+  __shared__ double A1[64][17], A2[64][17];
+  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+  const int c1 = blockIdx.y * 16 + ty, c2 = blockIdx.x * 16 + tx;
+  double s0 = 0.0, s1 = 0.0;
+  for (int64_t i0 = 0; i0 < rows; i0 += 64) {
+    for (int e = threadIdx.x; e < 64 * 16; e += 256) {
+      const int r = e >> 4, c = e & 15;
+      const int64_t i = i0 + r;
+      const int ca = blockIdx.y * 16 + c, cb = blockIdx.x * 16 + c;
+      const double wi = (i < rows && w) ? w[i] : 1.0;
+      A1[r][c] = (i < rows && ca < d) ? wi * A[i * d + ca] : 0.0;
+      A2[r][c] = (i < rows && cb < d) ? A[i * d + cb] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll 8
+    for (int r = 0; r < 64; r += 2) {
+      s0 += A1[r][ty] * A2[r][tx];
+      s1 += A1[r + 1][ty] * A2[r + 1][tx];
+    }
+    __syncthreads();
+  }
+  if (c1 < d && c2 < d) out[(size_t)c1 * d + c2] = s0 + s1;
+}
+
+hipError_t launch_wgram(const double* A, const double* w, int64_t rows, int d, double* out,
+                        hipStream_t st) {
+  const int tiles = (d + 15) / 16;
+  hipLaunchKernelGGL(k_wgram, dim3(tiles, tiles), dim3(256), 0, st, A, w, rows, d, out);
+  return hipGetLastError();
+}
+
+// Row Gram K = G_(2) G_(2)^T (I x I) of slice-major rows, for the rank check
+// of the leverage distribution when I <= d.
+__global__ __launch_bounds__(256) void k_row_gram(const double* __restrict__ G, int64_t I, int d,
+                                                  double* __restrict__ K) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= I * I) return;
+  const int64_t i = e / I, j = e - i * I;
+  double s = 0.0;
+  for (int c = 0; c < d; ++c) s += G[i * d + c] * G[j * d + c];
+  K[e] = s;
+}
+
+hipError_t launch_row_gram(const double* G, int64_t I, int d, double* K, hipStream_t st) {
+  hipLaunchKernelGGL(k_row_gram, dim3((unsigned)((I * I + 255) / 256)), dim3(256), 0, st, G, I, d,
+                     K);
+  return hipGetLastError();
+}
+
+}  // namespace trk

@@ -33,12 +33,21 @@ Geom make_geom(int N, const int64_t* I, const int* R, int n);
 
 enum DType { F64 = 0, F32 = 1, BF16 = 2 };
 
+// Work decomposition of one mode-n product.  The columns of X_[n] are
+// enumerated as (outer o, fast index i_f): f is the fastest-varying mode
+// other than n (f = 0 for n >= 1, f = 1 for n = 0), and o runs over all
+// remaining indices.  A unit is one chunk of KC consecutive i_f of one o;
+// workgroup (split, mtile) owns units [split*upw, (split+1)*upw).
 struct MttkrpPlan {
-  int MT;        // rows per tile (multiple of 16)
-  int mtiles;    // ceil(In / MT)
-  int nsplit;    // K splits
-  int64_t kchunk;  // columns per split (multiple of KC)
-  int psize;     // bytes per partial element (8 f64 path, 4 f32/bf16 path)
+  int MT;          // rows per tile (multiple of 16)
+  int mtiles;      // ceil(In / MT)
+  int nsplit;      // number of unit ranges
+  int psize;       // bytes per partial element (8 f64 path, 4 f32 path)
+  int f;           // fast mode
+  int nch;         // chunks per outer index, ceil(I_f / KC)
+  int64_t Kout;    // number of outer indices
+  int64_t upw;     // units per workgroup
+  int64_t sf, sm;  // X strides of i_f and of the row index i_n
 };
 
 MttkrpPlan plan_mttkrp(const Geom& g, int xdtype);
@@ -71,8 +80,10 @@ hipError_t launch_matmul(const double* A, const double* B, double* C, int d1, in
 // columns (r + Ra*r')), optionally added to / stored in Q, then optionally
 // inverted in place by Gauss-Jordan into Qinv.  status[0] is set to 1 on a
 // non-positive or tiny pivot.
+// With m_plain = 1, M is already a d x d matrix in the Q layout.
 hipError_t launch_invert_spd(const double* M, int Ra, int Rb, double* Q, int accumulate,
-                             int store_Q, double* Qinv, int* status, hipStream_t st);
+                             int store_Q, double* Qinv, int* status, hipStream_t st,
+                             int m_plain = 0);
 
 // Elementwise dtype conversion of n elements (round to nearest even).
 hipError_t launch_cast(const void* src, int sdt, void* dst, int ddt, int64_t n, hipStream_t st);
@@ -102,5 +113,43 @@ hipError_t launch_grad_combine(const void* Gsrc, int cdt, int64_t sr, int64_t si
 // Copy a strided core into slice-major FP64 rows and back.
 hipError_t launch_core_to_slices(const void* src, int cdt, int64_t sr, int64_t si, int64_t ss,
                                  int64_t I, int Ra, int Rb, double* dst, hipStream_t st);
+
+// ---- randomized variant (sketch.hip) --------------------------------------
+
+uint64_t rng_key(uint64_t seed, uint64_t step, uint64_t core, uint64_t kind);
+
+// m uniform draws over [I] / from the distribution p (cdf: I doubles of
+// scratch) into idx.
+hipError_t launch_draw_uniform(uint64_t key, int m, int64_t I, int* idx, hipStream_t st);
+hipError_t launch_draw_dist(uint64_t key, int m, int64_t I, const double* p, double* cdf,
+                            int* idx, hipStream_t st);
+
+// Leverage distribution of I slice-major rows of width d; Zinv = inverse
+// column Gram (I > d) or nullptr (every score 1, I <= d).
+hipError_t launch_leverage(const double* G, int64_t I, int d, const double* Zinv, double* p,
+                           hipStream_t st);
+
+// Sampled subchain rows A (m x d) of mode g.n and their weights w; idxs is
+// N x m (row q = samples of core q); probs (device array of N device
+// pointers) selects leverage weights, else every weight is wconst.
+hipError_t launch_sample_rows(const Geom& g, const CoreView& cv, const int* idxs, int m,
+                              const double* const* probs, double wconst, double* A, double* w,
+                              hipStream_t st);
+
+struct SketchPlan {
+  int MT, mtiles, nsplit, cpw, psize;
+};
+SketchPlan plan_sketch(const Geom& g, int m, int xdtype);
+
+// part[split][i][c] = sum_s X_S[i][s] w[s] A[s][c] over the split's samples.
+hipError_t launch_sketch_gemm(const Geom& g, const SketchPlan& p, const void* X, int xdt,
+                              const int* idxs, int m, const double* A, const double* w,
+                              void* part, hipStream_t st);
+
+// out = A^T diag(w) A (d x d, plain layout); w may be nullptr.
+hipError_t launch_wgram(const double* A, const double* w, int64_t rows, int d, double* out,
+                        hipStream_t st);
+// K = G G^T for I slice-major rows of width d.
+hipError_t launch_row_gram(const double* G, int64_t I, int d, double* K, hipStream_t st);
 
 }  // namespace trk

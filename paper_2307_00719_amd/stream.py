@@ -24,6 +24,7 @@ class TRStream:
             sketch_size=sketch_size, rescale=rescale, temporal_literal=temporal_literal,
             seed=seed, max_slices=max_slices, check_finite=check_finite, device=device,
             hip_stream=hip_stream)
+        self.sketch_size = int(sketch_size)
         self._keep = None
 
     def d(self, n):
@@ -31,6 +32,9 @@ class TRStream:
 
     def update(self, X_new):
         self._keep = _lib.tr_stream_update(self.handle, X_new)
+
+    def samples(self):
+        return _lib.tr_stream_get_samples(self.handle, self.N, self.sketch_size)
 
     def sync(self):
         _lib.tr_stream_sync(self.handle)
