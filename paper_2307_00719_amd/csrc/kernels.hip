@@ -297,14 +297,73 @@ __global__ __launch_bounds__(256) void k_mttkrp(Geom g, MttkrpPlan p, const T* _
 #pragma unroll
   for (int bi = 0; bi < MAXB; ++bi) acc[bi] = V4{0, 0, 0, 0};
 
-  int64_t cur_o = -1;
-  for (int64_t u = u0; u < u1; ++u) {
+  // Register staging: each thread moves NG slice elements and NA X elements
+  // per unit; the next unit's loads are issued before the current unit's
+  // subchain build and MFMAs so their latency overlaps that work.
+  constexpr int NG = (KC * RR + 255) / 256;
+  constexpr int NA = (64 * KC) / 256;
+  TC greg[NG];
+  T areg[NA];
+  auto load_unit = [&](int64_t u, int64_t xbase) {
     const int64_t o = u / p.nch;
     const int64_t if0 = (u - o * p.nch) * KC;
     const int kce = (int)(If - if0 < KC ? If - if0 : KC);
+#pragma unroll
+    for (int q = 0; q < NG; ++q) {
+      const int e = tid + 256 * q;
+      const int kk = e / RR, w = e - kk * RR;
+      const int a = w % RM, b = w / RM;
+      const bool ok = e < KC * RR && kk < kce && a < Rf && b < Rf1;
+      const TC v = Gf[ok ? a * fsr + (if0 + kk) * fsi + b * fss : 0];
+      greg[q] = ok ? v : TC(0);
+    }
+#pragma unroll
+    for (int q = 0; q < NA; ++q) {
+      const int e = tid + 256 * q;
+      int m, kk;
+      if (mfast) {
+        m = e % MT;
+        kk = e / MT;
+      } else {
+        kk = e % KC;
+        m = e / KC;
+      }
+      const int64_t mg = m0 + m;
+      const bool ok = e < MT * KC && mg < g.In && kk < kce;
+      const int64_t off = mfast ? xbase + (if0 + kk) * p.sf + mg : xbase + (if0 + kk) + mg * p.sm;
+      const T v = X[ok ? off : 0];
+      areg[q] = ok ? v : T(0);
+    }
+  };
+  auto store_unit = [&]() {
+#pragma unroll
+    for (int q = 0; q < NG; ++q) {
+      const int e = tid + 256 * q;
+      if (e < KC * RR) Gs[e] = greg[q];
+    }
+#pragma unroll
+    for (int q = 0; q < NA; ++q) {
+      const int e = tid + 256 * q;
+      if (e < MT * KC) {
+        if (mfast)
+          As[(e / MT) * MTP + (e % MT)] = areg[q];
+        else
+          As[(e / KC) * KCP + (e % KC)] = areg[q];
+      }
+    }
+  };
+
+  int64_t cur_o = -1;
+  if (u0 < u1) {
+    const int64_t o0 = u0 / p.nch;
+    if (tid == 0) xb_sh = decode_outer(g, o0, oidx);
+    __syncthreads();
+    load_unit(u0, xb_sh);
+  }
+  for (int64_t u = u0; u < u1; ++u) {
+    const int64_t o = u / p.nch;
     if (o != cur_o) {
-      if (tid == 0) xb_sh = decode_outer(g, o, oidx);
-      __syncthreads();
+      // xb_sh / oidx hold this unit's outer index (decoded before its loads)
       if (nU > 0 && tid < RM) {
         TC row[RM];
         if (tid < Rn1) {
@@ -330,33 +389,20 @@ __global__ __launch_bounds__(256) void k_mttkrp(Geom g, MttkrpPlan p, const T* _
       }
       cur_o = o;
     }
-    const int64_t xb = xb_sh;
-    // stage the KC slices of G_f: Gs[kk][a + RM*b], zero padded
-    for (int e = tid; e < KC * RR; e += 256) {
-      const int kk = e / RR, w = e - kk * RR;
-      const int a = w % RM, b = w / RM;
-      TC val = TC(0);
-      if (kk < kce && a < Rf && b < Rf1) val = Gf[a * fsr + (if0 + kk) * fsi + b * fss];
-      Gs[e] = val;
+    store_unit();
+    // decode the next unit's outer index (if it changes) and prefetch it
+    const int64_t un = u + 1;
+    const bool more = un < u1;
+    const int64_t on = more ? un / p.nch : o;
+    int64_t xbn = xb_sh;
+    if (more && on != o) {
+      __syncthreads();            // everyone has read oidx / Us / Vs inputs
+      if (tid == 0) xb_sh = decode_outer(g, on, oidx);
+      __syncthreads();
+      xbn = xb_sh;
     }
-    // stage the X block
-    if (mfast) {
-      for (int e = tid; e < MT * KC; e += 256) {
-        const int m = e % MT, kk = e / MT;
-        const int64_t mg = m0 + m;
-        T val = T(0);
-        if (mg < g.In && kk < kce) val = X[xb + (if0 + kk) * p.sf + mg];
-        As[kk * MTP + m] = val;
-      }
-    } else {
-      for (int e = tid; e < MT * KC; e += 256) {
-        const int kk = e % KC, m = e / KC;
-        const int64_t mg = m0 + m;
-        T val = T(0);
-        if (mg < g.In && kk < kce) val = X[xb + (if0 + kk) + mg * p.sm];
-        As[m * KCP + kk] = val;
-      }
-    }
+    if (more) load_unit(un, xbn);
+    const int kce = (int)(If - (u - o * p.nch) * KC < KC ? If - (u - o * p.nch) * KC : KC);
     __syncthreads();
     // subchain rows: B[kk][r + Rn*s] = (U[s,:] G_f(i_f) V)[r]
     for (int w = tid; w < KC * Rn1; w += 256) {
@@ -381,9 +427,10 @@ __global__ __launch_bounds__(256) void k_mttkrp(Geom g, MttkrpPlan p, const T* _
 #pragma unroll
         for (int r = 0; r < RM; ++r) v[r] += t[b] * Vs[b * RM + r];
       }
+      const bool live = kk < kce;
 #pragma unroll
       for (int r = 0; r < RM; ++r)
-        if (r < Rn) brow[r + Rn * s] = (T)v[r];
+        if (r < Rn) brow[r + Rn * s] = live ? (T)v[r] : T(0);
     }
     for (int w = tid; w < KC * (NTP - d); w += 256) {
       const int kk = w / (NTP - d), c = d + (w - kk * (NTP - d));
@@ -704,17 +751,22 @@ __global__ __launch_bounds__(TG* TG) void k_invert_spd(const double* __restrict_
     const double pv = colk[bs][k];
     if (!(pv > tol)) bad = true;
     const double ip = 1.0 / pv;
-    double fr[B], rr[B];
+    // unconditional LDS loads (clamped index), then selects
+    double cf[B], fr[B], rr[B];
 #pragma unroll
     for (int i = 0; i < B; ++i) {
       const int gi = ty * B + i;
-      fr[i] = gi == k ? 0.0 : colk[bs][gi < d ? gi : 0];
+      cf[i] = colk[bs][gi < d ? gi : d - 1];
     }
 #pragma unroll
     for (int j = 0; j < B; ++j) {
       const int gj = tx * B + j;
-      rr[j] = gj == k ? 0.0 : rowk[bs][gj < d ? gj : 0] * ip;
+      rr[j] = rowk[bs][gj < d ? gj : d - 1];
     }
+#pragma unroll
+    for (int i = 0; i < B; ++i) fr[i] = (ty * B + i == k) ? 0.0 : cf[i];
+#pragma unroll
+    for (int j = 0; j < B; ++j) rr[j] = (tx * B + j == k) ? 0.0 : rr[j] * ip;
 #pragma unroll
     for (int i = 0; i < B; ++i) {
 #pragma unroll
@@ -733,8 +785,7 @@ __global__ __launch_bounds__(TG* TG) void k_invert_spd(const double* __restrict_
       for (int j = 0; j < B; ++j)
         if (j == kr) {
 #pragma unroll
-          for (int i = 0; i < B; ++i)
-            if (ty * B + i != k) a[i][j] = -colk[bs][ty * B + i < d ? ty * B + i : 0] * ip;
+          for (int i = 0; i < B; ++i) a[i][j] = (ty * B + i != k) ? -cf[i] * ip : a[i][j];
         }
     }
   }
@@ -772,6 +823,205 @@ hipError_t launch_invert_spd(const double* M, int Ra, int Rb, double* Q, int acc
     default: TRK_INV(32, 8); break;
   }
 #undef TRK_INV
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Fused side step of one mode (Alg. 4): Gram refresh of the core updated by
+// the previous mode, Gram-chain product (Prop. subchain Gram), Q assembly
+// and Gauss-Jordan inverse, in one workgroup of 1024 threads (16 waves).
+// The Gram and the chain products use 16x16x4 FP64 MFMAs with operands
+// read through the cache; stages are separated by workgroup barriers.
+// ---------------------------------------------------------------------------
+__device__ inline void side_matmul(const double* __restrict__ A, const double* __restrict__ Bm,
+                                   double* __restrict__ C, int d1, int d2, int d3, int wave,
+                                   int lane) {
+  const int nb1 = (d1 + 15) >> 4, nb3 = (d3 + 15) >> 4;
+  const int ar = lane & 15, ak = lane >> 4;
+  for (int b = wave; b < nb1 * nb3; b += 16) {
+    const int rb = b / nb3, cb = b - rb * nb3;
+    d4 acc = {0, 0, 0, 0};
+    const int arow = rb * 16 + ar, bcol = cb * 16 + ar;
+    for (int k0 = 0; k0 < d2; k0 += 4) {
+      const int k = k0 + ak;
+      const double av = (arow < d1 && k < d2) ? A[(size_t)arow * d2 + k] : 0.0;
+      const double bv = (k < d2 && bcol < d3) ? Bm[(size_t)k * d3 + bcol] : 0.0;
+      acc = mfma16(av, bv, acc);
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int r = rb * 16 + Acc<double>::row(lane, v), c = cb * 16 + (lane & 15);
+      if (r < d1 && c < d3) C[(size_t)r * d3 + c] = acc[v];
+    }
+  }
+}
+
+template <int B>
+__global__ __launch_bounds__(1024) void k_side(SideArgs sa) {
+  constexpr int TG = 32;
+  __shared__ double rowk[2][TG * B], colk[2][TG * B];
+  __shared__ double sh_tol;
+  const int tid = threadIdx.x;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
+  // 1. Gram of the previous core, written in the transfer layout
+  if (sa.Gp) {
+    const int Ra = sa.Rpa, Rb = sa.Rpb, dp = Ra * Rb;
+    const int nb = (dp + 15) >> 4;
+    const int ar = lane & 15, ak = lane >> 4;
+    for (int b = wave; b < nb * nb; b += 16) {
+      const int rb = b / nb, cb = b - rb * nb;
+      const int c1 = rb * 16 + ar, c2 = cb * 16 + ar;
+      d4 acc = {0, 0, 0, 0};
+      for (int64_t k0 = 0; k0 < sa.rows_p; k0 += 4) {
+        const int64_t i = k0 + ak;
+        const double av = (i < sa.rows_p && c1 < dp) ? sa.Gp[i * dp + c1] : 0.0;
+        const double bv = (i < sa.rows_p && c2 < dp) ? sa.Gp[i * dp + c2] : 0.0;
+        acc = mfma16(av, bv, acc);
+      }
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int r = rb * 16 + Acc<double>::row(lane, v), c = cb * 16 + (lane & 15);
+        if (r < dp && c < dp) {
+          const int a1 = r % Ra, b1 = r / Ra, a2 = c % Ra, b2 = c / Ra;
+          sa.Ep[(size_t)(a1 + Ra * a2) * (Rb * Rb) + (b1 + Rb * b2)] = acc[v];
+        }
+      }
+    }
+    __syncthreads();
+  }
+  // 2. ring product of the transfer-layout factors
+  const double* M = sa.fac[0] ? sa.fac[0] : sa.Ep;
+  for (int j = 1; j < sa.nfac; ++j) {
+    const double* F = sa.fac[j] ? sa.fac[j] : sa.Ep;
+    double* out = sa.cbuf[(j - 1) & 1];
+    side_matmul(M, F, out, sa.fr[0], sa.fc[j - 1], sa.fc[j], wave, lane);
+    __syncthreads();
+    M = out;
+  }
+  // 3. Q assembly and Gauss-Jordan inverse (32 x 32 thread grid, B x B blocks)
+  const int Ra = sa.Ra, Rb = sa.Rb, d = Ra * Rb;
+  const int ty = tid / TG, tx = tid - (tid / TG) * TG;
+  double a[B][B];
+#pragma unroll
+  for (int i = 0; i < B; ++i) {
+#pragma unroll
+    for (int j = 0; j < B; ++j) {
+      const int gi = ty * B + i, gj = tx * B + j;
+      double v = 0.0;
+      if (gi < d && gj < d) {
+        const int e = gi * d + gj;
+        const int r = gi % Ra, s1 = gi / Ra, r2 = gj % Ra, s2 = gj / Ra;
+        v = M[(size_t)(s1 + Rb * s2) * (Ra * Ra) + (r + Ra * r2)];
+        if (sa.Q && sa.accumulate) v += sa.Q[e];
+        if (sa.Q && sa.store_Q) sa.Q[e] = v;
+      }
+      a[i][j] = v;
+    }
+  }
+  if (!sa.Qinv) return;
+  if (ty == tx) {
+#pragma unroll
+    for (int i = 0; i < B; ++i)
+      if (ty * B + i < d) colk[1][ty * B + i] = a[i][i];
+  }
+  __syncthreads();
+  if (tid < 64) {
+    double mx = 0.0;
+    for (int i = tid; i < d; i += 64) mx = fmax(mx, colk[1][i]);
+    for (int off = 32; off > 0; off >>= 1) mx = fmax(mx, __shfl_down(mx, off, 64));
+    if (tid == 0) sh_tol = (double)d * 2.220446049250313e-16 * mx;
+  }
+  __syncthreads();
+  const double tol = sh_tol;
+  bool bad = false;
+  for (int k = 0; k < d; ++k) {
+    const int bs = k & 1;
+    const int kb = k / B, kr = k - (k / B) * B;
+    if (ty == kb) {
+#pragma unroll
+      for (int i = 0; i < B; ++i)
+        if (i == kr) {
+#pragma unroll
+          for (int j = 0; j < B; ++j) rowk[bs][tx * B + j] = a[i][j];
+        }
+    }
+    if (tx == kb) {
+#pragma unroll
+      for (int j = 0; j < B; ++j)
+        if (j == kr) {
+#pragma unroll
+          for (int i = 0; i < B; ++i) colk[bs][ty * B + i] = a[i][j];
+        }
+    }
+    __syncthreads();
+    const double pv = colk[bs][k];
+    if (!(pv > tol)) bad = true;
+    const double ip = 1.0 / pv;
+    double cf[B], fr[B], rr[B];
+#pragma unroll
+    for (int i = 0; i < B; ++i) {
+      const int gi = ty * B + i;
+      cf[i] = colk[bs][gi < d ? gi : d - 1];
+    }
+#pragma unroll
+    for (int j = 0; j < B; ++j) {
+      const int gj = tx * B + j;
+      rr[j] = rowk[bs][gj < d ? gj : d - 1];
+    }
+#pragma unroll
+    for (int i = 0; i < B; ++i) fr[i] = (ty * B + i == k) ? 0.0 : cf[i];
+#pragma unroll
+    for (int j = 0; j < B; ++j) rr[j] = (tx * B + j == k) ? 0.0 : rr[j] * ip;
+#pragma unroll
+    for (int i = 0; i < B; ++i) {
+#pragma unroll
+      for (int j = 0; j < B; ++j) a[i][j] -= fr[i] * rr[j];
+    }
+    if (ty == kb) {
+#pragma unroll
+      for (int i = 0; i < B; ++i)
+        if (i == kr) {
+#pragma unroll
+          for (int j = 0; j < B; ++j) a[i][j] = (tx * B + j == k) ? ip : a[i][j] * ip;
+        }
+    }
+    if (tx == kb) {
+#pragma unroll
+      for (int j = 0; j < B; ++j)
+        if (j == kr) {
+#pragma unroll
+          for (int i = 0; i < B; ++i) a[i][j] = (ty * B + i != k) ? -cf[i] * ip : a[i][j];
+        }
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < B; ++i) {
+#pragma unroll
+    for (int j = 0; j < B; ++j) {
+      const int gi = ty * B + i, gj = tx * B + j;
+      if (gi < d && gj < d) sa.Qinv[gi * d + gj] = a[i][j];
+    }
+  }
+  if (bad && tid == 0 && sa.status) sa.status[0] = 1;
+}
+
+hipError_t launch_side(const SideArgs& a, hipStream_t st) {
+  const int d = a.Ra * a.Rb;
+  if (d > 256) return hipErrorInvalidValue;
+  const int B = (d + 31) / 32;
+#define TRK_SIDE(BB) \
+  hipLaunchKernelGGL(k_side<BB>, dim3(1), dim3(1024), 0, st, a)
+  switch (B) {
+    case 1: TRK_SIDE(1); break;
+    case 2: TRK_SIDE(2); break;
+    case 3: TRK_SIDE(3); break;
+    case 4: TRK_SIDE(4); break;
+    case 5: TRK_SIDE(5); break;
+    case 6: TRK_SIDE(6); break;
+    case 7: TRK_SIDE(7); break;
+    default: TRK_SIDE(8); break;
+  }
+#undef TRK_SIDE
   return hipGetLastError();
 }
 

@@ -45,7 +45,11 @@ struct tr_stream {
   double* P[MAXN] = {};
   double* Q[MAXN] = {};
   double* Minv = nullptr;
+  double* MinvM[MAXN] = {};    // per-mode inverses (two-stream STR update)
   double* chain[2] = {};
+  hipStream_t side = nullptr;  // second stream: Gram refresh, chain, inverse
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  hipEvent_t ev_inv[MAXN] = {}, ev_rs[MAXN] = {};
   void* xcast = nullptr;
   size_t xcast_bytes = 0;
   double* xf64 = nullptr;
@@ -158,7 +162,9 @@ CoreView colmajor_view(int N, const int64_t* dims, const int* R, const void* con
 // order (the Gram chain of Alg. 4 / Prop. subchain Gram), with `temporal`
 // standing for the temporal factor.  Returns the device pointer holding
 // the R_{n+1}^2 x R_n^2 product.
-const double* chain_product(tr_stream* s, int n, const double* temporal, hipError_t* err) {
+const double* chain_product(tr_stream* s, int n, const double* temporal, hipError_t* err,
+                            hipStream_t on = nullptr) {
+  if (!on) on = s->st;
   const int N = s->N;
   std::vector<int> order;
   for (int j = 1; j < N; ++j) order.push_back((n + j) % N);
@@ -171,7 +177,7 @@ const double* chain_product(tr_stream* s, int n, const double* temporal, hipErro
   for (size_t j = 1; j < order.size(); ++j) {
     const int q = order[j];
     const int c2 = s->R[(q + 1) % N] * s->R[(q + 1) % N];
-    *err = launch_matmul(cur, fac(q), s->chain[pp], rows, cols, c2, s->st);
+    *err = launch_matmul(cur, fac(q), s->chain[pp], rows, cols, c2, on);
     if (*err != hipSuccess) return nullptr;
     cur = s->chain[pp];
     pp ^= 1;
@@ -261,8 +267,9 @@ tr_status grow_temporal(tr_stream* s, int64_t need) {
 enum { PK_MTT_T = 0, PK_MTT_N = 1, PK_CHAIN = 2, PK_SOLVE = 3, PK_GRAM = 4, PK_STEP = 5 };
 
 // Starts a profiled region of `kind`; returns its record index or -1.
-long prof_begin(tr_stream* s, int kind) {
+long prof_begin(tr_stream* s, int kind, hipStream_t on = nullptr) {
   if (!s->prof) return -1;
+  if (!on) on = s->st;
   while (s->ev_used + 2 > s->ev_pool.size()) {
     hipEvent_t e;
     if (hipEventCreate(&e) != hipSuccess) return -1;
@@ -270,15 +277,15 @@ long prof_begin(tr_stream* s, int kind) {
   }
   const size_t a = s->ev_used;
   s->ev_used += 2;
-  if (hipEventRecord(s->ev_pool[a], s->st) != hipSuccess) return -1;
+  if (hipEventRecord(s->ev_pool[a], on) != hipSuccess) return -1;
   s->rec_kind.push_back(kind);
   s->rec_ev.push_back(a);
   return (long)s->rec_kind.size() - 1;
 }
 
-void prof_end(tr_stream* s, long rec) {
+void prof_end(tr_stream* s, long rec, hipStream_t on = nullptr) {
   if (rec < 0) return;
-  (void)hipEventRecord(s->ev_pool[s->rec_ev[rec] + 1], s->st);
+  (void)hipEventRecord(s->ev_pool[s->rec_ev[rec] + 1], on ? on : s->st);
 }
 
 tr_status read_status(tr_stream* s) {
@@ -511,6 +518,14 @@ tr_status tr_stream_init(const tr_config* cfg, const double* X_init, int64_t t_i
     TR_HIP(dev_alloc(&s->E[k], (size_t)rk * rk * rk1 * rk1));
   }
   TR_HIP(dev_alloc(&s->Minv, (size_t)dmax * dmax));
+  for (int k = 0; k < N; ++k) TR_HIP(dev_alloc(&s->MinvM[k], (size_t)dmax * dmax));
+  TR_HIP(hipStreamCreateWithFlags(&s->side, hipStreamNonBlocking));
+  TR_HIP(hipEventCreateWithFlags(&s->ev_fork, hipEventDisableTiming));
+  TR_HIP(hipEventCreateWithFlags(&s->ev_join, hipEventDisableTiming));
+  for (int k = 0; k < N; ++k) {
+    TR_HIP(hipEventCreateWithFlags(&s->ev_inv[k], hipEventDisableTiming));
+    TR_HIP(hipEventCreateWithFlags(&s->ev_rs[k], hipEventDisableTiming));
+  }
   int emax = 0;
   for (int k = 0; k < N; ++k) emax = std::max(emax, s->R[k] * s->R[k]);
   TR_HIP(dev_alloc(&s->chain[0], (size_t)emax * emax));
@@ -625,16 +640,47 @@ tr_status tr_stream_update(tr_stream* s, const void* X_new, int32_t x_dtype, int
     s->t_total += t_new;
     return TR_OK;
   }
+  // Two streams: main (s->st) runs MTTKRP -> reduce+solve per mode; side
+  // runs one fused kernel per mode (Gram refresh of the core updated just
+  // before, Gram chain, Q update, inverse), which does not depend on the
+  // mode's MTTKRP.  Events order every cross-stream dependency.
+  hipStream_t side = s->side;
   const long pstep = prof_begin(s, PK_STEP);
   long pr;
-  // temporal mode: G_N^new = X_[N]^new G^{!=N}_[2] (H^{!=N}_<2>)^+ (Alg. 4)
+  TR_HIP(hipEventRecord(s->ev_fork, s->st));
+  TR_HIP(hipStreamWaitEvent(side, s->ev_fork, 0));
+  auto side_args = [&](int n, int p, const double* Gp, int64_t rows_p) {
+    SideArgs a;
+    a.Gp = Gp;
+    a.rows_p = rows_p;
+    a.Rpa = s->R[p];
+    a.Rpb = s->R[(p + 1) % N];
+    a.Ep = s->E[p];
+    a.nfac = N - 1;
+    for (int j = 0; j < N - 1; ++j) {
+      const int q = (n + 1 + j) % N;
+      a.fac[j] = s->E[q];
+      a.fr[j] = s->R[q] * s->R[q];
+      a.fc[j] = s->R[(q + 1) % N] * s->R[(q + 1) % N];
+    }
+    a.cbuf[0] = s->chain[0];
+    a.cbuf[1] = s->chain[1];
+    a.Ra = s->R[n];
+    a.Rb = s->R[(n + 1) % N];
+    a.Q = n == N - 1 ? nullptr : s->Q[n];
+    a.accumulate = 1;
+    a.store_Q = 1;
+    a.Qinv = s->MinvM[n];
+    a.status = s->dstatus;
+    return a;
+  };
+  // temporal mode: G_N^new = X_[N]^new G^{!=N}_[2] (H^{!=N}_<2>)^+ (Alg. 4);
+  // its side kernel also refreshes Z_{N-1} of the previous step's last core
   {
-    pr = prof_begin(s, PK_CHAIN);
-    const double* M = chain_product(s, N - 1, s->E[N - 1], &he);
-    TR_HIP(he);
-    TR_HIP(launch_invert_spd(M, s->R[N - 1], s->R[0], nullptr, 0, 0, s->Minv, s->dstatus,
-                             s->st));
-    prof_end(s, pr);
+    pr = prof_begin(s, PK_CHAIN, side);
+    TR_HIP(launch_side(side_args(N - 1, N - 2, s->G[N - 2], s->I[N - 2]), side));
+    prof_end(s, pr, side);
+    TR_HIP(hipEventRecord(s->ev_inv[N - 1], side));
     Geom g = make_geom(N, gd.data(), s->R, N - 1);
     MttkrpPlan p = plan_mttkrp(g, s->dt);
     c = ensure_partials(s, g, p);
@@ -643,22 +689,25 @@ tr_status tr_stream_update(tr_stream* s, const void* X_new, int32_t x_dtype, int
     pr = prof_begin(s, PK_MTT_T);
     TR_HIP(launch_mttkrp(g, p, Xd, s->dt, cv, F64, s->part, s->st));
     prof_end(s, pr);
+    TR_HIP(hipStreamWaitEvent(s->st, s->ev_inv[N - 1], 0));
     pr = prof_begin(s, PK_SOLVE);
-    TR_HIP(launch_reduce_solve(s->part, p.psize, p.nsplit, g.In, g.d, nullptr, 0, s->Minv, Gnew,
-                               s->st));
+    TR_HIP(launch_reduce_solve(s->part, p.psize, p.nsplit, g.In, g.d, nullptr, 0,
+                               s->MinvM[N - 1], Gnew, s->st));
     prof_end(s, pr);
-    pr = prof_begin(s, PK_GRAM);
-    TR_HIP(launch_gram_E(Gnew, t_new, s->R[N - 1], s->R[0], s->E[N - 1], s->st));
-    prof_end(s, pr);
+    TR_HIP(hipEventRecord(s->ev_rs[N - 1], s->st));
   }
-  // non-temporal modes, in order (Alg. 4)
+  // non-temporal modes, in order (Alg. 4); mode n's side kernel refreshes the
+  // Gram of the core updated just before it (Z_N^new for n = 0)
   for (int n = 0; n < N - 1; ++n) {
-    pr = prof_begin(s, PK_CHAIN);
-    const double* M = chain_product(s, n, s->E[N - 1], &he);
-    TR_HIP(he);
-    TR_HIP(launch_invert_spd(M, s->R[n], s->R[(n + 1) % N], s->Q[n], 1, 1, s->Minv, s->dstatus,
-                             s->st));
-    prof_end(s, pr);
+    const int pidx = n == 0 ? N - 1 : n - 1;
+    TR_HIP(hipStreamWaitEvent(side, s->ev_rs[pidx], 0));
+    pr = prof_begin(s, PK_CHAIN, side);
+    if (n == 0)
+      TR_HIP(launch_side(side_args(0, N - 1, Gnew, t_new), side));
+    else
+      TR_HIP(launch_side(side_args(n, n - 1, s->G[n - 1], s->I[n - 1]), side));
+    prof_end(s, pr, side);
+    TR_HIP(hipEventRecord(s->ev_inv[n], side));
     Geom g = make_geom(N, gd.data(), s->R, n);
     MttkrpPlan p = plan_mttkrp(g, s->dt);
     c = ensure_partials(s, g, p);
@@ -667,14 +716,15 @@ tr_status tr_stream_update(tr_stream* s, const void* X_new, int32_t x_dtype, int
     pr = prof_begin(s, PK_MTT_N);
     TR_HIP(launch_mttkrp(g, p, Xd, s->dt, cv, F64, s->part, s->st));
     prof_end(s, pr);
+    TR_HIP(hipStreamWaitEvent(s->st, s->ev_inv[n], 0));
     pr = prof_begin(s, PK_SOLVE);
-    TR_HIP(launch_reduce_solve(s->part, p.psize, p.nsplit, g.In, g.d, s->P[n], 1, s->Minv,
+    TR_HIP(launch_reduce_solve(s->part, p.psize, p.nsplit, g.In, g.d, s->P[n], 1, s->MinvM[n],
                                s->G[n], s->st));
     prof_end(s, pr);
-    pr = prof_begin(s, PK_GRAM);
-    TR_HIP(launch_gram_E(s->G[n], s->I[n], s->R[n], s->R[(n + 1) % N], s->E[n], s->st));
-    prof_end(s, pr);
+    TR_HIP(hipEventRecord(s->ev_rs[n], s->st));
   }
+  TR_HIP(hipEventRecord(s->ev_join, side));
+  TR_HIP(hipStreamWaitEvent(s->st, s->ev_join, 0));
   prof_end(s, pstep);
   s->t_total += t_new;
   return TR_OK;
@@ -828,6 +878,15 @@ void tr_stream_destroy(tr_stream* s) {
   for (void* b : bufs)
     if (b) (void)hipFree(b);
   for (hipEvent_t e : s->ev_pool) (void)hipEventDestroy(e);
+  if (s->side) (void)hipStreamSynchronize(s->side);
+  for (int k = 0; k < MAXN; ++k) {
+    if (s->MinvM[k]) (void)hipFree(s->MinvM[k]);
+    if (s->ev_inv[k]) (void)hipEventDestroy(s->ev_inv[k]);
+    if (s->ev_rs[k]) (void)hipEventDestroy(s->ev_rs[k]);
+  }
+  if (s->ev_fork) (void)hipEventDestroy(s->ev_fork);
+  if (s->ev_join) (void)hipEventDestroy(s->ev_join);
+  if (s->side) (void)hipStreamDestroy(s->side);
   if (s->hpinned) (void)hipHostFree(s->hpinned);
   if (s->copy_done) (void)hipEventDestroy(s->copy_done);
   if (s->own_stream && s->st) (void)hipStreamDestroy(s->st);

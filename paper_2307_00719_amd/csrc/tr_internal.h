@@ -85,6 +85,28 @@ hipError_t launch_invert_spd(const double* M, int Ra, int Rb, double* Q, int acc
                              int store_Q, double* Qinv, int* status, hipStream_t st,
                              int m_plain = 0);
 
+// Fused per-mode side step (one workgroup of 1024 threads): optionally the
+// transfer-layout Gram E_p of `rows_p` slice-major rows Gp (written to Ep),
+// then the ring product of the nfac transfer-layout factors fac[0..nfac)
+// (fac[j] is fr[j] x fc[j]; a null entry stands for Ep), then the Q-layout
+// assembly / accumulation into Q and the Gauss-Jordan inverse into Qinv.
+struct SideArgs {
+  const double* Gp;
+  int64_t rows_p;
+  int Rpa, Rpb;
+  double* Ep;
+  int nfac;
+  const double* fac[MAXN];
+  int fr[MAXN], fc[MAXN];
+  double* cbuf[2];
+  int Ra, Rb;
+  double* Q;
+  int accumulate, store_Q;
+  double* Qinv;
+  int* status;
+};
+hipError_t launch_side(const SideArgs& a, hipStream_t st);
+
 // Elementwise dtype conversion of n elements (round to nearest even).
 hipError_t launch_cast(const void* src, int sdt, void* dst, int ddt, int64_t n, hipStream_t st);
 
