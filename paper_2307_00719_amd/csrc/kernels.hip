@@ -63,46 +63,6 @@ Geom make_geom(int N, const int64_t* I, const int* R, int n) {
 
 static int pad16(int64_t x) { return (int)((x + 15) / 16) * 16; }
 
-MttkrpPlan plan_mttkrp(const Geom& g, int xdtype) {
-  MttkrpPlan p;
-  const int NB = (g.d + 15) / 16;
-  int MT = pad16(g.In);
-  if (MT > 64) MT = 64;
-  while (MT > 16 && (MT / 16) * NB > 64) MT -= 16;
-  p.MT = MT;
-  p.mtiles = (int)((g.In + MT - 1) / MT);
-  p.psize = (xdtype == F64) ? 8 : 4;
-  p.f = g.n == 0 ? 1 : 0;
-  const int64_t If = g.I[p.f];
-  p.nch = (int)((If + KC - 1) / KC);
-  p.Kout = g.L * g.Rr / If;
-  if (g.n == 0) {
-    p.sf = g.I[0];      // X[m + I_0*(i_1 + I_1*o)]
-    p.sm = 1;
-  } else {
-    p.sf = 1;           // X[i_0 + I_0*l_hi + m*L + L*In*rr]
-    p.sm = g.L;
-  }
-  const int64_t units = p.Kout * p.nch;
-  const int64_t xbytes = g.L * g.Rr * g.In * (xdtype == F64 ? 8 : (xdtype == F32 ? 4 : 2));
-  int64_t ns = (512 + p.mtiles - 1) / p.mtiles;
-  const int64_t by_bytes = xbytes / (2 * (int64_t)g.In * g.d * p.psize);
-  if (ns > by_bytes) ns = by_bytes;
-  if (ns > units) ns = units;
-  if (ns < 1) ns = 1;
-  if (const char* e = getenv("TRSTREAM_NSPLIT")) {
-    int64_t v = atoll(e);
-    if (v > 0) ns = v < units ? v : units;
-  }
-  p.upw = (units + ns - 1) / ns;
-  p.nsplit = (int)((units + p.upw - 1) / p.upw);
-  return p;
-}
-
-size_t mttkrp_partial_bytes(const Geom& g, const MttkrpPlan& p) {
-  return (size_t)p.nsplit * (size_t)g.In * (size_t)g.d * (size_t)p.psize;
-}
-
 // ---------------------------------------------------------------------------
 // Subchain row: v = e_s^T S(k), i.e. row s of S(k), of length R_n.
 // idx holds i_q for every q != n of column k.  (Reconstruction kernel.)
@@ -158,319 +118,282 @@ __device__ inline int64_t decode_column(const Geom& g, int64_t k, int* idx) {
   return off;
 }
 
-// Outer index o of mode n -> X offset of (i_f = 0, i_n = 0) and the indices
-// of every mode other than n and f.
-__device__ inline int64_t decode_outer(const Geom& g, int64_t o, int* idx) {
+MttkrpPlan plan_mttkrp(const Geom& g, int xdtype) {
+  MttkrpPlan p;
+  const int N = g.N;
+  p.MT = 16;
+  p.mtiles = (int)((g.In + 15) / 16);
+  p.psize = (xdtype == F64) ? 8 : 4;
+  p.f = g.n == 0 ? 1 : 0;
+  const int f = p.f;
+  const int df = g.R[f] * g.R[(f + 1) % N];
+  p.nbf = (df + 15) / 16;
+  p.KS = p.nbf <= 4 ? 4 : (p.nbf <= 8 ? 2 : 1);
+  const int64_t If = g.I[f];
+  p.Q = (int)((If + 4 * p.KS - 1) / (4 * p.KS));
+  p.Kout = g.L * g.Rr / If;
   if (g.n == 0) {
-    int64_t t = o;
-    for (int q = 2; q < g.N; ++q) {
-      idx[q] = (int)(t % g.I[q]);
-      t /= g.I[q];
-    }
-    return g.I[0] * g.I[1] * o;
+    p.sf = g.I[0];      // X[m + I_0*(i_1 + I_1*o)]
+    p.sm = 1;
+  } else {
+    p.sf = 1;           // X[i_0 + I_0*l_hi + m*L + L*In*rr]
+    p.sm = g.L;
   }
+  // outer indices per workgroup: about 512 workgroups, and the partials
+  // (one I_n x d block per chunk) at most half the bytes of X
+  const int64_t xbytes = g.L * g.Rr * g.In * (xdtype == F64 ? 8 : (xdtype == F32 ? 4 : 2));
+  int64_t chunks = (512 + p.mtiles - 1) / p.mtiles;
+  const int64_t by_bytes = xbytes / (2 * (int64_t)g.In * g.d * p.psize);
+  if (chunks > by_bytes) chunks = by_bytes;
+  if (chunks > p.Kout) chunks = p.Kout;
+  if (chunks < 1) chunks = 1;
+  if (const char* e = getenv("TRSTREAM_NSPLIT")) {
+    int64_t v = atoll(e);
+    if (v > 0) chunks = v < p.Kout ? v : p.Kout;
+  }
+  p.upw = (p.Kout + chunks - 1) / chunks;
+  p.nsplit = (int)((p.Kout + p.upw - 1) / p.upw);
+  return p;
+}
+
+size_t mttkrp_partial_bytes(const Geom& g, const MttkrpPlan& p) {
+  return (size_t)p.nsplit * (size_t)g.In * (size_t)g.d * (size_t)p.psize;
+}
+
+// Index i_q (q != n, f) of outer index o of mode n, in the enumeration of
+// decode_outer.
+__device__ inline int outer_index(const Geom& g, int64_t o, int q) {
+  int64_t t;
+  int q0;
+  if (g.n == 0) {
+    t = o;
+    q0 = 2;
+  } else if (q < g.n) {
+    t = o % (g.L / g.I[0]);
+    q0 = 1;
+  } else {
+    t = o / (g.L / g.I[0]);
+    q0 = g.n + 1;
+  }
+  for (int p = q0; p < q; ++p) t /= g.I[p];
+  return (int)(t % g.I[q]);
+}
+
+// Ring product of nfac slices from mode q0 on, at the indices of outer index
+// o, into the 16 x 16 LDS matrix M (zero padded); tmp is 256 doubles of
+// scratch.  Ends with a workgroup barrier.
+template <typename TC>
+__device__ inline void ring_product_lds(const Geom& g, const CoreView& cv, int64_t o, int q0,
+                                        int nfac, double* M, double* tmp, int tid) {
+  const int N = g.N;
+  int q = q0;
+  {
+    const int a = tid >> 4, b = tid & 15;
+    const int Ra = g.R[q], Rb = g.R[q + 1 == N ? 0 : q + 1];
+    const bool ok = a < Ra && b < Rb;
+    const TC* G = (const TC*)cv.ptr[q] + (int64_t)outer_index(g, o, q) * cv.si[q];
+    const double v = (double)G[ok ? a * cv.sr[q] + b * cv.ss[q] : 0];
+    M[tid] = ok ? v : 0.0;
+  }
+  __syncthreads();
+  for (int j = 1; j < nfac; ++j) {
+    q = q + 1 == N ? 0 : q + 1;
+    const int a = tid >> 4, c = tid & 15;
+    const int Rq = g.R[q], Rc = g.R[q + 1 == N ? 0 : q + 1];
+    const TC* H = (const TC*)cv.ptr[q] + (int64_t)outer_index(g, o, q) * cv.si[q];
+    double acc = 0.0;
+    if (c < Rc)
+      for (int b = 0; b < Rq; ++b) acc += M[a * 16 + b] * (double)H[b * cv.sr[q] + c * cv.ss[q]];
+    tmp[tid] = acc;
+    __syncthreads();
+    M[tid] = tmp[tid];
+    __syncthreads();
+  }
+}
+
+// X offset of (i_f = 0, i_n = 0) for outer index o of mode n.
+__device__ inline int64_t outer_offset(const Geom& g, int64_t o) {
+  if (g.n == 0) return g.I[0] * g.I[1] * o;
   const int64_t Lh = g.L / g.I[0];
   const int64_t l_hi = o % Lh, rr = o / Lh;
-  int64_t t = l_hi;
-  for (int q = 1; q < g.n; ++q) {
-    idx[q] = (int)(t % g.I[q]);
-    t /= g.I[q];
-  }
-  t = rr;
-  for (int q = g.n + 1; q < g.N; ++q) {
-    idx[q] = (int)(t % g.I[q]);
-    t /= g.I[q];
-  }
   return g.I[0] * l_hi + g.L * g.In * rr;
 }
 
-// Row `row` of the product G_{q0}(i_{q0}) G_{q0+1}(..) ... over nfac slices
-// in ring order, written to out[0..RM).
-template <typename TC, int RM>
-__device__ inline void chain_row(const Geom& g, const CoreView& cv, const int* idx, int q0,
-                                 int nfac, int row, TC* out) {
-  const int N = g.N;
-  int q = q0;
-  TC v[RM];
-  {
-    const TC* G = (const TC*)cv.ptr[q] + idx[q] * cv.si[q] + row * cv.sr[q];
-    const int Rq1 = g.R[q + 1 == N ? 0 : q + 1];
-#pragma unroll
-    for (int b = 0; b < RM; ++b) v[b] = (b < Rq1) ? G[b * cv.ss[q]] : TC(0);
-  }
-  for (int j = 1; j < nfac; ++j) {
-    q = q + 1 == N ? 0 : q + 1;
-    const TC* H = (const TC*)cv.ptr[q] + idx[q] * cv.si[q];
-    const int Rq = g.R[q], Rq1 = g.R[q + 1 == N ? 0 : q + 1];
-    TC u[RM];
-#pragma unroll
-    for (int b = 0; b < RM; ++b) {
-      TC acc = TC(0);
-      if (b < Rq1) {
-#pragma unroll
-        for (int a = 0; a < RM; ++a)
-          if (a < Rq) acc += v[a] * H[a * cv.sr[q] + b * cv.ss[q]];
-      }
-      u[b] = acc;
-    }
-#pragma unroll
-    for (int b = 0; b < RM; ++b) v[b] = u[b];
-  }
-#pragma unroll
-  for (int b = 0; b < RM; ++b) out[b] = v[b];
-}
-
 // ---------------------------------------------------------------------------
-// MTTKRP: part[split][m][c] = sum over the split's columns k of
-//   X_[n][m, k] * G^{!=n}_[2][k, c].
-// Column k = (o, i_f) has subchain S = U(o) G_f(i_f) V(o): U is the ring
-// product of the slices from mode n+1 up to f-1, V from f+1 up to n-1; both
-// are fixed within a unit.  Per unit (KC consecutive i_f of one o): stage
-// the KC slices of G_f and the MT x KC block of X in LDS, build the KC
-// subchain rows (B) in LDS with one or two small products per row, then
-// 16x16x4 MFMAs; wave w owns the output blocks w, w+4, ...
+// MTTKRP: part[chunk][m][c] = sum over the chunk's outer indices o and all
+// i_f of X_[n][m, (o, i_f)] * G^{!=n}_[2][(o, i_f), c].
+// The columns of X_[n] are split as (o, i_f), f the fastest mode other than
+// n, and the subchain slice factors as S(o, i_f) = U(o) G_f(i_f) V(o) (U the
+// ring product of the modes n+1 .. f-1, V of f+1 .. n-1), so
+//   P[m, r + R_n s] = sum_o sum_{a,b} U(o)[s,a] Y_o[m, a + R_f b] V(o)[b,r],
+//   Y_o[m, :] = sum_{i_f} X[m, o, i_f] G_f(i_f)          (a GEMM, K = I_f).
+// One workgroup: 16 rows m x one chunk of o.  The GEMM runs on 16x16x4
+// MFMAs with both operands read straight into registers; the 4 waves split
+// K in KS parts and the column tiles of R_f R_{f+1} in 4/KS parts.  Lane
+// group g of K-part w handles the Q consecutive i_f from (4w + g) Q, so a
+// lane's loads walk contiguous memory when i_f is the unit-stride mode.
+// The K parts are summed in LDS in a fixed order, then U and V are applied
+// in FP64 and the result accumulated over the chunk.
 // ---------------------------------------------------------------------------
-template <typename T, typename TC, int RM, int MAXB>
-__global__ __launch_bounds__(256) void k_mttkrp(Geom g, MttkrpPlan p, const T* __restrict__ X,
-                                                CoreView cv,
-                                                typename Acc<T>::type* __restrict__ part) {
+template <typename T, typename TC, int NJ>
+__global__ __launch_bounds__(256, 2) void k_mttkrp(Geom g, MttkrpPlan p, const T* __restrict__ X,
+                                                   CoreView cv,
+                                                   typename Acc<T>::type* __restrict__ part) {
+  typedef typename Acc<T>::type PT;
   typedef typename Acc<T>::vec V4;
-  constexpr int KCP = KC + 1;
-  constexpr int RR = RM * RM;
-  const int tid = threadIdx.x;
+  constexpr int KG = 8;                     // k-steps whose loads are issued together
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int N = g.N, n = g.n, f = p.f;
-  const int d = g.d;
-  const int NB = (d + 15) >> 4;
-  const int NTP = NB * 16;
-  const int MT = p.MT, MTP = p.MT + 1;
   const int Rn = g.R[n], Rn1 = g.R[n + 1 == N ? 0 : n + 1];
   const int Rf = g.R[f], Rf1 = g.R[f + 1 == N ? 0 : f + 1];
-  const int64_t If = g.I[f];
-  // U factors: ring positions n+1 .. f-1; V factors: f+1 .. n-1
+  const int df = Rf * Rf1, nbf = p.nbf, dfp = 16 * nbf, dn = g.d;
+  const int KS = p.KS, CS = 4 / KS;
+  const int kslot = wave % KS, cslot = wave / KS;
+  const int g4 = lane >> 4, l16 = lane & 15;
+  const int If = (int)g.I[f];
+  const int Q = p.Q;
+  const int kbase = (kslot * 4 + g4) * Q;
   const int nU = (f - (n + 1) + N) % N;
   const int nV = (n - (f + 1) + N) % N;
   const int qU = n + 1 == N ? 0 : n + 1;
   const int qV = f + 1 == N ? 0 : f + 1;
+  const int wst = 16 * ((Rn1 * Rf1 + 15) / 16);
 
   extern __shared__ __align__(16) char smem[];
-  TC* Us = (TC*)smem;                                  // [RM][RM], zero padded
-  TC* Vs = Us + RR;                                    // [RM][RM], zero padded
-  TC* Gs = Vs + RR;                                    // [KC][RM][RM], zero padded
-  T* Bs = (T*)(Gs + KC * RR);                          // [KC][NTP]
-  T* As = Bs + KC * NTP;                               // [MT][KCP] or [KC][MTP]
-  __shared__ int oidx[MAXN];
-  __shared__ int64_t xb_sh;
+  double* Us = (double*)smem;               // [16][16]
+  double* Vs = Us + 256;                    // [16][16]
+  double* tmp = Vs + 256;                   // [256]
+  double* Pa = tmp + 256;                   // [16][dn] accumulated result
+  double* Ws = Pa + 16 * dn;                // [16][wst]
+  PT* Ys = (PT*)(Ws + 16 * wst);            // [16][dfp]
+  PT* red = Ys + 16 * dfp;                  // [KS-1][16][dfp]
 
-  const int split = blockIdx.x;
-  const int64_t m0 = (int64_t)blockIdx.y * MT;
-  const int64_t units = p.Kout * p.nch;
-  const int64_t u0 = (int64_t)split * p.upw;
-  const int64_t u1 = u0 + p.upw < units ? u0 + p.upw : units;
-  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int lane = tid & 63;
-  const int nblk = (MT >> 4) * NB;
-  const bool mfast = p.sm == 1;
-  const TC* Gf = (const TC*)cv.ptr[f];
-  const int64_t fsr = cv.sr[f], fsi = cv.si[f], fss = cv.ss[f];
-  const int ar = lane & 15, ak = lane >> 4;
-  // LDS offsets of this lane's A / B fragments for each owned block; blocks
-  // past nblk repeat the last one (computed, never stored)
-  const int sK = mfast ? MTP : 1;
-  int offA[MAXB], offB[MAXB];
+  const int64_t m0 = (int64_t)blockIdx.y * 16;
+  const int64_t o0 = (int64_t)blockIdx.x * p.upw;
+  const int64_t o1 = o0 + p.upw < p.Kout ? o0 + p.upw : p.Kout;
+  const TC* __restrict__ Gf = (const TC*)cv.ptr[f];
+  // 32-bit element offsets: the launcher checks that X spans of one outer
+  // index and the core G_f fit
+  const int fsi = (int)cv.si[f], sf = (int)p.sf;
+  int boff[NJ];
 #pragma unroll
-  for (int bi = 0; bi < MAXB; ++bi) {
-    int b = wave + 4 * bi;
-    b = b < nblk ? b : nblk - 1;
-    const int rb = b / NB, cb = b - rb * NB;
-    offA[bi] = mfast ? (rb * 16 + ar) + ak * MTP : (rb * 16 + ar) * KCP + ak;
-    offB[bi] = ak * NTP + cb * 16 + ar;
+  for (int j = 0; j < NJ; ++j) {
+    int c = (cslot + CS * j) * 16 + l16;
+    c = c < df ? c : df - 1;
+    boff[j] = (int)((c % Rf) * cv.sr[f] + (c / Rf) * cv.ss[f]);
   }
+  const int mrow = (int)(m0 + l16 < g.In ? m0 + l16 : g.In - 1);
+  const bool mok = m0 + l16 < g.In;
+  const int arow = (int)(mrow * p.sm);
+  for (int e = tid; e < 16 * dn; e += 256) Pa[e] = 0.0;
 
-  // identity U / V (zero padded) when there is no factor
-  for (int e = tid; e < RR; e += 256) {
-    const int r = e / RM, c = e - r * RM;
-    if (nU == 0) Us[e] = (r == c && r < Rn1) ? TC(1) : TC(0);
-    if (nV == 0) Vs[e] = (r == c && r < Rf1) ? TC(1) : TC(0);
-  }
-
-  V4 acc[MAXB];
+  for (int64_t o = o0; o < o1; ++o) {
+    const T* __restrict__ Xo = X + outer_offset(g, o);
+    if (nU > 0) ring_product_lds<TC>(g, cv, o, qU, nU, Us, tmp, tid);
+    if (nV > 0) ring_product_lds<TC>(g, cv, o, qV, nV, Vs, tmp, tid);
+    // GEMM part: acc[j] = 16 x 16 tile (rows m, columns cslot + CS j) of
+    // this wave's K part; the loads of KG k-steps are issued before their
+    // MFMAs, and out-of-range k contribute zeros
+    V4 acc[NJ];
 #pragma unroll
-  for (int bi = 0; bi < MAXB; ++bi) acc[bi] = V4{0, 0, 0, 0};
-
-  // Register staging: each thread moves NG slice elements and NA X elements
-  // per unit; the next unit's loads are issued before the current unit's
-  // subchain build and MFMAs so their latency overlaps that work.
-  constexpr int NG = (KC * RR + 255) / 256;
-  constexpr int NA = (64 * KC) / 256;
-  TC greg[NG];
-  T areg[NA];
-  auto load_unit = [&](int64_t u, int64_t xbase) {
-    const int64_t o = u / p.nch;
-    const int64_t if0 = (u - o * p.nch) * KC;
-    const int kce = (int)(If - if0 < KC ? If - if0 : KC);
+    for (int j = 0; j < NJ; ++j) acc[j] = V4{0, 0, 0, 0};
+#pragma unroll 1
+    for (int kc = 0; kc < Q; kc += KG) {
+      T av[KG], bv[KG][NJ];
 #pragma unroll
-    for (int q = 0; q < NG; ++q) {
-      const int e = tid + 256 * q;
-      const int kk = e / RR, w = e - kk * RR;
-      const int a = w % RM, b = w / RM;
-      const bool ok = e < KC * RR && kk < kce && a < Rf && b < Rf1;
-      const TC v = Gf[ok ? a * fsr + (if0 + kk) * fsi + b * fss : 0];
-      greg[q] = ok ? v : TC(0);
-    }
+      for (int q = 0; q < KG; ++q) {
+        const int k = kbase + kc + q;
+        const bool ok = kc + q < Q && k < If;
+        const int kcl = k < If ? k : If - 1;
+        const T x = Xo[arow + kcl * sf];
+        av[q] = ok && mok ? x : T(0);
 #pragma unroll
-    for (int q = 0; q < NA; ++q) {
-      const int e = tid + 256 * q;
-      int m, kk;
-      if (mfast) {
-        m = e % MT;
-        kk = e / MT;
-      } else {
-        kk = e % KC;
-        m = e / KC;
+        for (int j = 0; j < NJ; ++j) {
+          const TC b = Gf[kcl * fsi + boff[j]];
+          bv[q][j] = ok ? (T)b : T(0);
+        }
       }
-      const int64_t mg = m0 + m;
-      const bool ok = e < MT * KC && mg < g.In && kk < kce;
-      const int64_t off = mfast ? xbase + (if0 + kk) * p.sf + mg : xbase + (if0 + kk) + mg * p.sm;
-      const T v = X[ok ? off : 0];
-      areg[q] = ok ? v : T(0);
-    }
-  };
-  auto store_unit = [&]() {
 #pragma unroll
-    for (int q = 0; q < NG; ++q) {
-      const int e = tid + 256 * q;
-      if (e < KC * RR) Gs[e] = greg[q];
-    }
+      for (int q = 0; q < KG; ++q) {
 #pragma unroll
-    for (int q = 0; q < NA; ++q) {
-      const int e = tid + 256 * q;
-      if (e < MT * KC) {
-        if (mfast)
-          As[(e / MT) * MTP + (e % MT)] = areg[q];
-        else
-          As[(e / KC) * KCP + (e % KC)] = areg[q];
+        for (int j = 0; j < NJ; ++j) acc[j] = mfma16(av[q], bv[q][j], acc[j]);
       }
     }
-  };
-
-  int64_t cur_o = -1;
-  if (u0 < u1) {
-    const int64_t o0 = u0 / p.nch;
-    if (tid == 0) xb_sh = decode_outer(g, o0, oidx);
+    // sum the K parts in a fixed order into Ys
+    if (kslot > 0) {
+#pragma unroll
+      for (int j = 0; j < NJ; ++j) {
+        const int cb = cslot + CS * j;
+        if (cb < nbf) {
+#pragma unroll
+          for (int v = 0; v < 4; ++v)
+            red[((kslot - 1) * 16 + Acc<T>::row(lane, v)) * dfp + cb * 16 + l16] = acc[j][v];
+        }
+      }
+    }
     __syncthreads();
-    load_unit(u0, xb_sh);
-  }
-  for (int64_t u = u0; u < u1; ++u) {
-    const int64_t o = u / p.nch;
-    if (o != cur_o) {
-      // xb_sh / oidx hold this unit's outer index (decoded before its loads)
-      if (nU > 0 && tid < RM) {
-        TC row[RM];
-        if (tid < Rn1) {
-          chain_row<TC, RM>(g, cv, oidx, qU, nU, tid, row);
-        } else {
+    if (kslot == 0) {
 #pragma unroll
-          for (int b = 0; b < RM; ++b) row[b] = TC(0);
+      for (int j = 0; j < NJ; ++j) {
+        const int cb = cslot + CS * j;
+        if (cb < nbf) {
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int r = Acc<T>::row(lane, v);
+            PT s = acc[j][v];
+            for (int ks = 1; ks < KS; ++ks) s += red[((ks - 1) * 16 + r) * dfp + cb * 16 + l16];
+            Ys[r * dfp + cb * 16 + l16] = s;
+          }
         }
-#pragma unroll
-        for (int b = 0; b < RM; ++b) Us[tid * RM + b] = b < Rf ? row[b] : TC(0);
       }
-      if (nV > 0 && tid >= 64 && tid < 64 + RM) {
-        const int r0 = tid - 64;
-        TC row[RM];
-        if (r0 < Rf1) {
-          chain_row<TC, RM>(g, cv, oidx, qV, nV, r0, row);
-        } else {
-#pragma unroll
-          for (int b = 0; b < RM; ++b) row[b] = TC(0);
-        }
-#pragma unroll
-        for (int b = 0; b < RM; ++b) Vs[r0 * RM + b] = b < Rn ? row[b] : TC(0);
-      }
-      cur_o = o;
     }
-    store_unit();
-    // decode the next unit's outer index (if it changes) and prefetch it
-    const int64_t un = u + 1;
-    const bool more = un < u1;
-    const int64_t on = more ? un / p.nch : o;
-    int64_t xbn = xb_sh;
-    if (more && on != o) {
-      __syncthreads();            // everyone has read oidx / Us / Vs inputs
-      if (tid == 0) xb_sh = decode_outer(g, on, oidx);
+    __syncthreads();
+    // W[m][s + Rn1 b] = sum_a U[s][a] Y[m][a + Rf b]
+    if (nU > 0) {
+      for (int e = tid; e < 16 * Rn1 * Rf1; e += 256) {
+        const int m = e / (Rn1 * Rf1), w = e - m * (Rn1 * Rf1);
+        const int s = w % Rn1, b = w / Rn1;
+        double acc2 = 0.0;
+        for (int a = 0; a < Rf; ++a) acc2 += Us[s * 16 + a] * (double)Ys[m * dfp + a + Rf * b];
+        Ws[m * wst + s + Rn1 * b] = acc2;
+      }
       __syncthreads();
-      xbn = xb_sh;
     }
-    if (more) load_unit(un, xbn);
-    const int kce = (int)(If - (u - o * p.nch) * KC < KC ? If - (u - o * p.nch) * KC : KC);
-    __syncthreads();
-    // subchain rows: B[kk][r + Rn*s] = (U[s,:] G_f(i_f) V)[r]
-    for (int w = tid; w < KC * Rn1; w += 256) {
-      const int kk = w / Rn1, s = w - kk * Rn1;
-      T* brow = Bs + kk * NTP;
-      const TC* Gk = Gs + kk * RR;
-      constexpr int UO = RM <= 8 ? RM : 2;
-      TC t[RM];
-#pragma unroll
-      for (int b = 0; b < RM; ++b) t[b] = TC(0);
-#pragma unroll UO
-      for (int a = 0; a < RM; ++a) {
-        const TC ua = Us[s * RM + a];
-#pragma unroll
-        for (int b = 0; b < RM; ++b) t[b] += ua * Gk[a + RM * b];
+    // P[m][r + Rn s] += sum_b W[m][s + Rn1 b] V[b][r]
+    for (int e = tid; e < 16 * dn; e += 256) {
+      const int m = e / dn, c = e - m * dn;
+      const int r = c % Rn, s = c / Rn;
+      double val;
+      if (nV > 0) {
+        val = 0.0;
+        for (int b = 0; b < Rf1; ++b) {
+          const double w = nU > 0 ? Ws[m * wst + s + Rn1 * b] : (double)Ys[m * dfp + s + Rn1 * b];
+          val += w * Vs[b * 16 + r];
+        }
+      } else {
+        val = nU > 0 ? Ws[m * wst + s + Rn1 * r] : (double)Ys[m * dfp + s + Rn1 * r];
       }
-      TC v[RM];
-#pragma unroll
-      for (int r = 0; r < RM; ++r) v[r] = TC(0);
-#pragma unroll UO
-      for (int b = 0; b < RM; ++b) {
-#pragma unroll
-        for (int r = 0; r < RM; ++r) v[r] += t[b] * Vs[b * RM + r];
-      }
-      const bool live = kk < kce;
-#pragma unroll
-      for (int r = 0; r < RM; ++r)
-        if (r < Rn) brow[r + Rn * s] = live ? (T)v[r] : T(0);
-    }
-    for (int w = tid; w < KC * (NTP - d); w += 256) {
-      const int kk = w / (NTP - d), c = d + (w - kk * (NTP - d));
-      Bs[kk * NTP + c] = T(0);
-    }
-    __syncthreads();
-#pragma unroll
-    for (int k0 = 0; k0 < KC; k0 += 4) {
-#pragma unroll
-      for (int bi = 0; bi < MAXB; ++bi) {
-        const T a = As[offA[bi] + k0 * sK];
-        const T bv = Bs[offB[bi] + k0 * NTP];
-        acc[bi] = mfma16(a, bv, acc[bi]);
-      }
+      Pa[e] += val;
     }
     __syncthreads();
   }
-#pragma unroll
-  for (int bi = 0; bi < MAXB; ++bi) {
-    const int b = wave + 4 * bi;
-    if (b < nblk) {
-      const int rb = b / NB, cb = b - rb * NB;
-      const int col = cb * 16 + (lane & 15);
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int64_t mg = m0 + rb * 16 + Acc<T>::row(lane, v);
-        if (mg < g.In && col < d) part[((size_t)split * g.In + mg) * d + col] = acc[bi][v];
-      }
-    }
+  for (int e = tid; e < 16 * dn; e += 256) {
+    const int m = e / dn;
+    if (m0 + m < g.In) part[((size_t)blockIdx.x * g.In + m0) * dn + e] = (PT)Pa[e];
   }
 }
 
-template <typename T, typename TC, int RM, int MAXB>
+template <typename T, typename TC, int NJ>
 static hipError_t launch_mttkrp_t(const Geom& g, const MttkrpPlan& p, const void* X,
                                   const CoreView& cv, void* part, hipStream_t st) {
-  const int NTP = ((g.d + 15) / 16) * 16;
-  const size_t amax = std::max((size_t)p.MT * (KC + 1), (size_t)KC * (p.MT + 1));
-  const size_t lds = (size_t)(2 * RM * RM + KC * RM * RM) * sizeof(TC) +
-                     (size_t)KC * NTP * sizeof(T) + amax * sizeof(T);
-  auto fn = k_mttkrp<T, TC, RM, MAXB>;
+  typedef typename Acc<T>::type PT;
+  const int dfp = 16 * p.nbf;
+  const int Rn1 = g.R[(g.n + 1) % g.N], Rf1 = g.R[(p.f + 1) % g.N];
+  const int wst = 16 * ((Rn1 * Rf1 + 15) / 16);
+  const size_t lds = (size_t)(3 * 256 + 16 * g.d + 16 * wst) * sizeof(double) +
+                     (size_t)(16 * dfp) * p.KS * sizeof(PT);
+  auto fn = k_mttkrp<T, TC, NJ>;
   if (lds > 65536) {
     hipError_t e = hipFuncSetAttribute((const void*)fn,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -482,32 +405,30 @@ static hipError_t launch_mttkrp_t(const Geom& g, const MttkrpPlan& p, const void
   return hipGetLastError();
 }
 
-template <typename T, typename TC, int RM>
-static hipError_t launch_mttkrp_r(const Geom& g, const MttkrpPlan& p, const void* X,
-                                  const CoreView& cv, void* part, hipStream_t st) {
-  const int nblk = (p.MT / 16) * ((g.d + 15) / 16);
-  const int per = (nblk + 3) / 4;
-  if (per <= 2) return launch_mttkrp_t<T, TC, RM, 2>(g, p, X, cv, part, st);
-  if (per <= 4) return launch_mttkrp_t<T, TC, RM, 4>(g, p, X, cv, part, st);
-  if (per <= 8) return launch_mttkrp_t<T, TC, RM, 8>(g, p, X, cv, part, st);
-  return launch_mttkrp_t<T, TC, RM, 16>(g, p, X, cv, part, st);
-}
-
 template <typename T, typename TC>
-static hipError_t launch_mttkrp_c(const Geom& g, const MttkrpPlan& p, const void* X,
+static hipError_t launch_mttkrp_j(const Geom& g, const MttkrpPlan& p, const void* X,
                                   const CoreView& cv, void* part, hipStream_t st) {
-  int rmax = 1;
-  for (int k = 0; k < g.N; ++k) rmax = g.R[k] > rmax ? g.R[k] : rmax;
-  if (rmax <= 8) return launch_mttkrp_r<T, TC, 8>(g, p, X, cv, part, st);
-  if (rmax <= 12) return launch_mttkrp_r<T, TC, 12>(g, p, X, cv, part, st);
-  return launch_mttkrp_r<T, TC, 16>(g, p, X, cv, part, st);
+  const int nj = (p.nbf + 4 / p.KS - 1) / (4 / p.KS);
+  switch (nj) {
+    case 1: return launch_mttkrp_t<T, TC, 1>(g, p, X, cv, part, st);
+    case 2: return launch_mttkrp_t<T, TC, 2>(g, p, X, cv, part, st);
+    case 3: return launch_mttkrp_t<T, TC, 3>(g, p, X, cv, part, st);
+    default: return launch_mttkrp_t<T, TC, 4>(g, p, X, cv, part, st);
+  }
 }
 
 hipError_t launch_mttkrp(const Geom& g, const MttkrpPlan& p, const void* X, int xdt,
                          const CoreView& cv, int cdt, void* part, hipStream_t st) {
-  if (xdt == F64 && cdt == F64) return launch_mttkrp_c<double, double>(g, p, X, cv, part, st);
-  if (xdt == F32 && cdt == F64) return launch_mttkrp_c<float, double>(g, p, X, cv, part, st);
-  if (xdt == F32 && cdt == F32) return launch_mttkrp_c<float, float>(g, p, X, cv, part, st);
+  if (g.d > 256 || p.nbf > 16) return hipErrorInvalidValue;
+  // the kernel's per-outer-index offsets are 32-bit
+  const int f = p.f;
+  const int64_t xspan = (g.In - 1) * p.sm + (g.I[f] - 1) * p.sf + 1;
+  const int64_t gspan = (g.I[f] - 1) * cv.si[f] + (g.R[f] - 1) * cv.sr[f] +
+                        (g.R[(f + 1) % g.N] - 1) * cv.ss[f] + 1;
+  if (xspan >= ((int64_t)1 << 31) || gspan >= ((int64_t)1 << 31)) return hipErrorInvalidValue;
+  if (xdt == F64 && cdt == F64) return launch_mttkrp_j<double, double>(g, p, X, cv, part, st);
+  if (xdt == F32 && cdt == F64) return launch_mttkrp_j<float, double>(g, p, X, cv, part, st);
+  if (xdt == F32 && cdt == F32) return launch_mttkrp_j<float, float>(g, p, X, cv, part, st);
   return hipErrorInvalidValue;
 }
 
@@ -1005,9 +926,372 @@ __global__ __launch_bounds__(1024) void k_side(SideArgs sa) {
   if (bad && tid == 0 && sa.status) sa.status[0] = 1;
 }
 
+// ---------------------------------------------------------------------------
+// MFMA form of the side step for d <= 192.  Q is padded to D = 16*nb with an
+// identity block and held in 16x16 tiles in the FP64 MFMA accumulator layout
+// (lane l, register v: row l/16 + 4v, column l%16); tile t = ti*nb + tj
+// belongs to wave t % 16.  The inverse is the in-place Gauss-Jordan
+// elimination taken over 16x16 pivot blocks K:
+//   P = A_KK^{-1};  A_Kj <- P A_Kj;  A_iK <- -A_iK P;
+//   A_ij <- A_ij - A_iK P A_Kj;  A_KK <- P,
+// which leaves A^{-1} after the last block.  The pivot block is inverted by
+// its owning wave with cross-lane shuffles; the block updates run on MFMAs.
+// The scalar pivots met inside the pivot blocks are the Schur-complement
+// diagonals of the unblocked elimination, so the positivity test is the
+// same.  One workgroup barrier per pivot block.
+// ---------------------------------------------------------------------------
+
+// In-place Gauss-Jordan inverse of a 16x16 tile held by one wave in the
+// accumulator layout; rows / columns >= nvalid are identity padding and are
+// not tested.  Returns true if a tested pivot is not above tol.
+__device__ inline bool wave_gj16(d4& c, int lane, double tol, int nvalid) {
+  const int r0 = lane >> 4, j = lane & 15;
+  bool bad = false;
+#pragma unroll
+  for (int p = 0; p < 16; ++p) {
+    const double rowp = __shfl(c[p >> 2], ((p & 3) << 4) | j, 64);      // T[p][j]
+    const double piv = __shfl(c[p >> 2], ((p & 3) << 4) | p, 64);       // T[p][p]
+    double colp[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) colp[v] = __shfl(c[v], (r0 << 4) | p, 64);  // T[i][p]
+    if (p < nvalid && !(piv > tol)) bad = true;
+    const double ip = 1.0 / piv;
+    const double rs = rowp * ip;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int i = r0 + 4 * v;
+      const double x = c[v];
+      double y;
+      if (i == p)
+        y = (j == p) ? ip : x * ip;
+      else
+        y = (j == p) ? -x * ip : x - colp[v] * rs;
+      c[v] = y;
+    }
+  }
+  return bad;
+}
+
+// LDS budget of the side step, in doubles (64 KiB: room is left on the CU for
+// two MTTKRP workgroups running beside it).
+constexpr int SIDE_LDS = 8192;
+
+template <int MAXT>
+__global__ __launch_bounds__(1024) void k_side_mf(SideArgs sa) {
+  extern __shared__ double lds[];
+  __shared__ double dmax[16];
+  const int tid = threadIdx.x;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
+  const int ar = lane & 15, ak = lane >> 4;
+  // 1. Gram of the previous core, written in the transfer layout.  Rows are
+  //    staged through LDS in chunks of CR rows (every load of a chunk in
+  //    flight at once, the next chunk prefetched into registers while the
+  //    current one is multiplied); up to 4 output tiles per wave and pass.
+  if (sa.Gp) {
+    const int Ra = sa.Rpa, Rb = sa.Rpb, dp = Ra * Rb;
+    const int nbp = (dp + 15) >> 4, ntp = nbp * nbp;
+    const int64_t rows = sa.rows_p;
+    const int CR = (SIDE_LDS / dp) & ~3;
+    const int64_t nchunk = (rows + CR - 1) / CR;
+    constexpr int PER = SIDE_LDS / 1024;
+    const double* __restrict__ Gp = sa.Gp;
+    for (int t0 = 0; t0 < ntp; t0 += 64) {
+      d4 acc[4];
+#pragma unroll
+      for (int s = 0; s < 4; ++s) acc[s] = d4{0, 0, 0, 0};
+      double pre[PER];
+      // the address is clamped independently of the mask so that every load
+      // of the chunk is issued unconditionally
+      const int64_t tot = rows * dp;
+      auto fetch = [&](int64_t c) {
+        const int64_t base = c * CR * dp;
+        const int64_t lim = (rows - c * CR < CR ? rows - c * CR : CR) * dp;
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+          const int e = tid + 1024 * q;
+          const double x = Gp[min(base + e, tot - 1)];
+          pre[q] = e < lim ? x : 0.0;
+        }
+      };
+      if (nchunk > 0) fetch(0);
+      for (int64_t c = 0; c < nchunk; ++c) {
+#pragma unroll
+        for (int q = 0; q < PER; ++q) lds[tid + 1024 * q] = pre[q];
+        __syncthreads();
+        if (c + 1 < nchunk) fetch(c + 1);
+        const int64_t crow = rows - c * CR < CR ? rows - c * CR : CR;
+        const int kend = (int)((crow + 3) & ~3);
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+          const int t = t0 + wave + 16 * s;
+          if (t < ntp) {
+            const int rb = t / nbp, cb = t - rb * nbp;
+            const int c1 = min(rb * 16 + ar, dp - 1), c2 = min(cb * 16 + ar, dp - 1);
+            d4 a = acc[s];
+#pragma unroll 8
+            for (int k0 = 0; k0 < kend; k0 += 4) {
+              const int i = k0 + ak;
+              a = mfma16(lds[i * dp + c1], lds[i * dp + c2], a);
+            }
+            acc[s] = a;
+          }
+        }
+        __syncthreads();
+      }
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        const int t = t0 + wave + 16 * s;
+        if (t < ntp) {
+          const int rb = t / nbp, cb = t - rb * nbp;
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int r = rb * 16 + Acc<double>::row(lane, v), c = cb * 16 + ar;
+            if (r < dp && c < dp) {
+              const int a1 = r % Ra, b1 = r / Ra, a2 = c % Ra, b2 = c / Ra;
+              sa.Ep[(size_t)(a1 + Ra * a2) * (Rb * Rb) + (b1 + Rb * b2)] = acc[s][v];
+            }
+          }
+        }
+      }
+    }
+    __syncthreads();
+  }
+  // 2. ring product of the transfer-layout factors: both operands staged in
+  //    LDS when they fit, else read through the cache in batches of 8 k-steps.
+  const double* M = sa.fac[0] ? sa.fac[0] : sa.Ep;
+  for (int j = 1; j < sa.nfac; ++j) {
+    const double* __restrict__ F = sa.fac[j] ? sa.fac[j] : sa.Ep;
+    double* out = sa.cbuf[(j - 1) & 1];
+    const int d1 = sa.fr[0], d2 = sa.fc[j - 1], d3 = sa.fc[j];
+    const int nb1 = (d1 + 15) >> 4, nb3 = (d3 + 15) >> 4;
+    const bool staged = d1 * d2 + d2 * d3 <= SIDE_LDS;
+    if (staged) {
+      // [M | F] copied to LDS with all loads in flight at once
+      const int n1 = d1 * d2, n2 = d2 * d3;
+      constexpr int PER = SIDE_LDS / 1024;
+      double x[PER];
+#pragma unroll
+      for (int q = 0; q < PER; ++q) {
+        const int e = tid + 1024 * q;
+        const double a = M[min(e, n1 - 1)];
+        const double b = F[min(max(e - n1, 0), n2 - 1)];
+        x[q] = e < n1 ? a : b;
+      }
+#pragma unroll
+      for (int q = 0; q < PER; ++q) {
+        const int e = tid + 1024 * q;
+        if (e < n1 + n2) lds[e] = x[q];
+      }
+      __syncthreads();
+    }
+    for (int b = wave; b < nb1 * nb3; b += 16) {
+      const int rb = b / nb3, cb = b - rb * nb3;
+      const int arow = min(rb * 16 + ar, d1 - 1), bcol = min(cb * 16 + ar, d3 - 1);
+      d4 acc = {0, 0, 0, 0};
+      const int kfull = d2 & ~3;
+      if (staged) {
+        const double* Ms = lds;
+        const double* Fs = lds + d1 * d2;
+#pragma unroll 8
+        for (int k0 = 0; k0 < kfull; k0 += 4) {
+          const int k = k0 + ak;
+          acc = mfma16(Ms[arow * d2 + k], Fs[k * d3 + bcol], acc);
+        }
+      } else {
+        int k0 = 0;
+        for (; k0 + 32 <= kfull; k0 += 32) {
+          double av[8], bv[8];
+#pragma unroll
+          for (int q = 0; q < 8; ++q) {
+            const int k = k0 + 4 * q + ak;
+            av[q] = M[(size_t)arow * d2 + k];
+            bv[q] = F[(size_t)k * d3 + bcol];
+          }
+#pragma unroll
+          for (int q = 0; q < 8; ++q) acc = mfma16(av[q], bv[q], acc);
+        }
+        for (; k0 < kfull; k0 += 4) {
+          const int k = k0 + ak;
+          acc = mfma16(M[(size_t)arow * d2 + k], F[(size_t)k * d3 + bcol], acc);
+        }
+      }
+      if (kfull < d2) {
+        // ragged last k-step: lanes past d2 contribute zeros
+        const int k = kfull + ak;
+        const int kc = min(k, d2 - 1);
+        const double av = staged ? lds[arow * d2 + kc] : M[(size_t)arow * d2 + kc];
+        const double bv = staged ? lds[d1 * d2 + kc * d3 + bcol] : F[(size_t)kc * d3 + bcol];
+        acc = mfma16(k < d2 ? av : 0.0, k < d2 ? bv : 0.0, acc);
+      }
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int r = rb * 16 + Acc<double>::row(lane, v), c = cb * 16 + ar;
+        if (r < d1 && c < d3) out[(size_t)r * d3 + c] = acc[v];
+      }
+    }
+    __syncthreads();
+    M = out;
+  }
+  // 3. Q tiles: assembly from the chain product, accumulation, store
+  const int Ra = sa.Ra, Rb = sa.Rb, d = Ra * Rb;
+  const int nb = (d + 15) >> 4, ntile = nb * nb;
+  d4 A[MAXT];
+  double mx = 0.0;
+#pragma unroll
+  for (int s = 0; s < MAXT; ++s) {
+    const int t = wave + 16 * s;
+    d4 x = {0, 0, 0, 0};
+    if (t < ntile) {
+      const int ti = t / nb, tj = t - ti * nb;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int gi = ti * 16 + Acc<double>::row(lane, v), gj = tj * 16 + ar;
+        double val;
+        if (gi < d && gj < d) {
+          const int e = gi * d + gj;
+          const int r = gi % Ra, s1 = gi / Ra, r2 = gj % Ra, s2 = gj / Ra;
+          val = M[(size_t)(s1 + Rb * s2) * (Ra * Ra) + (r + Ra * r2)];
+          if (sa.Q && sa.accumulate) val += sa.Q[e];
+          if (sa.Q && sa.store_Q) sa.Q[e] = val;
+          if (gi == gj) mx = fmax(mx, val);
+        } else {
+          val = gi == gj ? 1.0 : 0.0;
+        }
+        x[v] = val;
+      }
+    }
+    A[s] = x;
+  }
+  if (!sa.Qinv) return;
+  for (int off = 32; off > 0; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off, 64));
+  if (lane == 0) dmax[wave] = mx;
+  __syncthreads();
+  mx = 0.0;
+#pragma unroll
+  for (int w = 0; w < 16; ++w) mx = fmax(mx, dmax[w]);
+  const double tol = (double)d * 2.220446049250313e-16 * mx;
+  // 4. blocked Gauss-Jordan, LDS double-buffered per pivot block:
+  //    Pb = P (row-major), PbT = P^T, RowB[j] = A_Kj (row-major),
+  //    ColT[i] = A_iK^T
+  const int bstride = 2 * nb * 256 + 512;
+  const bool dbuf = 2 * bstride <= SIDE_LDS;
+  const int kq = lane >> 4, cl = lane & 15;
+  bool bad = false;
+  for (int K = 0; K < nb; ++K) {
+    double* Pb = lds + (dbuf ? (K & 1) * bstride : 0);
+    double* PbT = Pb + 256;
+    double* RowB = Pb + 512;
+    double* ColT = RowB + nb * 256;
+#pragma unroll
+    for (int s = 0; s < MAXT; ++s) {
+      const int t = wave + 16 * s;
+      if (t < ntile) {
+        const int ti = t / nb, tj = t - ti * nb;
+        if (ti == K && tj == K) {
+          bad |= wave_gj16(A[s], lane, tol, d - 16 * K);
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int r = Acc<double>::row(lane, v);
+            Pb[r * 16 + cl] = A[s][v];
+            PbT[cl * 16 + r] = A[s][v];
+          }
+        } else if (ti == K) {
+#pragma unroll
+          for (int v = 0; v < 4; ++v)
+            RowB[tj * 256 + Acc<double>::row(lane, v) * 16 + cl] = A[s][v];
+        } else if (tj == K) {
+#pragma unroll
+          for (int v = 0; v < 4; ++v)
+            ColT[ti * 256 + cl * 16 + Acc<double>::row(lane, v)] = A[s][v];
+        }
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int s = 0; s < MAXT; ++s) {
+      const int t = wave + 16 * s;
+      if (t < ntile) {
+        const int ti = t / nb, tj = t - ti * nb;
+        if (ti == K && tj == K) {
+          // holds P already
+        } else if (ti == K) {
+          // A_Kj <- P A_Kj
+          d4 acc = {0, 0, 0, 0};
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const int o = (4 * q + kq) * 16 + cl;
+            acc = mfma16(PbT[o], RowB[tj * 256 + o], acc);
+          }
+          A[s] = acc;
+        } else if (tj == K) {
+          // A_iK <- -A_iK P
+          d4 acc = {0, 0, 0, 0};
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const int o = (4 * q + kq) * 16 + cl;
+            acc = mfma16(-ColT[ti * 256 + o], Pb[o], acc);
+          }
+          A[s] = acc;
+        } else {
+          // U = -P^T A_iK^T = (-A_iK P)^T: its accumulator layout is the
+          // A-operand layout of -A_iK P, so A_ij += (-A_iK P) A_Kj follows.
+          d4 u = {0, 0, 0, 0};
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const int o = (4 * q + kq) * 16 + cl;
+            u = mfma16(-Pb[o], ColT[ti * 256 + o], u);
+          }
+          d4 acc = A[s];
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const int o = (4 * q + kq) * 16 + cl;
+            acc = mfma16(u[q], RowB[tj * 256 + o], acc);
+          }
+          A[s] = acc;
+        }
+      }
+    }
+    if (!dbuf) __syncthreads();
+  }
+#pragma unroll
+  for (int s = 0; s < MAXT; ++s) {
+    const int t = wave + 16 * s;
+    if (t < ntile) {
+      const int ti = t / nb, tj = t - ti * nb;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int gi = ti * 16 + Acc<double>::row(lane, v), gj = tj * 16 + cl;
+        if (gi < d && gj < d) sa.Qinv[gi * d + gj] = A[s][v];
+      }
+    }
+  }
+  if (bad && lane == 0 && sa.status) sa.status[0] = 1;
+}
+
+template <int MAXT>
+static hipError_t launch_side_mf(const SideArgs& a, int nb, hipStream_t st) {
+  const size_t lds = (size_t)SIDE_LDS * sizeof(double);
+  auto fn = k_side_mf<MAXT>;
+  if (lds > 65536) {
+    hipError_t e = hipFuncSetAttribute((const void*)fn,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(fn, dim3(1), dim3(1024), lds, st, a);
+  return hipGetLastError();
+}
+
 hipError_t launch_side(const SideArgs& a, hipStream_t st) {
   const int d = a.Ra * a.Rb;
   if (d > 256) return hipErrorInvalidValue;
+  const int nb = (d + 15) / 16;
+  static const bool scalar_gj = getenv("TRSTREAM_SCALAR_GJ") != nullptr;
+  if (nb <= 12 && !scalar_gj) {
+    if (nb * nb <= 16) return launch_side_mf<1>(a, nb, st);
+    if (nb * nb <= 32) return launch_side_mf<2>(a, nb, st);
+    if (nb * nb <= 64) return launch_side_mf<4>(a, nb, st);
+    return launch_side_mf<9>(a, nb, st);
+  }
   const int B = (d + 31) / 32;
 #define TRK_SIDE(BB) \
   hipLaunchKernelGGL(k_side<BB>, dim3(1), dim3(1024), 0, st, a)

@@ -36,17 +36,19 @@ enum DType { F64 = 0, F32 = 1, BF16 = 2 };
 // Work decomposition of one mode-n product.  The columns of X_[n] are
 // enumerated as (outer o, fast index i_f): f is the fastest-varying mode
 // other than n (f = 0 for n >= 1, f = 1 for n = 0), and o runs over all
-// remaining indices.  A unit is one chunk of KC consecutive i_f of one o;
-// workgroup (split, mtile) owns units [split*upw, (split+1)*upw).
+// remaining indices.  Workgroup (chunk, mtile) owns rows [16 mtile, +16)
+// and the outer indices [chunk*upw, (chunk+1)*upw).
 struct MttkrpPlan {
-  int MT;          // rows per tile (multiple of 16)
-  int mtiles;      // ceil(In / MT)
-  int nsplit;      // number of unit ranges
+  int MT;          // rows per tile (16)
+  int mtiles;      // ceil(In / 16)
+  int nsplit;      // number of outer-index chunks (partials)
   int psize;       // bytes per partial element (8 f64 path, 4 f32 path)
   int f;           // fast mode
-  int nch;         // chunks per outer index, ceil(I_f / KC)
+  int nbf;         // 16-column tiles of R_f R_{f+1}
+  int KS;          // waves splitting K = I_f (4, 2 or 1)
+  int Q;           // consecutive i_f per lane group
   int64_t Kout;    // number of outer indices
-  int64_t upw;     // units per workgroup
+  int64_t upw;     // outer indices per workgroup
   int64_t sf, sm;  // X strides of i_f and of the row index i_n
 };
 
