@@ -7,7 +7,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libtrstream.so")
-SOURCES = [os.path.join(HERE, "csrc", f) for f in ("kernels.hip", "sketch.hip", "runtime.hip")]
+SOURCES = [os.path.join(HERE, "csrc", f) for f in ("kernels.hip", "sketch.hip", "ksrft.hip", "runtime.hip")]
 
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

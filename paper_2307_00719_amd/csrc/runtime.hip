@@ -78,6 +78,22 @@ struct tr_stream {
   double* Sw = nullptr;      // m weights
   double* Zb = nullptr;      // dmax^2 (or I^2 <= 256^2) scratch Gram
   double* Zi = nullptr;      // its inverse
+  // KSRFT state (rSTR-K)
+  double* dsign[MAXN] = {};  // diagonal of D_k (temporal: ksign_cap entries)
+  int64_t ksign_cap = 0;
+  double* GSc[MAXN] = {};    // sampled mixed slices: 2 planes of m x d_k
+  double** dGSc = nullptr;   // device copy of GSc[]
+  double* Ast = nullptr;     // [Re A; Im A], 2m x dmax
+  double* Bst = nullptr;     // product operand, 2m x 2 dmax
+  double* Sw2 = nullptr;     // 2m weights
+  void* Wmix = nullptr;      // mixing matrix of one mode
+  size_t Wmix_bytes = 0;
+  void* xh[2] = {};          // mixed batch, 2 planes (ping-pong)
+  size_t xh_bytes[2] = {};
+  double* Zk = nullptr;      // reduced sketched product, I x 2d
+  size_t Zk_bytes = 0;
+  double* dPk = nullptr;     // unmixed increment, I x d
+  size_t dPk_bytes = 0;
   // event profiling (tr_stream_profile)
   bool prof = false;
   std::vector<hipEvent_t> ev_pool;
@@ -450,6 +466,169 @@ tr_status sketch_update(tr_stream* s, const void* Xd, int64_t t_new, double* Gne
   return TR_OK;
 }
 
+// ---- rSTR-K (Alg. 9) --------------------------------------------------------
+
+// D_k of the current step for every mode (the temporal one over t entries).
+tr_status ksrft_signs(tr_stream* s, int64_t t) {
+  const int N = s->N;
+  if (t > s->ksign_cap) {
+    if (s->dsign[N - 1]) {
+      TR_HIP(hipStreamSynchronize(s->st));
+      TR_HIP(hipFree(s->dsign[N - 1]));
+    }
+    TR_HIP(dev_alloc(&s->dsign[N - 1], (size_t)t));
+    s->ksign_cap = t;
+  }
+  for (int k = 0; k < N; ++k) {
+    const int64_t n = k == N - 1 ? t : s->I[k];
+    TR_HIP(launch_signs(rng_key(s->seed, (uint64_t)s->step, (uint64_t)k, 1), n, s->dsign[k],
+                        s->st));
+  }
+  return TR_OK;
+}
+
+// Xhat = X x_1 (F_1 D_1) ... x_N (F_N D_N) (Alg. 6) of a batch of t slices in
+// the compute dtype; *xhat receives the two planes (F64, or F32 for the F32
+// and BF16 paths).
+tr_status ksrft_mix(tr_stream* s, const void* Xd, int64_t t, const void** xhat) {
+  const int N = s->N;
+  std::vector<int64_t> dims(N);
+  int64_t total = 1;
+  for (int k = 0; k < N; ++k) {
+    dims[k] = k == N - 1 ? t : s->I[k];
+    total *= dims[k];
+  }
+  const size_t xs = s->dt == F64 ? 8 : 4;
+  const size_t ws = s->dt == F64 ? 8 : (s->dt == F32 ? 4 : 2);
+  for (int b = 0; b < 2; ++b) TR_HIP(ensure(&s->xh[b], &s->xh_bytes[b], 2 * (size_t)total * xs));
+  size_t wneed = 0;
+  for (int k = 0; k < N; ++k)
+    wneed = std::max(wneed, (size_t)2 * dims[k] * mix_k_padded(dims[k], 2) * ws);
+  TR_HIP(ensure(&s->Wmix, &s->Wmix_bytes, wneed));
+  const void* in = Xd;
+  int idt = s->dt, pin = 1, cur = 0;
+  int64_t S = 1;
+  for (int k = 0; k < N; ++k) {
+    const int64_t Ik = dims[k], C = total / (S * Ik);
+    TR_HIP(launch_mix_weights(Ik, pin, s->dsign[k], s->dt, s->Wmix, s->st));
+    TR_HIP(launch_mix_mode(in, idt, pin, total, s->xh[cur], total, S, Ik, C, s->Wmix, s->dt,
+                           s->st));
+    in = s->xh[cur];
+    idt = s->dt == F64 ? F64 : F32;
+    pin = 2;
+    cur ^= 1;
+    S *= Ik;
+  }
+  *xhat = in;
+  return TR_OK;
+}
+
+// Sampled mixed slices of core k: rows of (F_k D_k) G_k at idxs(:, k).
+tr_status ksrft_slices(tr_stream* s, int k, const double* rows, int64_t I) {
+  TR_HIP(launch_mix_slices(rows, I, s->d(k), s->dsign[k], s->idxs + (size_t)k * s->m, (int)s->m,
+                           s->GSc[k], s->st));
+  return TR_OK;
+}
+
+// One mode of Alg. 9: Re(Q_n) += Re(Ghat_S^T W conj(Ghat_S)) and
+// Re(P_n) += Re(D_n F_n^* Xhat_S W conj(Ghat_S)), then G_n = Re(P_n) Re(Q_n)^-1
+// when `solve`; for the temporal mode (n = N-1) the rows G_N^new are written
+// to Gout from the increments alone (or the literal reading
+// Re(D F^* Xhat_S) (Re(Ghat_S)^T)^+ when temporal_literal is set).
+tr_status ksrft_increment(tr_stream* s, int n, const void* xhat, int64_t t, int accumulate,
+                          bool solve, double* Gout) {
+  const int N = s->N;
+  std::vector<int64_t> gd(N);
+  int64_t total = 1;
+  for (int k = 0; k < N; ++k) {
+    gd[k] = k == N - 1 ? t : s->I[k];
+    total *= gd[k];
+  }
+  Geom g = make_geom(N, gd.data(), s->R, n);
+  const int m = (int)s->m, d = g.d;
+  const bool temporal = n == N - 1;
+  const bool literal = temporal && s->temporal_literal;
+  double w = 1.0;
+  if (s->rescale && !literal)
+    w = temporal ? (double)prod_dims_except(s, -1) / m : (double)prod_dims_except(s, n) * t / m;
+  TR_HIP(launch_sample_rows_c(g, (const double* const*)s->dGSc, m, w, literal ? 1 : 0, s->Ast,
+                              s->Bst, s->Sw2, s->st));
+  if (literal)
+    TR_HIP(launch_wgram(s->Ast, nullptr, m, d, s->Zb, s->st));
+  else
+    TR_HIP(launch_wgram(s->Ast, s->Sw2, 2 * (int64_t)m, d, s->Zb, s->st));
+  if (temporal)
+    TR_HIP(launch_invert_spd(s->Zb, s->R[n], s->R[(n + 1) % N], nullptr, 0, 0, s->Minv,
+                             s->dstatus, s->st, 1));
+  else
+    TR_HIP(launch_invert_spd(s->Zb, s->R[n], s->R[(n + 1) % N], s->Q[n], accumulate, 1,
+                             solve ? s->Minv : nullptr, s->dstatus, s->st, 1));
+  SgemmPlan sp = plan_sgemm(g, m, 2 * d, s->dt);
+  TR_HIP(ensure(&s->part, &s->part_bytes, (size_t)sp.nsplit * g.In * 2 * d * sp.psize));
+  TR_HIP(launch_sgemm(g, sp, 2 * d, total, xhat, s->dt, s->idxs, m, s->Bst, s->part, s->st));
+  TR_HIP(ensure((void**)&s->Zk, &s->Zk_bytes, (size_t)g.In * 2 * d * sizeof(double)));
+  TR_HIP(ensure((void**)&s->dPk, &s->dPk_bytes, (size_t)g.In * d * sizeof(double)));
+  TR_HIP(launch_reduce_solve(s->part, sp.psize, sp.nsplit, g.In, 2 * d, s->Zk, 0, nullptr,
+                             nullptr, s->st));
+  TR_HIP(launch_unmix(s->Zk, g.In, d, s->dsign[n], s->dPk, s->st));
+  TR_HIP(launch_reduce_solve(s->dPk, 8, 1, g.In, d, temporal ? nullptr : s->P[n], accumulate,
+                             solve ? s->Minv : nullptr, Gout, s->st));
+  return TR_OK;
+}
+
+tr_status ksrft_init(tr_stream* s, const void* Xd, int64_t t_init) {
+  const int N = s->N;
+  s->step = 0;
+  tr_status c = ksrft_signs(s, t_init);
+  if (c != TR_OK) return c;
+  const void* xhat = nullptr;
+  c = ksrft_mix(s, Xd, t_init, &xhat);
+  if (c != TR_OK) return c;
+  for (int k = 0; k < N; ++k) {
+    c = draw_samples(s, k, k == N - 1 ? t_init : s->I[k]);
+    if (c != TR_OK) return c;
+  }
+  for (int k = 0; k < N; ++k) {
+    c = ksrft_slices(s, k, s->G[k], k == N - 1 ? t_init : s->I[k]);
+    if (c != TR_OK) return c;
+  }
+  for (int n = 0; n < N - 1; ++n) {
+    c = ksrft_increment(s, n, xhat, t_init, 0, false, nullptr);
+    if (c != TR_OK) return c;
+  }
+  return TR_OK;
+}
+
+// One time step of rSTR-K (Alg. 9).
+tr_status ksrft_update(tr_stream* s, const void* Xd, int64_t t_new, double* Gnew) {
+  const int N = s->N;
+  s->step += 1;
+  tr_status c = ksrft_signs(s, t_new);
+  if (c != TR_OK) return c;
+  const void* xhat = nullptr;
+  c = ksrft_mix(s, Xd, t_new, &xhat);
+  if (c != TR_OK) return c;
+  for (int k = 0; k < N - 1; ++k) {
+    c = ksrft_slices(s, k, s->G[k], s->I[k]);
+    if (c != TR_OK) return c;
+  }
+  c = ksrft_increment(s, N - 1, xhat, t_new, 0, true, Gnew);
+  if (c != TR_OK) return c;
+  c = draw_samples(s, N - 1, t_new);
+  if (c != TR_OK) return c;
+  c = ksrft_slices(s, N - 1, Gnew, t_new);
+  if (c != TR_OK) return c;
+  for (int n = 0; n < N - 1; ++n) {
+    c = ksrft_increment(s, n, xhat, t_new, 1, true, s->G[n]);
+    if (c != TR_OK) return c;
+    c = draw_samples(s, n, s->I[n]);
+    if (c != TR_OK) return c;
+    c = ksrft_slices(s, n, s->G[n], s->I[n]);
+    if (c != TR_OK) return c;
+  }
+  return TR_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -468,10 +647,18 @@ tr_status tr_stream_init(const tr_config* cfg, const double* X_init, int64_t t_i
     if (cfg->ranks[k] < 1) return TR_ERR_SHAPE;
   for (int k = 0; k < N; ++k)
     if (cfg->ranks[k] > RMAXC) return TR_ERR_UNSUPPORTED;
-  if (cfg->compute_dtype != TR_F64 && cfg->compute_dtype != TR_F32) return TR_ERR_UNSUPPORTED;
   if (cfg->sketch != TR_SKETCH_NONE && cfg->sketch != TR_SKETCH_UNIFORM &&
-      cfg->sketch != TR_SKETCH_LEVERAGE)
+      cfg->sketch != TR_SKETCH_LEVERAGE && cfg->sketch != TR_SKETCH_KSRFT)
+    return TR_ERR_ARG;
+  if (cfg->compute_dtype != TR_F64 && cfg->compute_dtype != TR_F32 &&
+      !(cfg->compute_dtype == TR_BF16 && cfg->sketch == TR_SKETCH_KSRFT))
     return TR_ERR_UNSUPPORTED;
+  if (cfg->sketch == TR_SKETCH_KSRFT) {
+    // the mixing kernels take modes of up to 256 indices per batch
+    for (int k = 0; k < N - 1; ++k)
+      if (cfg->dims[k] > 256) return TR_ERR_UNSUPPORTED;
+    if (t_init > 256) return TR_ERR_UNSUPPORTED;
+  }
   if (cfg->sketch != TR_SKETCH_NONE) {
     if (cfg->sketch_size < 1 || cfg->sketch_size > (1 << 24)) return TR_ERR_ARG;
     for (int k = 0; k < N; ++k)
@@ -544,6 +731,15 @@ tr_status tr_stream_init(const tr_config* cfg, const double* X_init, int64_t t_i
       for (int k = 0; k < N - 1; ++k) TR_HIP(dev_alloc(&s->probs[k], (size_t)s->I[k]));
     TR_HIP(hipMemcpyAsync(s->dprobs, s->probs, N * sizeof(double*), hipMemcpyHostToDevice, s->st));
   }
+  if (s->sketch == TR_SKETCH_KSRFT) {
+    for (int k = 0; k < N - 1; ++k) TR_HIP(dev_alloc(&s->dsign[k], (size_t)s->I[k]));
+    for (int k = 0; k < N; ++k) TR_HIP(dev_alloc(&s->GSc[k], (size_t)2 * s->m * s->d(k)));
+    TR_HIP(dev_alloc(&s->dGSc, (size_t)N));
+    TR_HIP(hipMemcpyAsync(s->dGSc, s->GSc, N * sizeof(double*), hipMemcpyHostToDevice, s->st));
+    TR_HIP(dev_alloc(&s->Ast, (size_t)2 * s->m * dmax));
+    TR_HIP(dev_alloc(&s->Bst, (size_t)4 * s->m * dmax));
+    TR_HIP(dev_alloc(&s->Sw2, (size_t)2 * s->m));
+  }
 
   // cores: column-major FP64 (host or device) -> slice-major state
   std::vector<int64_t> dims(N);
@@ -583,7 +779,7 @@ tr_status tr_stream_init(const tr_config* cfg, const double* X_init, int64_t t_i
   std::vector<int64_t> gd(dims);
   const CoreView cv = state_view(s, s->G[N - 1]);
   if (s->sketch != TR_SKETCH_NONE) {
-    c = sketch_init(s, Xd, t_init);
+    c = s->sketch == TR_SKETCH_KSRFT ? ksrft_init(s, Xd, t_init) : sketch_init(s, Xd, t_init);
     if (c != TR_OK) return c;
     TR_HIP(hipStreamSynchronize(s->st));
     s->copy_pending = false;
@@ -634,7 +830,10 @@ tr_status tr_stream_update(tr_stream* s, const void* X_new, int32_t x_dtype, int
 
   if (s->sketch != TR_SKETCH_NONE) {
     const long pst = prof_begin(s, PK_STEP);
-    c = sketch_update(s, Xd, t_new, Gnew);
+    if (s->sketch == TR_SKETCH_KSRFT && t_new > 256)
+      return fail(s, TR_ERR_UNSUPPORTED, "KSRFT batches hold at most 256 slices");
+    c = s->sketch == TR_SKETCH_KSRFT ? ksrft_update(s, Xd, t_new, Gnew)
+                                     : sketch_update(s, Xd, t_new, Gnew);
     if (c != TR_OK) return c;
     prof_end(s, pst);
     s->t_total += t_new;
@@ -870,8 +1069,14 @@ void tr_stream_destroy(tr_stream* s) {
     if (s->P[k]) (void)hipFree(s->P[k]);
     if (s->Q[k]) (void)hipFree(s->Q[k]);
   }
-  for (int k = 0; k < MAXN; ++k)
+  for (int k = 0; k < MAXN; ++k) {
     if (s->probs[k]) (void)hipFree(s->probs[k]);
+    if (s->dsign[k]) (void)hipFree(s->dsign[k]);
+    if (s->GSc[k]) (void)hipFree(s->GSc[k]);
+  }
+  void* kbufs[] = {s->dGSc, s->Ast, s->Bst, s->Sw2, s->Wmix, s->xh[0], s->xh[1], s->Zk, s->dPk};
+  for (void* b : kbufs)
+    if (b) (void)hipFree(b);
   void* bufs[] = {s->Minv, s->chain[0], s->chain[1], s->xcast, s->xf64, s->part,
                   s->wg,   s->pair,     s->dstatus,  s->idxs,  s->SA,   s->Sw,
                   s->Zb,   s->Zi,       s->dprobs,   s->cdf};

@@ -16,13 +16,6 @@
 
 namespace trk {
 
-__host__ __device__ inline uint64_t mix64(uint64_t x) {
-  uint64_t z = x + 0x9E3779B97F4A7C15ull;
-  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
-  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
-  return z ^ (z >> 31);
-}
-
 uint64_t rng_key(uint64_t seed, uint64_t step, uint64_t core, uint64_t kind) {
   const uint64_t tag = (step << 32) | (core << 16) | kind;
   return mix64(seed ^ mix64(tag));

@@ -176,4 +176,49 @@ hipError_t launch_wgram(const double* A, const double* w, int64_t rows, int d, d
 // K = G G^T for I slice-major rows of width d.
 hipError_t launch_row_gram(const double* G, int64_t I, int d, double* K, hipStream_t st);
 
+// ---- KSRFT-sketched variant (ksrft.hip) ------------------------------------
+
+// SplitMix64 output function (Steele, Lea & Flood, OOPSLA 2014).
+__host__ __device__ inline uint64_t mix64(uint64_t x) {
+  uint64_t z = x + 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+// n random signs (+1 / -1, FP64) of the stream `key`.
+hipError_t launch_signs(uint64_t key, int64_t n, double* out, hipStream_t st);
+
+// Mixing matrix of one mode (2I x mix_k_padded(I, pin), row-major, dtype
+// cdt) for a real (pin = 1) or complex (pin = 2, stacked planes) input.
+int mix_k_padded(int64_t I, int pin);
+hipError_t launch_mix_weights(int64_t I, int pin, const double* D, int cdt, void* W,
+                              hipStream_t st);
+// out (2 planes, dtype F64 for cdt F64, else F32) = W applied along a mode
+// of stride S and size I (C = product of the slower modes) of `in` (pin
+// planes of dtype idt, plane strides ips / ops elements).
+hipError_t launch_mix_mode(const void* in, int idt, int pin, int64_t ips, void* out,
+                           int64_t ops, int64_t S, int64_t I, int64_t C, const void* W, int cdt,
+                           hipStream_t st);
+// GS (2 planes of m x d) = sampled rows idx of the mixed core (F D) G.
+hipError_t launch_mix_slices(const double* G, int64_t I, int d, const double* D, const int* idx,
+                             int m, double* GS, hipStream_t st);
+// Complex sampled subchain rows of mode g.n from the sampled mixed slices
+// GS (device array of N pointers): Ast (2m x d), Bst (2m x 2d), w2 (2m).
+hipError_t launch_sample_rows_c(const Geom& g, const double* const* GS, int m, double w,
+                                int literal, double* Ast, double* Bst, double* w2,
+                                hipStream_t st);
+
+struct SgemmPlan {
+  int MT, mtiles, nsplit, kchunks, psize, nblk;
+};
+SgemmPlan plan_sgemm(const Geom& g, int m, int dB, int cdt);
+// part[split][i][c] = sum_k Xg[i][k] B[k][c] over stacked planes (see ksrft.hip).
+hipError_t launch_sgemm(const Geom& g, const SgemmPlan& p, int dB, int64_t pstride,
+                        const void* X, int cdt, const int* idxs, int m, const double* B,
+                        void* part, hipStream_t st);
+// dP (I x d) = Re(D F^* Z) for Z = [Re | Im] (I x 2d).
+hipError_t launch_unmix(const double* Z, int64_t I, int d, const double* D, double* dP,
+                        hipStream_t st);
+
 }  // namespace trk

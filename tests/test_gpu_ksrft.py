@@ -1,0 +1,148 @@
+"""GPU parity of rSTR-K (Alg. 9, KSRFT sketch) against the FP64 oracle.
+
+Both sides draw the same sample indices and the same random signs of the
+D_j from the counter-based generator, so the FP64 path is compared element
+by element: sample indices bit-exact, Re(P_n), Re(Q_n), the cores and the
+fit error within 1e-10 relative.  The GPU applies the unmixing D_n F_n^*
+after the sketched product instead of to the sampled fibres (the same
+linear map, associated differently), so FP64 agreement is at rounding
+level.  The FP32 and BF16 paths round the mixing and the sketched product
+(BF16: 8-bit significands, FP32 accumulation); their tolerances are the
+measured deviations with a margin, stated per test.
+"""
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import randomized as rs
+
+pytestmark = pytest.mark.gpu
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.ravel(a - b)) / max(np.linalg.norm(np.ravel(b)), 1e-300))
+
+
+def run_pair(P, X, init, t_init, t_new, nb, m, seed=11, dt="f64", literal=False, log=""):
+    o = rs.RSTR(X[..., :t_init], [G.copy() for G in init], m=m, sketch="ksrft", seed=seed,
+                temporal_literal=literal)
+    g = P.TRStream(X[..., :t_init], init, compute_dtype=dt, sketch="ksrft", sketch_size=m,
+                   seed=seed, temporal_literal=literal)
+    N = X.ndim
+    s0 = g.samples()
+    assert all(np.array_equal(s0[k], o.idxs[k]) for k in range(N)), "initial samples differ"
+    pq0 = 0.0
+    for n in range(N - 1):
+        Pg, Qg = g.PQ(n)
+        pq0 = max(pq0, rel(Pg, o.P[n].real), rel(Qg, o.Q[n].real))
+    worst = 0.0
+    for b in range(nb):
+        xb = X[..., t_init + b * t_new:t_init + (b + 1) * t_new]
+        o.update(xb)
+        g.update(xb)
+        T = t_init + (b + 1) * t_new
+        eo, eg = o.rel_error(X[..., :T]), g.reconstruct_error(X[..., :T])
+        worst = max(worst, abs(eg - eo) / eo)
+        sg = g.samples()
+        assert all(np.array_equal(sg[k], o.idxs[k]) for k in range(N)), \
+            f"samples differ after batch {b}"
+    out = dict(err_dev=worst, err=eg, err_oracle=eo, PQ_init=pq0)
+    out["cores"] = max(rel(a, b) for a, b in zip(g.cores(), o.cores))
+    pq = 0.0
+    for n in range(N - 1):
+        Pg, Qg = g.PQ(n)
+        pq = max(pq, rel(Pg, o.P[n].real), rel(Qg, o.Q[n].real))
+    out["PQ"] = pq
+    g.close()
+    print(f"[ksrft {log} {dt}{' literal' if literal else ''}] {out}", flush=True)
+    return out
+
+
+CASES = [
+    ((9, 8, 5), (2, 3, 2, 2), 6, 4, 2, 60),
+    ((10, 12), (2, 3, 2), 8, 5, 3, 40),
+    ((7, 6, 3, 4), (2, 2, 3, 2, 2), 5, 3, 2, 80),
+]
+
+
+def problem(dims, ranks, t_init, t_new, nb, noise=0.05, seed=5):
+    T = t_init + nb * t_new
+    cores, X = W.random_tr_problem(tuple(dims) + (T,), ranks, seed, noise=noise)
+    init = [G.copy() for G in cores]
+    init[-1] = init[-1][:, :t_init, :]
+    return cores, X, init
+
+
+@pytest.mark.parametrize("dims,ranks,t_init,t_new,nb,m", CASES)
+def test_ksrft_parity_f64(trlib, dims, ranks, t_init, t_new, nb, m):
+    _, X, init = problem(dims, ranks, t_init, t_new, nb)
+    init = W.perturb(init, 0.05, np.random.default_rng(1))
+    r = run_pair(trlib, X, init, t_init, t_new, nb, m, log=str(dims))
+    assert r["PQ_init"] < 1e-10
+    assert r["err_dev"] < 1e-10 and r["PQ"] < 1e-10 and r["cores"] < 1e-9
+
+
+def test_ksrft_literal_temporal_f64(trlib):
+    dims, ranks, t_init, t_new, nb, m = CASES[0]
+    _, X, init = problem(dims, ranks, t_init, t_new, nb)
+    init = W.perturb(init, 0.05, np.random.default_rng(2))
+    r = run_pair(trlib, X, init, t_init, t_new, nb, m, literal=True, log="literal")
+    assert r["err_dev"] < 1e-9 and r["PQ"] < 1e-9 and r["cores"] < 1e-8
+
+
+# deviation from the FP64 oracle: FP32 1.5e-7 fit error and 1.1e-7 P/Q
+# measured (bounds 1e-5, 1e-5); BF16 5.0e-3 fit error and 3.2e-3 P/Q
+# measured (bounds 2e-2, 2e-2), set by the 2^-9 unit roundoff of the mixed data
+LOWP_TOL = {"f32": (1e-5, 1e-5), "bf16": (2e-2, 2e-2)}
+
+
+@pytest.mark.parametrize("dt", ["f32", "bf16"])
+def test_ksrft_low_precision(trlib, dt):
+    dims, ranks, t_init, t_new, nb, m = CASES[0]
+    _, X, init = problem(dims, ranks, t_init, t_new, nb)
+    init = W.perturb(init, 0.05, np.random.default_rng(3))
+    r = run_pair(trlib, X, init, t_init, t_new, nb, m, dt=dt, log="lowp")
+    te, tp = LOWP_TOL[dt]
+    assert np.isfinite(r["err"]) and r["err_dev"] < te and r["PQ"] < tp
+
+
+@pytest.mark.parametrize("dt,tol", [("f64", 1e-10), ("f32", 1e-5), ("bf16", 5e-3)])
+def test_ksrft_exact_recovery(trlib, dt, tol):
+    """Noiseless TR data started from the true cores stays at the fixed point
+    (Alg. 9 keeps exact recovery for a full-rank sample set)."""
+    cores, X = W.random_tr_problem((12, 10, 20), (2, 3, 2), 4)
+    init = [G.copy() for G in cores]
+    init[-1] = init[-1][:, :8, :]
+    g = trlib.TRStream(X[..., :8], init, compute_dtype=dt, sketch="ksrft", sketch_size=60,
+                       seed=9)
+    for b in range(3):
+        g.update(X[..., 8 + 4 * b:12 + 4 * b])
+    e = g.reconstruct_error(X)
+    g.close()
+    print(f"[ksrft exact {dt}] {e}", flush=True)
+    assert e < tol
+
+
+@pytest.mark.parametrize("dt", ["f64", "bf16"])
+def test_ksrft_video_workload(trlib, dt):
+    """The 120 x 160 x 3 video-like stream (TR-ranks 12, batches of 20, m =
+    1440): two batches against the oracle.  Each spatial factor of the field
+    spans cosines of four frequencies (rank 8 < 12), so the initial Re(Q_n)
+    have cond about 2e9..5e9: two correct FP64 solvers then agree on the
+    cores and P/Q only to about cond * eps ~ 1e-6 (bound 1e-5), while the fit
+    error, the stated measure, agrees to 2e-10 (bound 1e-9).  In BF16 the
+    same conditioning lets the cores drift by a few percent along the near
+    null directions after the first solve, so the comparison is the fit error
+    (1.8e-4 measured, bound 5e-3) and P/Q at initialisation, before any solve
+    (1.6e-3 measured, bound 1e-2)."""
+    nb = 2
+    w = W.make("c4", T=60 + nb * 20)
+    T = w.t_init + nb * w.t_new
+    X = np.asfortranarray(w.X[..., :T])
+    r = run_pair(trlib, X, w.cores_init, w.t_init, w.t_new, nb, w.m, seed=w.sketch_seed, dt=dt,
+                 log="video")
+    if dt == "f64":
+        assert r["err_dev"] < 1e-9 and r["PQ"] < 1e-5 and r["cores"] < 1e-5
+    else:
+        assert np.isfinite(r["err"]) and r["err_dev"] < 5e-3 and r["PQ_init"] < 1e-2

@@ -129,6 +129,7 @@ class Workload:
     cores_true: list
     X: np.ndarray                # full stream, Fortran order
     cores_init: list = field(default_factory=list)
+    sketch_seed: int = 0         # key of the sample / sign generator
 
     @property
     def N(self):
@@ -181,6 +182,7 @@ def make(name, init_noise=1e-4, dims=None, T=None, t_init=None, t_new=None, R=No
             X = _add_noise(X0, np.multiply(e, s, out=e))
     X = np.asfortranarray(X)
     w = Workload(name, full, ranks, t_init, t_new, c["sketch"], c["m"], cores, X)
+    w.sketch_seed = 2307719 * 10 + cfg
     if t_init > 0:
         init = [G.copy() for G in cores]
         init[-1] = init[-1][:, :t_init, :]
