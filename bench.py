@@ -98,6 +98,78 @@ def run_gpu(w, X_dev, dtype, steps, warmup):
     return dict(wall_s=wall, event_ms=ev_ms, kinds=kinds, rel_err=err)
 
 
+def run_stream(name, dt, steps, warmup, sketch=None):
+    """Slices/s of the update on another configuration's stream (the sketched
+    variants use that configuration's m and seed)."""
+    import torch
+    import workloads as W
+    import paper_2307_00719_amd as P
+
+    c = W.CONFIGS[name]
+    T = c["t_init"] + (warmup + steps) * c["t_new"]
+    w = W.make(name, T=T)
+    sk = sketch if sketch is not None else w.sketch
+    sk = None if sk == "none" else sk
+    X_dev = torch.from_numpy(w.X).cuda()
+    stream = torch.cuda.Stream()
+    g = P.TRStream(X_dev[..., :w.t_init], w.cores_init, compute_dtype=dt, sketch=sk,
+                   sketch_size=w.m, seed=w.sketch_seed, max_slices=T,
+                   hip_stream=stream.cuda_stream)
+    for b in range(warmup):
+        g.update(X_dev[..., w.t_init + b * w.t_new:w.t_init + (b + 1) * w.t_new])
+    g.sync()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for b in range(warmup, warmup + steps):
+        g.update(X_dev[..., w.t_init + b * w.t_new:w.t_init + (b + 1) * w.t_new])
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    err = g.reconstruct_error(X_dev[..., :T])
+    g.close()
+    return {"workload": f"{'x'.join(map(str, w.dims[:-1]))} stream, TR-ranks {w.ranks[0]}, "
+                        f"batches of {w.t_new}" + (f", {sk} sketch m={w.m}" if sk else ""),
+            "dtype": dt, "slices_per_s": steps * w.t_new / (ms / 1e3),
+            "us_per_step": 1e3 * ms / steps, "steps": steps, "rel_fit_error": err}
+
+
+def run_fitloss(steps, warmup):
+    """Forward + backward of the TR fit loss on the 64^3 x 50 batch, TR-ranks
+    16, FP32, at the perturbed-truth evaluation point."""
+    import numpy as np
+    import torch
+    import workloads as W
+    import paper_2307_00719_amd as P
+
+    w = W.make("c5")
+    X = torch.from_numpy(np.asarray(w.X, dtype=np.float32)).cuda()
+    cores = [torch.from_numpy(G.astype(np.float32)).cuda().requires_grad_(True)
+             for G in W.c5_point(w)]
+
+    def once():
+        for G in cores:
+            G.grad = None
+        loss = P.tr_fit_loss(X, cores)
+        loss.backward()
+        return loss
+
+    for _ in range(warmup):
+        once()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        once()
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    flop = 4 * 2.0 * X.numel() * 16 * 16          # the four MTTKRPs of the backward
+    return {"workload": "64x64x64x50 batch, TR-ranks 16, loss + core gradients",
+            "dtype": "f32", "us_per_eval": 1e3 * ms, "slices_per_s": 50 / (ms / 1e3),
+            "mttkrp_tflops_lower_bound": flop / (ms * 1e-3) / 1e12,
+            "mttkrp_frac_lower_bound": flop / (ms * 1e-3) / PEAK["f32"], "steps": steps}
+
+
 def cpu_baseline(w, budget_s):
     """The FP64 oracle on the host: STR over as many batches as fit the
     budget (at least 2)."""
@@ -130,6 +202,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the other workloads (sketched variants, order 4, fit loss)")
+    ap.add_argument("--extra-steps", type=int, default=10)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the streaming update is built and timed on a "
@@ -191,6 +266,20 @@ def main():
             "mttkrp_avg_us": res["f32"]["kinds"]["mttkrp"]["avg_us"]},
         "wall_s_timed_region": r["wall_s"],
     }
+    if not args.no_extra:
+        extra = {}
+        for key, name, dt, sk in [("rstr_uniform_f32", "c3", "f32", "uniform"),
+                                  ("rstr_leverage_f32", "c3", "f32", "leverage"),
+                                  ("rstr_ksrft_bf16", "c4", "bf16", "ksrft"),
+                                  ("rstr_ksrft_f64", "c4", "f64", "ksrft"),
+                                  ("str_f32_order4", "c3", "f32", "none")]:
+            extra[key] = run_stream(name, dt, args.extra_steps, 3, sketch=sk)
+            print(f"[bench] {key}: {extra[key]['us_per_step']:.1f} us/step", file=sys.stderr,
+                  flush=True)
+        extra["fit_loss_f32"] = run_fitloss(args.extra_steps, 2)
+        print(f"[bench] fit_loss_f32: {extra['fit_loss_f32']['us_per_eval']:.1f} us/eval",
+              file=sys.stderr, flush=True)
+        out["other_workloads"] = extra
     if not args.no_cpu:
         cb = cpu_baseline(w, args.cpu_budget)
         out["cpu_baseline"] = {k: cb[k] for k in ("value", "unit", "cores", "kind", "sample")}
