@@ -49,7 +49,7 @@ struct tr_stream {
   double* chain[2] = {};
   hipStream_t side = nullptr;  // second stream: Gram refresh, chain, inverse
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
-  hipEvent_t ev_inv[MAXN] = {}, ev_rs[MAXN] = {};
+  hipEvent_t ev_inv[MAXN] = {}, ev_rs[MAXN] = {};  // MTTKRP done (main), solve done (side)
   void* xcast = nullptr;
   size_t xcast_bytes = 0;
   double* xf64 = nullptr;
@@ -839,10 +839,12 @@ tr_status tr_stream_update(tr_stream* s, const void* X_new, int32_t x_dtype, int
     s->t_total += t_new;
     return TR_OK;
   }
-  // Two streams: main (s->st) runs MTTKRP -> reduce+solve per mode; side
-  // runs one fused kernel per mode (Gram refresh of the core updated just
-  // before, Gram chain, Q update, inverse), which does not depend on the
-  // mode's MTTKRP.  Events order every cross-stream dependency.
+  // Two streams.  The side stream carries the serial chain of the step: per
+  // mode one fused kernel (Gram refresh of the core updated just before,
+  // Gram chain, Q update, inverse) and then the split reduction + solve.
+  // The caller's stream runs the MTTKRPs, each after the solve of the mode
+  // before it; a solve waits for its mode's MTTKRP, which has usually
+  // finished by then, so no cross-stream wait sits on the chain.
   hipStream_t side = s->side;
   const long pstep = prof_begin(s, PK_STEP);
   long pr;
@@ -873,54 +875,40 @@ tr_status tr_stream_update(tr_stream* s, const void* X_new, int32_t x_dtype, int
     a.status = s->dstatus;
     return a;
   };
-  // temporal mode: G_N^new = X_[N]^new G^{!=N}_[2] (H^{!=N}_<2>)^+ (Alg. 4);
-  // its side kernel also refreshes Z_{N-1} of the previous step's last core
-  {
+  // modes in order: temporal (its side kernel also refreshes Z_{N-1} of the
+  // previous step's last core), then n = 0..N-2 (mode n's side kernel
+  // refreshes the Gram of the core updated just before it; Z_N^new for n = 0)
+  for (int j = 0; j < N; ++j) {
+    const int n = j == 0 ? N - 1 : j - 1;
+    const bool temporal = n == N - 1;
     pr = prof_begin(s, PK_CHAIN, side);
-    TR_HIP(launch_side(side_args(N - 1, N - 2, s->G[N - 2], s->I[N - 2]), side));
-    prof_end(s, pr, side);
-    TR_HIP(hipEventRecord(s->ev_inv[N - 1], side));
-    Geom g = make_geom(N, gd.data(), s->R, N - 1);
-    MttkrpPlan p = plan_mttkrp(g, s->dt);
-    c = ensure_partials(s, g, p);
-    if (c != TR_OK) return c;
-    const CoreView cv = state_view(s, Gnew);
-    pr = prof_begin(s, PK_MTT_T);
-    TR_HIP(launch_mttkrp(g, p, Xd, s->dt, cv, F64, s->part, s->st));
-    prof_end(s, pr);
-    TR_HIP(hipStreamWaitEvent(s->st, s->ev_inv[N - 1], 0));
-    pr = prof_begin(s, PK_SOLVE);
-    TR_HIP(launch_reduce_solve(s->part, p.psize, p.nsplit, g.In, g.d, nullptr, 0,
-                               s->MinvM[N - 1], Gnew, s->st));
-    prof_end(s, pr);
-    TR_HIP(hipEventRecord(s->ev_rs[N - 1], s->st));
-  }
-  // non-temporal modes, in order (Alg. 4); mode n's side kernel refreshes the
-  // Gram of the core updated just before it (Z_N^new for n = 0)
-  for (int n = 0; n < N - 1; ++n) {
-    const int pidx = n == 0 ? N - 1 : n - 1;
-    TR_HIP(hipStreamWaitEvent(side, s->ev_rs[pidx], 0));
-    pr = prof_begin(s, PK_CHAIN, side);
-    if (n == 0)
+    if (temporal)
+      TR_HIP(launch_side(side_args(N - 1, N - 2, s->G[N - 2], s->I[N - 2]), side));
+    else if (n == 0)
       TR_HIP(launch_side(side_args(0, N - 1, Gnew, t_new), side));
     else
       TR_HIP(launch_side(side_args(n, n - 1, s->G[n - 1], s->I[n - 1]), side));
     prof_end(s, pr, side);
-    TR_HIP(hipEventRecord(s->ev_inv[n], side));
+    if (!temporal) TR_HIP(hipStreamWaitEvent(s->st, s->ev_rs[n == 0 ? N - 1 : n - 1], 0));
     Geom g = make_geom(N, gd.data(), s->R, n);
     MttkrpPlan p = plan_mttkrp(g, s->dt);
     c = ensure_partials(s, g, p);
     if (c != TR_OK) return c;
     const CoreView cv = state_view(s, Gnew);
-    pr = prof_begin(s, PK_MTT_N);
+    pr = prof_begin(s, temporal ? PK_MTT_T : PK_MTT_N);
     TR_HIP(launch_mttkrp(g, p, Xd, s->dt, cv, F64, s->part, s->st));
     prof_end(s, pr);
-    TR_HIP(hipStreamWaitEvent(s->st, s->ev_inv[n], 0));
-    pr = prof_begin(s, PK_SOLVE);
-    TR_HIP(launch_reduce_solve(s->part, p.psize, p.nsplit, g.In, g.d, s->P[n], 1, s->MinvM[n],
-                               s->G[n], s->st));
-    prof_end(s, pr);
-    TR_HIP(hipEventRecord(s->ev_rs[n], s->st));
+    TR_HIP(hipEventRecord(s->ev_inv[n], s->st));
+    TR_HIP(hipStreamWaitEvent(side, s->ev_inv[n], 0));
+    pr = prof_begin(s, PK_SOLVE, side);
+    if (temporal)
+      TR_HIP(launch_reduce_solve(s->part, p.psize, p.nsplit, g.In, g.d, nullptr, 0,
+                                 s->MinvM[N - 1], Gnew, side));
+    else
+      TR_HIP(launch_reduce_solve(s->part, p.psize, p.nsplit, g.In, g.d, s->P[n], 1,
+                                 s->MinvM[n], s->G[n], side));
+    prof_end(s, pr, side);
+    TR_HIP(hipEventRecord(s->ev_rs[n], side));
   }
   TR_HIP(hipEventRecord(s->ev_join, side));
   TR_HIP(hipStreamWaitEvent(s->st, s->ev_join, 0));
