@@ -152,7 +152,7 @@ def run_fitloss(steps, warmup):
     import numpy as np
     import torch
     import workloads as W
-    import paper_2307_00719_amd as P
+    from paper_2307_00719_amd import autograd as PA
 
     w = W.make("c5")
     X = torch.from_numpy(np.asarray(w.X, dtype=np.float32)).cuda()
@@ -162,7 +162,7 @@ def run_fitloss(steps, warmup):
     def once():
         for G in cores:
             G.grad = None
-        loss = P.tr_fit_loss(X, cores)
+        loss = PA.tr_fit_loss(X, cores)
         loss.backward()
         return loss
 

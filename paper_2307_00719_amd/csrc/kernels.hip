@@ -236,9 +236,9 @@ __device__ inline int64_t outer_offset(const Geom& g, int64_t o) {
 // in FP64 and the result accumulated over the chunk.
 // ---------------------------------------------------------------------------
 template <typename T, typename TC, int NJ>
-__global__ __launch_bounds__(256, 2) void k_mttkrp(Geom g, MttkrpPlan p, const T* __restrict__ X,
-                                                   CoreView cv,
-                                                   typename Acc<T>::type* __restrict__ part) {
+__device__ inline void mttkrp_body(const Geom& g, const MttkrpPlan& p, const T* __restrict__ X,
+                                   const CoreView& cv, typename Acc<T>::type* __restrict__ part,
+                                   int chunk, int mtile, char* smem) {
   typedef typename Acc<T>::type PT;
   typedef typename Acc<T>::vec V4;
   constexpr int KG = 8;                     // k-steps whose loads are issued together
@@ -260,7 +260,6 @@ __global__ __launch_bounds__(256, 2) void k_mttkrp(Geom g, MttkrpPlan p, const T
   const int qV = f + 1 == N ? 0 : f + 1;
   const int wst = 16 * ((Rn1 * Rf1 + 15) / 16);
 
-  extern __shared__ __align__(16) char smem[];
   double* Us = (double*)smem;               // [16][16]
   double* Vs = Us + 256;                    // [16][16]
   double* tmp = Vs + 256;                   // [256]
@@ -269,8 +268,8 @@ __global__ __launch_bounds__(256, 2) void k_mttkrp(Geom g, MttkrpPlan p, const T
   PT* Ys = (PT*)(Ws + 16 * wst);            // [16][dfp]
   PT* red = Ys + 16 * dfp;                  // [KS-1][16][dfp]
 
-  const int64_t m0 = (int64_t)blockIdx.y * 16;
-  const int64_t o0 = (int64_t)blockIdx.x * p.upw;
+  const int64_t m0 = (int64_t)mtile * 16;
+  const int64_t o0 = (int64_t)chunk * p.upw;
   const int64_t o1 = o0 + p.upw < p.Kout ? o0 + p.upw : p.Kout;
   const TC* __restrict__ Gf = (const TC*)cv.ptr[f];
   // 32-bit element offsets: the launcher checks that X spans of one outer
@@ -380,8 +379,16 @@ __global__ __launch_bounds__(256, 2) void k_mttkrp(Geom g, MttkrpPlan p, const T
   }
   for (int e = tid; e < 16 * dn; e += 256) {
     const int m = e / dn;
-    if (m0 + m < g.In) part[((size_t)blockIdx.x * g.In + m0) * dn + e] = (PT)Pa[e];
+    if (m0 + m < g.In) part[((size_t)chunk * g.In + m0) * dn + e] = (PT)Pa[e];
   }
+}
+
+template <typename T, typename TC, int NJ>
+__global__ __launch_bounds__(256, 2) void k_mttkrp(Geom g, MttkrpPlan p, const T* __restrict__ X,
+                                                   CoreView cv,
+                                                   typename Acc<T>::type* __restrict__ part) {
+  extern __shared__ __align__(16) char smem[];
+  mttkrp_body<T, TC, NJ>(g, p, X, cv, part, blockIdx.x, blockIdx.y, smem);
 }
 
 template <typename T, typename TC, int NJ>
@@ -955,7 +962,10 @@ __device__ inline bool wave_gj16(d4& c, int lane, double tol, int nvalid) {
 #pragma unroll
     for (int v = 0; v < 4; ++v) colp[v] = __shfl(c[v], (r0 << 4) | p, 64);  // T[i][p]
     if (p < nvalid && !(piv > tol)) bad = true;
-    const double ip = 1.0 / piv;
+    // 1/piv: hardware reciprocal refined by two Newton steps
+    double ip = __builtin_amdgcn_rcp(piv);
+    ip = fma(fma(-piv, ip, 1.0), ip, ip);
+    ip = fma(fma(-piv, ip, 1.0), ip, ip);
     const double rs = rowp * ip;
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
@@ -976,126 +986,62 @@ __device__ inline bool wave_gj16(d4& c, int lane, double tol, int nvalid) {
 // two MTTKRP workgroups running beside it).
 constexpr int SIDE_LDS = 8192;
 
-template <int MAXT>
-__global__ __launch_bounds__(1024) void k_side_mf(SideArgs sa) {
-  extern __shared__ double lds[];
-  __shared__ double dmax[16];
-  const int tid = threadIdx.x;
+// Serial part of the side step, for a workgroup of NW waves: the ring
+// product of the transfer-layout factors, the Q tiles (assembly,
+// accumulation, store) and the blocked Gauss-Jordan inverse.  MAXT >=
+// ceil(nb^2 / NW) tiles per wave.
+template <int NW, int MAXT>
+__device__ inline void side_serial(const SideArgs& sa, double* lds, double* dmax, int tid) {
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
   const int ar = lane & 15, ak = lane >> 4;
-  // 1. Gram of the previous core, written in the transfer layout.  Rows are
-  //    staged through LDS in chunks of CR rows (every load of a chunk in
-  //    flight at once, the next chunk prefetched into registers while the
-  //    current one is multiplied); up to 4 output tiles per wave and pass.
-  if (sa.Gp) {
-    const int Ra = sa.Rpa, Rb = sa.Rpb, dp = Ra * Rb;
-    const int nbp = (dp + 15) >> 4, ntp = nbp * nbp;
-    const int64_t rows = sa.rows_p;
-    const int CR = (SIDE_LDS / dp) & ~3;
-    const int64_t nchunk = (rows + CR - 1) / CR;
-    constexpr int PER = SIDE_LDS / 1024;
-    const double* __restrict__ Gp = sa.Gp;
-    for (int t0 = 0; t0 < ntp; t0 += 64) {
-      d4 acc[4];
-#pragma unroll
-      for (int s = 0; s < 4; ++s) acc[s] = d4{0, 0, 0, 0};
-      double pre[PER];
-      // the address is clamped independently of the mask so that every load
-      // of the chunk is issued unconditionally
-      const int64_t tot = rows * dp;
-      auto fetch = [&](int64_t c) {
-        const int64_t base = c * CR * dp;
-        const int64_t lim = (rows - c * CR < CR ? rows - c * CR : CR) * dp;
-#pragma unroll
-        for (int q = 0; q < PER; ++q) {
-          const int e = tid + 1024 * q;
-          const double x = Gp[min(base + e, tot - 1)];
-          pre[q] = e < lim ? x : 0.0;
-        }
-      };
-      if (nchunk > 0) fetch(0);
-      for (int64_t c = 0; c < nchunk; ++c) {
-#pragma unroll
-        for (int q = 0; q < PER; ++q) lds[tid + 1024 * q] = pre[q];
-        __syncthreads();
-        if (c + 1 < nchunk) fetch(c + 1);
-        const int64_t crow = rows - c * CR < CR ? rows - c * CR : CR;
-        const int kend = (int)((crow + 3) & ~3);
-#pragma unroll
-        for (int s = 0; s < 4; ++s) {
-          const int t = t0 + wave + 16 * s;
-          if (t < ntp) {
-            const int rb = t / nbp, cb = t - rb * nbp;
-            const int c1 = min(rb * 16 + ar, dp - 1), c2 = min(cb * 16 + ar, dp - 1);
-            d4 a = acc[s];
-#pragma unroll 8
-            for (int k0 = 0; k0 < kend; k0 += 4) {
-              const int i = k0 + ak;
-              a = mfma16(lds[i * dp + c1], lds[i * dp + c2], a);
-            }
-            acc[s] = a;
-          }
-        }
-        __syncthreads();
-      }
-#pragma unroll
-      for (int s = 0; s < 4; ++s) {
-        const int t = t0 + wave + 16 * s;
-        if (t < ntp) {
-          const int rb = t / nbp, cb = t - rb * nbp;
-#pragma unroll
-          for (int v = 0; v < 4; ++v) {
-            const int r = rb * 16 + Acc<double>::row(lane, v), c = cb * 16 + ar;
-            if (r < dp && c < dp) {
-              const int a1 = r % Ra, b1 = r / Ra, a2 = c % Ra, b2 = c / Ra;
-              sa.Ep[(size_t)(a1 + Ra * a2) * (Rb * Rb) + (b1 + Rb * b2)] = acc[s][v];
-            }
-          }
-        }
-      }
-    }
-    __syncthreads();
-  }
   // 2. ring product of the transfer-layout factors: both operands staged in
-  //    LDS when they fit, else read through the cache in batches of 8 k-steps.
+  //    LDS when they fit (the left factor column-major, so the 16 lanes of
+  //    an operand read consecutive words), else read through the cache in
+  //    batches of 8 k-steps.  When the last product has at most 16 tiles it
+  //    is kept in LDS for the assembly.
   const double* M = sa.fac[0] ? sa.fac[0] : sa.Ep;
   for (int j = 1; j < sa.nfac; ++j) {
     const double* __restrict__ F = sa.fac[j] ? sa.fac[j] : sa.Ep;
     double* out = sa.cbuf[(j - 1) & 1];
     const int d1 = sa.fr[0], d2 = sa.fc[j - 1], d3 = sa.fc[j];
-    const int nb1 = (d1 + 15) >> 4, nb3 = (d3 + 15) >> 4;
+    const int nb1 = (d1 + 15) >> 4, nb3 = (d3 + 15) >> 4, ntile = nb1 * nb3;
     const bool staged = d1 * d2 + d2 * d3 <= SIDE_LDS;
     if (staged) {
-      // [M | F] copied to LDS with all loads in flight at once
+      // [M^T | F] copied to LDS with all loads in flight at once
       const int n1 = d1 * d2, n2 = d2 * d3;
-      constexpr int PER = SIDE_LDS / 1024;
+      constexpr int PER = SIDE_LDS / (64 * NW);
       double x[PER];
 #pragma unroll
       for (int q = 0; q < PER; ++q) {
-        const int e = tid + 1024 * q;
+        const int e = tid + 64 * NW * q;
         const double a = M[min(e, n1 - 1)];
         const double b = F[min(max(e - n1, 0), n2 - 1)];
         x[q] = e < n1 ? a : b;
       }
 #pragma unroll
       for (int q = 0; q < PER; ++q) {
-        const int e = tid + 1024 * q;
-        if (e < n1 + n2) lds[e] = x[q];
+        const int e = tid + 64 * NW * q;
+        if (e < n1) {
+          const int r = e / d2;
+          lds[(e - r * d2) * d1 + r] = x[q];
+        } else if (e < n1 + n2) {
+          lds[n1 + (e - n1)] = x[q];
+        }
       }
       __syncthreads();
     }
-    for (int b = wave; b < nb1 * nb3; b += 16) {
+    auto tile_mm = [&](int b) -> d4 {
       const int rb = b / nb3, cb = b - rb * nb3;
       const int arow = min(rb * 16 + ar, d1 - 1), bcol = min(cb * 16 + ar, d3 - 1);
       d4 acc = {0, 0, 0, 0};
       const int kfull = d2 & ~3;
       if (staged) {
-        const double* Ms = lds;
+        const double* MsT = lds;
         const double* Fs = lds + d1 * d2;
 #pragma unroll 8
         for (int k0 = 0; k0 < kfull; k0 += 4) {
           const int k = k0 + ak;
-          acc = mfma16(Ms[arow * d2 + k], Fs[k * d3 + bcol], acc);
+          acc = mfma16(MsT[k * d1 + arow], Fs[k * d3 + bcol], acc);
         }
       } else {
         int k0 = 0;
@@ -1119,18 +1065,42 @@ __global__ __launch_bounds__(1024) void k_side_mf(SideArgs sa) {
         // ragged last k-step: lanes past d2 contribute zeros
         const int k = kfull + ak;
         const int kc = min(k, d2 - 1);
-        const double av = staged ? lds[arow * d2 + kc] : M[(size_t)arow * d2 + kc];
+        const double av = staged ? lds[kc * d1 + arow] : M[(size_t)arow * d2 + kc];
         const double bv = staged ? lds[d1 * d2 + kc * d3 + bcol] : F[(size_t)kc * d3 + bcol];
         acc = mfma16(k < d2 ? av : 0.0, k < d2 ? bv : 0.0, acc);
       }
+      return acc;
+    };
+    auto store_tile = [&](int b, const d4& acc, double* dst) {
+      const int rb = b / nb3, cb = b - rb * nb3;
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int r = rb * 16 + Acc<double>::row(lane, v), c = cb * 16 + ar;
-        if (r < d1 && c < d3) out[(size_t)r * d3 + c] = acc[v];
+        if (r < d1 && c < d3) dst[(size_t)r * d3 + c] = acc[v];
       }
+    };
+    constexpr int RM = (16 + NW - 1) / NW;
+    if (ntile <= NW * RM) {
+      const bool keep = j == sa.nfac - 1 && d1 * d3 <= SIDE_LDS;
+      d4 res[RM];
+#pragma unroll
+      for (int t = 0; t < RM; ++t) {
+        const int b = wave + NW * t;
+        res[t] = b < ntile ? tile_mm(b) : d4{0, 0, 0, 0};
+      }
+      __syncthreads();
+#pragma unroll
+      for (int t = 0; t < RM; ++t) {
+        const int b = wave + NW * t;
+        if (b < ntile) store_tile(b, res[t], keep ? lds : out);
+      }
+      __syncthreads();
+      M = keep ? lds : out;
+    } else {
+      for (int b = wave; b < ntile; b += NW) store_tile(b, tile_mm(b), out);
+      __syncthreads();
+      M = out;
     }
-    __syncthreads();
-    M = out;
   }
   // 3. Q tiles: assembly from the chain product, accumulation, store
   const int Ra = sa.Ra, Rb = sa.Rb, d = Ra * Rb;
@@ -1139,7 +1109,7 @@ __global__ __launch_bounds__(1024) void k_side_mf(SideArgs sa) {
   double mx = 0.0;
 #pragma unroll
   for (int s = 0; s < MAXT; ++s) {
-    const int t = wave + 16 * s;
+    const int t = wave + NW * s;
     d4 x = {0, 0, 0, 0};
     if (t < ntile) {
       const int ti = t / nb, tj = t - ti * nb;
@@ -1168,7 +1138,7 @@ __global__ __launch_bounds__(1024) void k_side_mf(SideArgs sa) {
   __syncthreads();
   mx = 0.0;
 #pragma unroll
-  for (int w = 0; w < 16; ++w) mx = fmax(mx, dmax[w]);
+  for (int w = 0; w < NW; ++w) mx = fmax(mx, dmax[w]);
   const double tol = (double)d * 2.220446049250313e-16 * mx;
   // 4. blocked Gauss-Jordan, LDS double-buffered per pivot block:
   //    Pb = P (row-major), PbT = P^T, RowB[j] = A_Kj (row-major),
@@ -1184,7 +1154,7 @@ __global__ __launch_bounds__(1024) void k_side_mf(SideArgs sa) {
     double* ColT = RowB + nb * 256;
 #pragma unroll
     for (int s = 0; s < MAXT; ++s) {
-      const int t = wave + 16 * s;
+      const int t = wave + NW * s;
       if (t < ntile) {
         const int ti = t / nb, tj = t - ti * nb;
         if (ti == K && tj == K) {
@@ -1209,7 +1179,7 @@ __global__ __launch_bounds__(1024) void k_side_mf(SideArgs sa) {
     __syncthreads();
 #pragma unroll
     for (int s = 0; s < MAXT; ++s) {
-      const int t = wave + 16 * s;
+      const int t = wave + NW * s;
       if (t < ntile) {
         const int ti = t / nb, tj = t - ti * nb;
         if (ti == K && tj == K) {
@@ -1255,7 +1225,7 @@ __global__ __launch_bounds__(1024) void k_side_mf(SideArgs sa) {
   }
 #pragma unroll
   for (int s = 0; s < MAXT; ++s) {
-    const int t = wave + 16 * s;
+    const int t = wave + NW * s;
     if (t < ntile) {
       const int ti = t / nb, tj = t - ti * nb;
 #pragma unroll
@@ -1268,6 +1238,187 @@ __global__ __launch_bounds__(1024) void k_side_mf(SideArgs sa) {
   if (bad && lane == 0 && sa.status) sa.status[0] = 1;
 }
 
+// One upper-triangle 16x16 tile (index `tile`, row-major over the upper
+// triangle) of G_(2)^T G_(2) of the previous core: the rows are split over
+// the NW waves (8 k-steps of loads in flight per wave), the partial tiles
+// summed in LDS in a fixed order, and the tile and its mirror written in the
+// transfer layout.
+template <int NW>
+__device__ inline void gram_tile(const SideArgs& sa, double* lds, int tid, int tile) {
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
+  const int ar = lane & 15, ak = lane >> 4;
+  const int Ra = sa.Rpa, Rb = sa.Rpb, dp = Ra * Rb;
+  const int nbp = (dp + 15) >> 4;
+  int rb = 0, cb = tile;
+  while (cb >= nbp - rb) {
+    cb -= nbp - rb;
+    ++rb;
+  }
+  cb += rb;
+  const int64_t rows = sa.rows_p, rl = rows > 0 ? rows - 1 : 0;
+  const int64_t nks = (rows + 3) / 4;
+  const double* __restrict__ Gp = sa.Gp;
+  const int c1 = min(rb * 16 + ar, dp - 1), c2 = min(cb * 16 + ar, dp - 1);
+  d4 acc = {0, 0, 0, 0};
+  for (int64_t k0 = wave; k0 < nks; k0 += 8 * NW) {
+    double av[8], bv[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int64_t ks = k0 + NW * q;
+      const int64_t i = ks * 4 + ak;
+      const int64_t ic = i < rows ? i : rl;
+      const double xa = Gp[ic * dp + c1], xb = Gp[ic * dp + c2];
+      const bool ok = i < rows && ks < nks;
+      av[q] = ok ? xa : 0.0;
+      bv[q] = ok ? xb : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < 8; ++q) acc = mfma16(av[q], bv[q], acc);
+  }
+#pragma unroll
+  for (int v = 0; v < 4; ++v) lds[wave * 256 + Acc<double>::row(lane, v) * 16 + ar] = acc[v];
+  __syncthreads();
+  for (int e = tid; e < 256; e += 64 * NW) {
+    double sum = 0.0;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) sum += lds[w * 256 + e];
+    const int r = rb * 16 + (e >> 4), c = cb * 16 + (e & 15);
+    if (r < dp && c < dp) {
+      const int a1 = r % Ra, b1 = r / Ra, a2 = c % Ra, b2 = c / Ra;
+      sa.Ep[(size_t)(a1 + Ra * a2) * (Rb * Rb) + (b1 + Rb * b2)] = sum;
+      sa.Ep[(size_t)(a2 + Ra * a1) * (Rb * Rb) + (b2 + Rb * b1)] = sum;
+    }
+  }
+}
+
+// Arrival of a Gram workgroup: release its tile, count it in; true for the
+// last of `total` to arrive (which also resets the counter and acquires the
+// other tiles).
+__device__ inline bool gram_arrive(unsigned* counter, unsigned total, int tid) {
+  __shared__ int sh_last;
+  __threadfence();
+  __syncthreads();
+  if (tid == 0) sh_last = atomicAdd(counter, 1u) == total - 1;
+  __syncthreads();
+  if (!sh_last) return false;
+  __threadfence();
+  if (tid == 0) *counter = 0u;
+  return true;
+}
+
+template <int MAXT>
+__global__ __launch_bounds__(1024) void k_side_mf(SideArgs sa) {
+  extern __shared__ double lds[];
+  __shared__ double dmax[16];
+  const int tid = threadIdx.x;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
+  const int ar = lane & 15, ak = lane >> 4;
+  // 1. Gram of the previous core, spread over the grid (one upper-triangle
+  //    tile per workgroup); the last workgroup to finish goes on with the
+  //    chain, Q and the inverse while the others exit.
+  if (sa.Gp) {
+    gram_tile<16>(sa, lds, tid, blockIdx.x);
+    if (!gram_arrive(sa.counter, gridDim.x, tid)) return;
+  }
+  side_serial<16, MAXT>(sa, lds, dmax, tid);
+}
+
+// ---------------------------------------------------------------------------
+// One mode of the STR update in one launch (Alg. 4): the first workgroups
+// each form one upper-triangle tile of the Gram of the core updated just
+// before, and the last of them to finish runs the rest of the side step
+// (Gram chain, Q update, inverse) with its 4 waves; every other workgroup
+// runs one MTTKRP tile.  The side step and the MTTKRP do not read what the
+// other writes, and no workgroup waits for another; the split reduction and
+// solve follow on the same stream.
+// ---------------------------------------------------------------------------
+template <typename T, typename TC, int NJ, int MAXT>
+__global__ __launch_bounds__(256, 2) void k_mode(Geom g, MttkrpPlan p, const T* __restrict__ X,
+                                                 CoreView cv,
+                                                 typename Acc<T>::type* __restrict__ part,
+                                                 SideArgs sa) {
+  extern __shared__ __align__(16) char smem[];
+  __shared__ double dmax[4];
+  const int nbp = (sa.Rpa * sa.Rpb + 15) >> 4;
+  const int ngram = sa.Gp ? nbp * (nbp + 1) / 2 : 1;
+  if ((int)blockIdx.x < ngram) {
+    // the side step is the longer chain: its waves take issue priority over
+    // the MTTKRP waves sharing the compute unit
+    __builtin_amdgcn_s_setprio(3);
+    double* lds = (double*)smem;
+    if (sa.Gp) {
+      gram_tile<4>(sa, lds, threadIdx.x, blockIdx.x);
+      if (!gram_arrive(sa.counter, (unsigned)ngram, threadIdx.x)) return;
+    }
+    side_serial<4, MAXT>(sa, lds, dmax, threadIdx.x);
+    return;
+  }
+  const int w = blockIdx.x - ngram;
+  mttkrp_body<T, TC, NJ>(g, p, X, cv, part, w % p.nsplit, w / p.nsplit, smem);
+}
+
+bool mode_fusable(const Geom& g, const SideArgs& sa) {
+  return sa.Ra * sa.Rb <= 64 && g.d <= 64;
+}
+
+template <typename T, int NJ, int MAXT>
+static hipError_t launch_mode_t(const Geom& g, const MttkrpPlan& p, const void* X,
+                                const CoreView& cv, void* part, const SideArgs& sa,
+                                hipStream_t st) {
+  typedef typename Acc<T>::type PT;
+  const int dfp = 16 * p.nbf;
+  const int Rn1 = g.R[(g.n + 1) % g.N], Rf1 = g.R[(p.f + 1) % g.N];
+  const int wst = 16 * ((Rn1 * Rf1 + 15) / 16);
+  const size_t lmt = (size_t)(3 * 256 + 16 * g.d + 16 * wst) * sizeof(double) +
+                     (size_t)(16 * dfp) * p.KS * sizeof(PT);
+  const size_t lds = std::max(lmt, (size_t)SIDE_LDS * sizeof(double));
+  auto fn = k_mode<T, double, NJ, MAXT>;
+  if (lds > 65536) {
+    hipError_t e = hipFuncSetAttribute((const void*)fn,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  const int nbp = (sa.Rpa * sa.Rpb + 15) / 16;
+  const unsigned ngram = sa.Gp ? (unsigned)(nbp * (nbp + 1) / 2) : 1u;
+  const unsigned grid = ngram + (unsigned)p.nsplit * (unsigned)p.mtiles;
+  hipLaunchKernelGGL(fn, dim3(grid), dim3(256), lds, st, g, p, (const T*)X, cv,
+                     (typename Acc<T>::type*)part, sa);
+  return hipGetLastError();
+}
+
+template <typename T, int MAXT>
+static hipError_t launch_mode_j(const Geom& g, const MttkrpPlan& p, const void* X,
+                                const CoreView& cv, void* part, const SideArgs& sa,
+                                hipStream_t st) {
+  const int nj = (p.nbf + 4 / p.KS - 1) / (4 / p.KS);
+  switch (nj) {
+    case 1: return launch_mode_t<T, 1, MAXT>(g, p, X, cv, part, sa, st);
+    case 2: return launch_mode_t<T, 2, MAXT>(g, p, X, cv, part, sa, st);
+    case 3: return launch_mode_t<T, 3, MAXT>(g, p, X, cv, part, sa, st);
+    default: return launch_mode_t<T, 4, MAXT>(g, p, X, cv, part, sa, st);
+  }
+}
+
+hipError_t launch_mode(const Geom& g, const MttkrpPlan& p, const void* X, int xdt,
+                       const CoreView& cv, int cdt, void* part, const SideArgs& sa,
+                       hipStream_t st) {
+  if (cdt != F64 || !mode_fusable(g, sa)) return hipErrorInvalidValue;
+  const int f = p.f;
+  const int64_t xspan = (g.In - 1) * p.sm + (g.I[f] - 1) * p.sf + 1;
+  const int64_t gspan = (g.I[f] - 1) * cv.si[f] + (g.R[f] - 1) * cv.sr[f] +
+                        (g.R[(f + 1) % g.N] - 1) * cv.ss[f] + 1;
+  if (xspan >= ((int64_t)1 << 31) || gspan >= ((int64_t)1 << 31)) return hipErrorInvalidValue;
+  const int nb = (sa.Ra * sa.Rb + 15) / 16;
+  const bool small = nb * nb <= 4;
+  if (xdt == F64)
+    return small ? launch_mode_j<double, 1>(g, p, X, cv, part, sa, st)
+                 : launch_mode_j<double, 4>(g, p, X, cv, part, sa, st);
+  if (xdt == F32)
+    return small ? launch_mode_j<float, 1>(g, p, X, cv, part, sa, st)
+                 : launch_mode_j<float, 4>(g, p, X, cv, part, sa, st);
+  return hipErrorInvalidValue;
+}
+
 template <int MAXT>
 static hipError_t launch_side_mf(const SideArgs& a, int nb, hipStream_t st) {
   const size_t lds = (size_t)SIDE_LDS * sizeof(double);
@@ -1277,7 +1428,12 @@ static hipError_t launch_side_mf(const SideArgs& a, int nb, hipStream_t st) {
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL(fn, dim3(1), dim3(1024), lds, st, a);
+  unsigned grid = 1;
+  if (a.Gp) {
+    const int nbp = (a.Rpa * a.Rpb + 15) / 16;
+    grid = (unsigned)(nbp * (nbp + 1) / 2);
+  }
+  hipLaunchKernelGGL(fn, dim3(grid), dim3(1024), lds, st, a);
   return hipGetLastError();
 }
 

@@ -47,6 +47,7 @@ struct tr_stream {
   double* Minv = nullptr;
   double* MinvM[MAXN] = {};    // per-mode inverses (two-stream STR update)
   double* chain[2] = {};
+  unsigned* sidecnt = nullptr;  // arrival counter of the side kernel's Gram workgroups
   hipStream_t side = nullptr;  // second stream: Gram refresh, chain, inverse
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   hipEvent_t ev_inv[MAXN] = {}, ev_rs[MAXN] = {};  // MTTKRP done (main), solve done (side)
@@ -707,11 +708,16 @@ tr_status tr_stream_init(const tr_config* cfg, const double* X_init, int64_t t_i
   TR_HIP(dev_alloc(&s->Minv, (size_t)dmax * dmax));
   for (int k = 0; k < N; ++k) TR_HIP(dev_alloc(&s->MinvM[k], (size_t)dmax * dmax));
   TR_HIP(hipStreamCreateWithFlags(&s->side, hipStreamNonBlocking));
-  TR_HIP(hipEventCreateWithFlags(&s->ev_fork, hipEventDisableTiming));
-  TR_HIP(hipEventCreateWithFlags(&s->ev_join, hipEventDisableTiming));
+  // ordering events between the two streams of one device: a device-scope
+  // release suffices (each kernel's dispatch already releases its writes to
+  // the device), and the default system-scope writeback costs ~15 us per
+  // event on the dependent path
+  const unsigned evf = hipEventDisableTiming | hipEventReleaseToDevice;
+  TR_HIP(hipEventCreateWithFlags(&s->ev_fork, evf));
+  TR_HIP(hipEventCreateWithFlags(&s->ev_join, evf));
   for (int k = 0; k < N; ++k) {
-    TR_HIP(hipEventCreateWithFlags(&s->ev_inv[k], hipEventDisableTiming));
-    TR_HIP(hipEventCreateWithFlags(&s->ev_rs[k], hipEventDisableTiming));
+    TR_HIP(hipEventCreateWithFlags(&s->ev_inv[k], evf));
+    TR_HIP(hipEventCreateWithFlags(&s->ev_rs[k], evf));
   }
   int emax = 0;
   for (int k = 0; k < N; ++k) emax = std::max(emax, s->R[k] * s->R[k]);
@@ -720,6 +726,8 @@ tr_status tr_stream_init(const tr_config* cfg, const double* X_init, int64_t t_i
   TR_HIP(dev_alloc(&s->pair, 2));
   TR_HIP(dev_alloc(&s->dstatus, 4));
   TR_HIP(hipMemsetAsync(s->dstatus, 0, 4 * sizeof(int), s->st));
+  TR_HIP(dev_alloc(&s->sidecnt, 1));
+  TR_HIP(hipMemsetAsync(s->sidecnt, 0, sizeof(unsigned), s->st));
   if (s->sketch != TR_SKETCH_NONE) {
     TR_HIP(dev_alloc(&s->idxs, (size_t)N * s->m));
     TR_HIP(dev_alloc(&s->SA, (size_t)s->m * dmax));
@@ -839,17 +847,15 @@ tr_status tr_stream_update(tr_stream* s, const void* X_new, int32_t x_dtype, int
     s->t_total += t_new;
     return TR_OK;
   }
-  // Two streams.  The side stream carries the serial chain of the step: per
-  // mode one fused kernel (Gram refresh of the core updated just before,
-  // Gram chain, Q update, inverse) and then the split reduction + solve.
-  // The caller's stream runs the MTTKRPs, each after the solve of the mode
-  // before it; a solve waits for its mode's MTTKRP, which has usually
-  // finished by then, so no cross-stream wait sits on the chain.
+  // Per mode: the side step (Gram refresh of the core updated just before,
+  // Gram chain, Q update, inverse), the MTTKRP, then the split reduction +
+  // solve, which needs both.  When every mode fits the fused launch the side
+  // step and the MTTKRP share one kernel on the caller's stream.  Otherwise
+  // the side stream carries the serial chain (side kernel, then solve) and
+  // the caller's stream the MTTKRPs, each after the solve before it.
   hipStream_t side = s->side;
   const long pstep = prof_begin(s, PK_STEP);
   long pr;
-  TR_HIP(hipEventRecord(s->ev_fork, s->st));
-  TR_HIP(hipStreamWaitEvent(side, s->ev_fork, 0));
   auto side_args = [&](int n, int p, const double* Gp, int64_t rows_p) {
     SideArgs a;
     a.Gp = Gp;
@@ -873,21 +879,54 @@ tr_status tr_stream_update(tr_stream* s, const void* X_new, int32_t x_dtype, int
     a.store_Q = 1;
     a.Qinv = s->MinvM[n];
     a.status = s->dstatus;
+    a.counter = s->sidecnt;
     return a;
   };
-  // modes in order: temporal (its side kernel also refreshes Z_{N-1} of the
-  // previous step's last core), then n = 0..N-2 (mode n's side kernel
-  // refreshes the Gram of the core updated just before it; Z_N^new for n = 0)
+  auto side_of = [&](int n) {
+    if (n == N - 1) return side_args(N - 1, N - 2, s->G[N - 2], s->I[N - 2]);
+    if (n == 0) return side_args(0, N - 1, Gnew, t_new);
+    return side_args(n, n - 1, s->G[n - 1], s->I[n - 1]);
+  };
+  // one stream when every mode fits the fused launch: per mode the side
+  // step and the MTTKRP in one kernel, then the split reduction + solve
+  bool fused = true;
+  for (int n = 0; n < N; ++n) fused = fused && mode_fusable(make_geom(N, gd.data(), s->R, n), side_of(n));
+  if (fused) {
+    for (int j = 0; j < N; ++j) {
+      const int n = j == 0 ? N - 1 : j - 1;
+      const bool temporal = n == N - 1;
+      Geom g = make_geom(N, gd.data(), s->R, n);
+      MttkrpPlan p = plan_mttkrp(g, s->dt);
+      c = ensure_partials(s, g, p);
+      if (c != TR_OK) return c;
+      const CoreView cv = state_view(s, Gnew);
+      pr = prof_begin(s, temporal ? PK_MTT_T : PK_MTT_N);
+      TR_HIP(launch_mode(g, p, Xd, s->dt, cv, F64, s->part, side_of(n), s->st));
+      prof_end(s, pr);
+      pr = prof_begin(s, PK_SOLVE);
+      if (temporal)
+        TR_HIP(launch_reduce_solve(s->part, p.psize, p.nsplit, g.In, g.d, nullptr, 0,
+                                   s->MinvM[N - 1], Gnew, s->st));
+      else
+        TR_HIP(launch_reduce_solve(s->part, p.psize, p.nsplit, g.In, g.d, s->P[n], 1,
+                                   s->MinvM[n], s->G[n], s->st));
+      prof_end(s, pr);
+    }
+    prof_end(s, pstep);
+    s->t_total += t_new;
+    return TR_OK;
+  }
+  // otherwise two streams.  Modes in order: temporal (its side kernel also
+  // refreshes Z_{N-1} of the previous step's last core), then n = 0..N-2
+  // (mode n's side kernel refreshes the Gram of the core updated just
+  // before it; Z_N^new for n = 0)
+  TR_HIP(hipEventRecord(s->ev_fork, s->st));
+  TR_HIP(hipStreamWaitEvent(side, s->ev_fork, 0));
   for (int j = 0; j < N; ++j) {
     const int n = j == 0 ? N - 1 : j - 1;
     const bool temporal = n == N - 1;
     pr = prof_begin(s, PK_CHAIN, side);
-    if (temporal)
-      TR_HIP(launch_side(side_args(N - 1, N - 2, s->G[N - 2], s->I[N - 2]), side));
-    else if (n == 0)
-      TR_HIP(launch_side(side_args(0, N - 1, Gnew, t_new), side));
-    else
-      TR_HIP(launch_side(side_args(n, n - 1, s->G[n - 1], s->I[n - 1]), side));
+    TR_HIP(launch_side(side_of(n), side));
     prof_end(s, pr, side);
     if (!temporal) TR_HIP(hipStreamWaitEvent(s->st, s->ev_rs[n == 0 ? N - 1 : n - 1], 0));
     Geom g = make_geom(N, gd.data(), s->R, n);
@@ -1065,7 +1104,7 @@ void tr_stream_destroy(tr_stream* s) {
   void* kbufs[] = {s->dGSc, s->Ast, s->Bst, s->Sw2, s->Wmix, s->xh[0], s->xh[1], s->Zk, s->dPk};
   for (void* b : kbufs)
     if (b) (void)hipFree(b);
-  void* bufs[] = {s->Minv, s->chain[0], s->chain[1], s->xcast, s->xf64, s->part,
+  void* bufs[] = {s->sidecnt, s->Minv, s->chain[0], s->chain[1], s->xcast, s->xf64, s->part,
                   s->wg,   s->pair,     s->dstatus,  s->idxs,  s->SA,   s->Sw,
                   s->Zb,   s->Zi,       s->dprobs,   s->cdf};
   for (void* b : bufs)

@@ -87,8 +87,9 @@ hipError_t launch_invert_spd(const double* M, int Ra, int Rb, double* Q, int acc
                              int store_Q, double* Qinv, int* status, hipStream_t st,
                              int m_plain = 0);
 
-// Fused per-mode side step (one workgroup of 1024 threads): optionally the
-// transfer-layout Gram E_p of `rows_p` slice-major rows Gp (written to Ep),
+// Fused per-mode side step (workgroups of 1024 threads): optionally the
+// transfer-layout Gram E_p of `rows_p` slice-major rows Gp (written to Ep,
+// one workgroup per upper-triangle 16x16 tile; the last to finish goes on),
 // then the ring product of the nfac transfer-layout factors fac[0..nfac)
 // (fac[j] is fr[j] x fc[j]; a null entry stands for Ep), then the Q-layout
 // assembly / accumulation into Q and the Gauss-Jordan inverse into Qinv.
@@ -106,8 +107,18 @@ struct SideArgs {
   int accumulate, store_Q;
   double* Qinv;
   int* status;
+  unsigned* counter;   // arrival counter of the Gram workgroups (zero between launches)
 };
 hipError_t launch_side(const SideArgs& a, hipStream_t st);
+
+// One mode in one launch: the side step of `sa` in workgroup 0 (4 waves)
+// beside the MTTKRP of (g, p) in the other workgroups.  Valid when
+// mode_fusable (R_nR_{n+1} <= 64 for the mode and its side step); state
+// cores in FP64.
+bool mode_fusable(const Geom& g, const SideArgs& sa);
+hipError_t launch_mode(const Geom& g, const MttkrpPlan& p, const void* X, int xdt,
+                       const CoreView& cv, int cdt, void* part, const SideArgs& sa,
+                       hipStream_t st);
 
 // Elementwise dtype conversion of n elements (round to nearest even).
 hipError_t launch_cast(const void* src, int sdt, void* dst, int ddt, int64_t n, hipStream_t st);
