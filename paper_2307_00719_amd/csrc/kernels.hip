@@ -948,43 +948,84 @@ __global__ __launch_bounds__(1024) void k_side(SideArgs sa) {
 // same.  One workgroup barrier per pivot block.
 // ---------------------------------------------------------------------------
 
+// floor(a / b) for 0 <= a < 2^22 and b > 0, given rb = 1.0f / b: the float
+// product is within a relative 2^-23 of (a + 0.5) / b, which lies at least
+// 0.5 / b from the nearest integer, so the truncation is exact.  It replaces
+// the integer division sequence on the latency-bound side path.
+__device__ inline int small_div(int a, float rb) { return (int)(((float)a + 0.5f) * rb); }
+
+// Cross-lane moves of the pivot step, all on the VALU (no LDS round trip):
+// group_bcast<K> gives every lane the value held by the lane of the same
+// column in row group K (lanes 16K..16K+15): a 16-lane-row swap picks rows
+// {K&1, K&1 + 2}, a 32-lane-half swap then the half K&2.  row_bcast<p>
+// gives every lane the value of lane p of its own 16-lane row (DPP row
+// broadcast).  lane_value<L> reads lane L into a wave-uniform value.
+template <int K>
+__device__ inline double group_bcast(double x) {
+  const unsigned long long u = __builtin_bit_cast(unsigned long long, x);
+  const unsigned lo = (unsigned)u, hi = (unsigned)(u >> 32);
+  const auto a = __builtin_amdgcn_permlane16_swap(lo, lo, false, false);
+  const auto b = __builtin_amdgcn_permlane16_swap(hi, hi, false, false);
+  const unsigned lo1 = (K & 1) ? a[1] : a[0], hi1 = (K & 1) ? b[1] : b[0];
+  const auto c = __builtin_amdgcn_permlane32_swap(lo1, lo1, false, false);
+  const auto e = __builtin_amdgcn_permlane32_swap(hi1, hi1, false, false);
+  const unsigned lo2 = (K & 2) ? c[1] : c[0], hi2 = (K & 2) ? e[1] : e[0];
+  return __builtin_bit_cast(double, ((unsigned long long)hi2 << 32) | lo2);
+}
+template <int P>
+__device__ inline double row_bcast(double x) {
+  return __builtin_amdgcn_update_dpp(0.0, x, 0x150 + P, 0xf, 0xf, false);
+}
+template <int L>
+__device__ inline double lane_value(double x) {
+  const unsigned long long u = __builtin_bit_cast(unsigned long long, x);
+  const unsigned lo = __builtin_amdgcn_readlane((unsigned)u, L);
+  const unsigned hi = __builtin_amdgcn_readlane((unsigned)(u >> 32), L);
+  return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+
+// One pivot step p of the in-wave Gauss-Jordan elimination (tile layout:
+// lane l, register v holds T[l/16 + 4v][l%16]).
+template <int p>
+__device__ inline void gj16_step(d4& c, int r0, int j, double tol, int nvalid, bool& bad) {
+  const double rowp = group_bcast<(p & 3)>(c[p >> 2]);          // T[p][j]
+  const double piv = lane_value<((p & 3) << 4) | p>(c[p >> 2]);   // T[p][p]
+  double colp[4];
+#pragma unroll
+  for (int v = 0; v < 4; ++v) colp[v] = row_bcast<p>(c[v]);      // T[r0 + 4v][p]
+  if (p < nvalid && !(piv > tol)) bad = true;
+  // 1/piv: hardware reciprocal refined by two Newton steps
+  double ip = __builtin_amdgcn_rcp(piv);
+  ip = fma(fma(-piv, ip, 1.0), ip, ip);
+  ip = fma(fma(-piv, ip, 1.0), ip, ip);
+  const double rs = rowp * ip;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int i = r0 + 4 * v;
+    const double x = c[v];
+    double y;
+    if (i == p)
+      y = (j == p) ? ip : x * ip;
+    else
+      y = (j == p) ? -x * ip : x - colp[v] * rs;
+    c[v] = y;
+  }
+  if constexpr (p < 15) gj16_step<p + 1>(c, r0, j, tol, nvalid, bad);
+}
+
 // In-place Gauss-Jordan inverse of a 16x16 tile held by one wave in the
 // accumulator layout; rows / columns >= nvalid are identity padding and are
 // not tested.  Returns true if a tested pivot is not above tol.
 __device__ inline bool wave_gj16(d4& c, int lane, double tol, int nvalid) {
-  const int r0 = lane >> 4, j = lane & 15;
   bool bad = false;
-#pragma unroll
-  for (int p = 0; p < 16; ++p) {
-    const double rowp = __shfl(c[p >> 2], ((p & 3) << 4) | j, 64);      // T[p][j]
-    const double piv = __shfl(c[p >> 2], ((p & 3) << 4) | p, 64);       // T[p][p]
-    double colp[4];
-#pragma unroll
-    for (int v = 0; v < 4; ++v) colp[v] = __shfl(c[v], (r0 << 4) | p, 64);  // T[i][p]
-    if (p < nvalid && !(piv > tol)) bad = true;
-    // 1/piv: hardware reciprocal refined by two Newton steps
-    double ip = __builtin_amdgcn_rcp(piv);
-    ip = fma(fma(-piv, ip, 1.0), ip, ip);
-    ip = fma(fma(-piv, ip, 1.0), ip, ip);
-    const double rs = rowp * ip;
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int i = r0 + 4 * v;
-      const double x = c[v];
-      double y;
-      if (i == p)
-        y = (j == p) ? ip : x * ip;
-      else
-        y = (j == p) ? -x * ip : x - colp[v] * rs;
-      c[v] = y;
-    }
-  }
+  gj16_step<0>(c, lane >> 4, lane & 15, tol, nvalid, bad);
   return bad;
 }
 
-// LDS budget of the side step, in doubles (64 KiB: room is left on the CU for
-// two MTTKRP workgroups running beside it).
-constexpr int SIDE_LDS = 8192;
+// LDS budget of the side step, in doubles (66 KiB: two 64 x 64 chain operands,
+// one of them with padded rows; room is left on the CU for an MTTKRP
+// workgroup beside it).
+constexpr int SIDE_LDS = 8448;
 
 // Serial part of the side step, for a workgroup of NW waves: the ring
 // product of the transfer-layout factors, the Q tiles (assembly,
@@ -994,22 +1035,58 @@ template <int NW, int MAXT>
 __device__ inline void side_serial(const SideArgs& sa, double* lds, double* dmax, int tid) {
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
   const int ar = lane & 15, ak = lane >> 4;
+  const int Ra = sa.Ra, Rb = sa.Rb, d = Ra * Rb;
+  const int nb = (d + 15) >> 4, ntile = nb * nb;
+  const float rRa = 1.0f / (float)Ra;
+  // tile coordinates of the (up to MAXT) Q tiles of this wave
+  int TI[MAXT], TJ[MAXT];
+  {
+    const float rnb = 1.0f / (float)nb;
+#pragma unroll
+    for (int s = 0; s < MAXT; ++s) {
+      const int t = wave + NW * s;
+      TI[s] = small_div(t, rnb);
+      TJ[s] = t - TI[s] * nb;
+    }
+  }
+  // the Q entries this lane accumulates, loaded now so that their latency
+  // overlaps the chain product
+  const bool qacc = sa.Q && sa.accumulate;
+  double qpre[MAXT][4];
+#pragma unroll
+  for (int s = 0; s < MAXT; ++s) {
+    const int t = wave + NW * s;
+    const int ti = t < ntile ? TI[s] : nb - 1, tj = t < ntile ? TJ[s] : nb - 1;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int gi = min(ti * 16 + Acc<double>::row(lane, v), d - 1), gj = min(tj * 16 + ar, d - 1);
+      const double q = qacc ? sa.Q[gi * d + gj] : 0.0;
+      qpre[s][v] = q;
+    }
+  }
   // 2. ring product of the transfer-layout factors: both operands staged in
-  //    LDS when they fit (the left factor column-major, so the 16 lanes of
-  //    an operand read consecutive words), else read through the cache in
-  //    batches of 8 k-steps.  When the last product has at most 16 tiles it
-  //    is kept in LDS for the assembly.
+  //    LDS when they fit (rows of the left factor padded by one element, so
+  //    the 16 lanes of an operand read 16 different banks and the staging
+  //    stores are contiguous), else read through the cache in batches of 8
+  //    k-steps.  When the last product has at most 16 tiles it is kept in
+  //    LDS for the assembly.
+  // M is always a global pointer (a pointer that may also address LDS would
+  // turn every load into a flat load with conservative waits); m_lds says
+  // the last product is in LDS instead
   const double* M = sa.fac[0] ? sa.fac[0] : sa.Ep;
+  bool m_lds = false;
   for (int j = 1; j < sa.nfac; ++j) {
     const double* __restrict__ F = sa.fac[j] ? sa.fac[j] : sa.Ep;
     double* out = sa.cbuf[(j - 1) & 1];
     const int d1 = sa.fr[0], d2 = sa.fc[j - 1], d3 = sa.fc[j];
     const int nb1 = (d1 + 15) >> 4, nb3 = (d3 + 15) >> 4, ntile = nb1 * nb3;
-    const bool staged = d1 * d2 + d2 * d3 <= SIDE_LDS;
+    const int d2p = d2 + 1;
+    const float rd2 = 1.0f / (float)d2, rnb3 = 1.0f / (float)nb3;
+    const bool staged = d1 * d2p + d2 * d3 <= SIDE_LDS;
     if (staged) {
-      // [M^T | F] copied to LDS with all loads in flight at once
+      // [M (padded rows) | F] copied to LDS with all loads in flight at once
       const int n1 = d1 * d2, n2 = d2 * d3;
-      constexpr int PER = SIDE_LDS / (64 * NW);
+      constexpr int PER = (SIDE_LDS + 64 * NW - 1) / (64 * NW);
       double x[PER];
 #pragma unroll
       for (int q = 0; q < PER; ++q) {
@@ -1022,26 +1099,26 @@ __device__ inline void side_serial(const SideArgs& sa, double* lds, double* dmax
       for (int q = 0; q < PER; ++q) {
         const int e = tid + 64 * NW * q;
         if (e < n1) {
-          const int r = e / d2;
-          lds[(e - r * d2) * d1 + r] = x[q];
+          const int r = small_div(e, rd2);
+          lds[r * d2p + (e - r * d2)] = x[q];
         } else if (e < n1 + n2) {
-          lds[n1 + (e - n1)] = x[q];
+          lds[d1 * d2p + (e - n1)] = x[q];
         }
       }
       __syncthreads();
     }
     auto tile_mm = [&](int b) -> d4 {
-      const int rb = b / nb3, cb = b - rb * nb3;
+      const int rb = small_div(b, rnb3), cb = b - rb * nb3;
       const int arow = min(rb * 16 + ar, d1 - 1), bcol = min(cb * 16 + ar, d3 - 1);
       d4 acc = {0, 0, 0, 0};
       const int kfull = d2 & ~3;
       if (staged) {
-        const double* MsT = lds;
-        const double* Fs = lds + d1 * d2;
+        const double* Ms = lds;
+        const double* Fs = lds + d1 * d2p;
 #pragma unroll 8
         for (int k0 = 0; k0 < kfull; k0 += 4) {
           const int k = k0 + ak;
-          acc = mfma16(MsT[k * d1 + arow], Fs[k * d3 + bcol], acc);
+          acc = mfma16(Ms[arow * d2p + k], Fs[k * d3 + bcol], acc);
         }
       } else {
         int k0 = 0;
@@ -1065,14 +1142,14 @@ __device__ inline void side_serial(const SideArgs& sa, double* lds, double* dmax
         // ragged last k-step: lanes past d2 contribute zeros
         const int k = kfull + ak;
         const int kc = min(k, d2 - 1);
-        const double av = staged ? lds[kc * d1 + arow] : M[(size_t)arow * d2 + kc];
-        const double bv = staged ? lds[d1 * d2 + kc * d3 + bcol] : F[(size_t)kc * d3 + bcol];
+        const double av = staged ? lds[arow * d2p + kc] : M[(size_t)arow * d2 + kc];
+        const double bv = staged ? lds[d1 * d2p + kc * d3 + bcol] : F[(size_t)kc * d3 + bcol];
         acc = mfma16(k < d2 ? av : 0.0, k < d2 ? bv : 0.0, acc);
       }
       return acc;
     };
     auto store_tile = [&](int b, const d4& acc, double* dst) {
-      const int rb = b / nb3, cb = b - rb * nb3;
+      const int rb = small_div(b, rnb3), cb = b - rb * nb3;
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int r = rb * 16 + Acc<double>::row(lane, v), c = cb * 16 + ar;
@@ -1095,7 +1172,8 @@ __device__ inline void side_serial(const SideArgs& sa, double* lds, double* dmax
         if (b < ntile) store_tile(b, res[t], keep ? lds : out);
       }
       __syncthreads();
-      M = keep ? lds : out;
+      M = out;
+      m_lds = keep;
     } else {
       for (int b = wave; b < ntile; b += NW) store_tile(b, tile_mm(b), out);
       __syncthreads();
@@ -1103,8 +1181,6 @@ __device__ inline void side_serial(const SideArgs& sa, double* lds, double* dmax
     }
   }
   // 3. Q tiles: assembly from the chain product, accumulation, store
-  const int Ra = sa.Ra, Rb = sa.Rb, d = Ra * Rb;
-  const int nb = (d + 15) >> 4, ntile = nb * nb;
   d4 A[MAXT];
   double mx = 0.0;
 #pragma unroll
@@ -1112,16 +1188,21 @@ __device__ inline void side_serial(const SideArgs& sa, double* lds, double* dmax
     const int t = wave + NW * s;
     d4 x = {0, 0, 0, 0};
     if (t < ntile) {
-      const int ti = t / nb, tj = t - ti * nb;
+      const int ti = TI[s], tj = TJ[s];
+      const int s2 = small_div(tj * 16 + ar, rRa), r2 = tj * 16 + ar - s2 * Ra;
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int gi = ti * 16 + Acc<double>::row(lane, v), gj = tj * 16 + ar;
         double val;
         if (gi < d && gj < d) {
           const int e = gi * d + gj;
-          const int r = gi % Ra, s1 = gi / Ra, r2 = gj % Ra, s2 = gj / Ra;
-          val = M[(size_t)(s1 + Rb * s2) * (Ra * Ra) + (r + Ra * r2)];
-          if (sa.Q && sa.accumulate) val += sa.Q[e];
+          const int s1 = small_div(gi, rRa), r = gi - s1 * Ra;
+          const int mi = (s1 + Rb * s2) * (Ra * Ra) + (r + Ra * r2);
+          if (m_lds)
+            val = lds[mi];
+          else
+            val = M[mi];
+          if (qacc) val += qpre[s][v];
           if (sa.Q && sa.store_Q) sa.Q[e] = val;
           if (gi == gj) mx = fmax(mx, val);
         } else {
@@ -1156,7 +1237,7 @@ __device__ inline void side_serial(const SideArgs& sa, double* lds, double* dmax
     for (int s = 0; s < MAXT; ++s) {
       const int t = wave + NW * s;
       if (t < ntile) {
-        const int ti = t / nb, tj = t - ti * nb;
+        const int ti = TI[s], tj = TJ[s];
         if (ti == K && tj == K) {
           bad |= wave_gj16(A[s], lane, tol, d - 16 * K);
 #pragma unroll
@@ -1181,7 +1262,7 @@ __device__ inline void side_serial(const SideArgs& sa, double* lds, double* dmax
     for (int s = 0; s < MAXT; ++s) {
       const int t = wave + NW * s;
       if (t < ntile) {
-        const int ti = t / nb, tj = t - ti * nb;
+        const int ti = TI[s], tj = TJ[s];
         if (ti == K && tj == K) {
           // holds P already
         } else if (ti == K) {
@@ -1227,7 +1308,7 @@ __device__ inline void side_serial(const SideArgs& sa, double* lds, double* dmax
   for (int s = 0; s < MAXT; ++s) {
     const int t = wave + NW * s;
     if (t < ntile) {
-      const int ti = t / nb, tj = t - ti * nb;
+      const int ti = TI[s], tj = TJ[s];
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int gi = ti * 16 + Acc<double>::row(lane, v), gj = tj * 16 + cl;
@@ -1284,7 +1365,8 @@ __device__ inline void gram_tile(const SideArgs& sa, double* lds, int tid, int t
     for (int w = 0; w < NW; ++w) sum += lds[w * 256 + e];
     const int r = rb * 16 + (e >> 4), c = cb * 16 + (e & 15);
     if (r < dp && c < dp) {
-      const int a1 = r % Ra, b1 = r / Ra, a2 = c % Ra, b2 = c / Ra;
+      const float rRa = 1.0f / (float)Ra;
+      const int b1 = small_div(r, rRa), a1 = r - b1 * Ra, b2 = small_div(c, rRa), a2 = c - b2 * Ra;
       sa.Ep[(size_t)(a1 + Ra * a2) * (Rb * Rb) + (b1 + Rb * b2)] = sum;
       sa.Ep[(size_t)(a2 + Ra * a1) * (Rb * Rb) + (b2 + Rb * b1)] = sum;
     }
