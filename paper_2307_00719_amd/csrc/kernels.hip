@@ -999,16 +999,20 @@ __device__ inline void gj16_step(d4& c, int r0, int j, double tol, int nvalid, b
   ip = fma(fma(-piv, ip, 1.0), ip, ip);
   ip = fma(fma(-piv, ip, 1.0), ip, ip);
   const double rs = rowp * ip;
+  // branch-free update (selects, no exec-mask regions): row p is scaled by
+  // 1/piv, column p becomes -x/piv, the pivot 1/piv, the rest x - colp*rs;
+  // only register p/4 holds part of row p
+  const bool cj = j == p;
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
-    const int i = r0 + 4 * v;
     const double x = c[v];
-    double y;
-    if (i == p)
-      y = (j == p) ? ip : x * ip;
-    else
-      y = (j == p) ? -x * ip : x - colp[v] * rs;
-    c[v] = y;
+    const double yo = cj ? -x * ip : fma(-colp[v], rs, x);
+    if (v == (p >> 2)) {
+      const double yr = cj ? ip : x * ip;
+      c[v] = r0 == (p & 3) ? yr : yo;
+    } else {
+      c[v] = yo;
+    }
   }
   if constexpr (p < 15) gj16_step<p + 1>(c, r0, j, tol, nvalid, bad);
 }
