@@ -1026,6 +1026,113 @@ __device__ inline bool wave_gj16(d4& c, int lane, double tol, int nvalid) {
   return bad;
 }
 
+// ---------------------------------------------------------------------------
+// Column-owner Gauss-Jordan inverse of a symmetric positive definite matrix
+// of at most 64 x 64 (nb <= 4 tiles a side) on four waves: wave j holds tile
+// column j (A[i] = tile (i, j)).  The elimination runs over pivot blocks of
+// four: step k pivots on rows / columns 4k..4k+3, which are register k%4 of
+// tile row k/4.  Per step:
+//   Pinv = P^{-1} of the 4 x 4 pivot block (four scalar pivots, owner wave),
+//   pivot rows   R_j <- Pinv R_j                      (MFMA, B operand R_j),
+//   other rows   T_ij <- T_ij - C_i (Pinv R_j)        (one 16x16x4 MFMA),
+//   pivot columns C_i <- -C_i Pinv                    (MFMA, owner wave),
+//   pivot block  <- Pinv.
+// The pivot columns are never read: in-place elimination of a symmetric
+// matrix keeps T[a][b] = -T[b][a] when exactly one of a, b has been pivoted
+// and T[a][b] = T[b][a] otherwise, so C_i is the transposed pivot-row strip
+// of tile column i with the rows already pivoted negated.  The transposed
+// strip in the A-operand layout sits in the same lanes as the strip in the
+// accumulator layout, so the waves only exchange the four pivot rows (one
+// register per tile) and Pinv through LDS, with one barrier per step.  The
+// scalar pivots are the Schur-complement diagonals of the unblocked
+// elimination, so the positivity test is the same.
+// ---------------------------------------------------------------------------
+
+// Pinv of the 4 x 4 pivot block held in register x at lanes 16g + 4*KK + r
+// (row g, column r): four in-wave scalar Gauss-Jordan steps.  Lanes outside
+// the block's columns end with Pinv times their row strip (unused).
+template <int KK, int p>
+__device__ inline void pinv4_step(double& x, int g, int r, double tol, int nvalid, bool& bad) {
+  const double rowp = group_bcast<p>(x);                      // P[p][r]
+  const double colp = row_bcast<4 * KK + p>(x);               // P[g][p]
+  const double piv = lane_value<16 * p + 4 * KK + p>(x);      // P[p][p]
+  if (4 * KK + p < nvalid && !(piv > tol)) bad = true;
+  // the hardware reciprocal is good to about 2^-26; one Newton step squares
+  // its error to the last bit or two of the double
+  double ip = __builtin_amdgcn_rcp(piv);
+  ip = fma(fma(-piv, ip, 1.0), ip, ip);
+  const bool cj = r == 4 * KK + p;
+  const double yo = cj ? -x * ip : fma(-colp, rowp * ip, x);
+  const double yr = cj ? ip : x * ip;
+  x = g == p ? yr : yo;
+  if constexpr (p < 3) pinv4_step<KK, p + 1>(x, g, r, tol, nvalid, bad);
+}
+
+// Input of elimination step k: every wave publishes its part of the pivot
+// rows (register k%4 of tile (k/4, j)), the owner wave inverts the pivot
+// block and publishes Pinv (kept in `pinv` for its own fix-ups).  LDS per
+// step parity: four 64-lane strips and the 16 entries of Pinv.
+template <int k>
+__device__ inline void gj64_publish(const d4 (&A)[4], double* lds, int lane, int wave, int nb,
+                                    int d, double tol, bool& bad, double& pinv) {
+  constexpr int K = k >> 2, KK = k & 3;
+  double* S = lds + (k & 1) * 320;
+  double* Pv = S + 256;
+  if (wave < nb) S[wave * 64 + lane] = A[K][KK];
+  if (wave == K) {
+    const int g = lane >> 4, r = lane & 15;
+    pinv = A[K][KK];
+    pinv4_step<KK, 0>(pinv, g, r, tol, d - 16 * K, bad);
+    if ((r >> 2) == KK) Pv[g * 4 + (r & 3)] = pinv;
+  }
+}
+
+// Elimination step k (pivot rows 4k..4k+3), then the next.  The tile row
+// of the next pivot block is updated first and the next step's input is
+// published right after it, before the other tiles of this step.
+template <int k>
+__device__ inline void gj64_step(d4 (&A)[4], double* lds, int lane, int wave, int nb, int d,
+                                 double tol, bool& bad, double& pinv) {
+  constexpr int K = k >> 2, KK = k & 3;
+  if (K >= nb) return;
+  const int g = lane >> 4, r = lane & 15;
+  const double* S = lds + (k & 1) * 320;
+  const double* Pv = S + 256;
+  __syncthreads();
+  const double pin = pinv;
+  if (wave < nb) {
+    const d4 zero = {0, 0, 0, 0};
+    const double pa = r < 4 ? Pv[r * 4 + g] : 0.0;            // Pinv[r][g], A operand
+    const d4 d1 = mfma16(pa, A[K][KK], zero);                 // rows 0..3: Pinv R_j
+    const bool own = wave == K;
+    const bool colP = own && (r >> 2) == KK;
+    const double pb = colP ? Pv[g * 4 + (r & 3)] : 0.0;       // Pinv in the pivot columns
+    constexpr int KN = (k + 1) >> 2;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int i = (KN + t) & 3;
+      if (i < nb) {
+        const double sv = S[i * 64 + lane];
+        const double a2 = 16 * i + r < 4 * k ? sv : -sv;      // -C_i, A operand
+        const d4 d2 = mfma16(a2, d1[0], A[i]);
+        d4 d3 = zero;
+        if (own) d3 = mfma16(a2, pb, zero);                   // -C_i Pinv
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          if (i == K && v == KK)
+            A[i][v] = colP ? pin : d1[0];
+          else
+            A[i][v] = colP ? d3[v] : d2[v];
+        }
+      }
+      if constexpr (k < 15) {
+        if (t == 0 && KN < nb) gj64_publish<k + 1>(A, lds, lane, wave, nb, d, tol, bad, pinv);
+      }
+    }
+  }
+  if constexpr (k < 15) gj64_step<k + 1>(A, lds, lane, wave, nb, d, tol, bad, pinv);
+}
+
 // LDS budget of the side step, in doubles (66 KiB: two 64 x 64 chain operands,
 // one of them with padded rows; room is left on the CU for an MTTKRP
 // workgroup beside it).
@@ -1042,15 +1149,27 @@ __device__ inline void side_serial(const SideArgs& sa, double* lds, double* dmax
   const int Ra = sa.Ra, Rb = sa.Rb, d = Ra * Rb;
   const int nb = (d + 15) >> 4, ntile = nb * nb;
   const float rRa = 1.0f / (float)Ra;
-  // tile coordinates of the (up to MAXT) Q tiles of this wave
+  // tile coordinates of the (up to MAXT) Q tiles of this wave: with four
+  // waves and MAXT = 4 (nb <= 4, checked by the host) wave w holds tile
+  // column w, as the column-owner elimination needs; otherwise tile
+  // t = wave + NW*s in row-major order
+  constexpr bool COLS = NW == 4 && MAXT == 4;
   int TI[MAXT], TJ[MAXT];
+  bool TV[MAXT];
   {
     const float rnb = 1.0f / (float)nb;
 #pragma unroll
     for (int s = 0; s < MAXT; ++s) {
-      const int t = wave + NW * s;
-      TI[s] = small_div(t, rnb);
-      TJ[s] = t - TI[s] * nb;
+      if (COLS) {
+        TI[s] = s;
+        TJ[s] = wave;
+        TV[s] = s < nb && wave < nb;
+      } else {
+        const int t = wave + NW * s;
+        TI[s] = small_div(t, rnb);
+        TJ[s] = t - TI[s] * nb;
+        TV[s] = t < ntile;
+      }
     }
   }
   // the Q entries this lane accumulates, loaded now so that their latency
@@ -1059,8 +1178,7 @@ __device__ inline void side_serial(const SideArgs& sa, double* lds, double* dmax
   double qpre[MAXT][4];
 #pragma unroll
   for (int s = 0; s < MAXT; ++s) {
-    const int t = wave + NW * s;
-    const int ti = t < ntile ? TI[s] : nb - 1, tj = t < ntile ? TJ[s] : nb - 1;
+    const int ti = TV[s] ? TI[s] : nb - 1, tj = TV[s] ? TJ[s] : nb - 1;
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const int gi = min(ti * 16 + Acc<double>::row(lane, v), d - 1), gj = min(tj * 16 + ar, d - 1);
@@ -1189,9 +1307,8 @@ __device__ inline void side_serial(const SideArgs& sa, double* lds, double* dmax
   double mx = 0.0;
 #pragma unroll
   for (int s = 0; s < MAXT; ++s) {
-    const int t = wave + NW * s;
     d4 x = {0, 0, 0, 0};
-    if (t < ntile) {
+    if (TV[s]) {
       const int ti = TI[s], tj = TJ[s];
       const int s2 = small_div(tj * 16 + ar, rRa), r2 = tj * 16 + ar - s2 * Ra;
 #pragma unroll
@@ -1225,13 +1342,19 @@ __device__ inline void side_serial(const SideArgs& sa, double* lds, double* dmax
 #pragma unroll
   for (int w = 0; w < NW; ++w) mx = fmax(mx, dmax[w]);
   const double tol = (double)d * 2.220446049250313e-16 * mx;
+  bool bad = false;
+  if constexpr (COLS) {
+    // 4. column-owner elimination in pivot blocks of four
+    double pinv = 0.0;
+    gj64_publish<0>(A, lds, lane, wave, nb, d, tol, bad, pinv);
+    gj64_step<0>(A, lds, lane, wave, nb, d, tol, bad, pinv);
+  } else {
   // 4. blocked Gauss-Jordan, LDS double-buffered per pivot block:
   //    Pb = P (row-major), PbT = P^T, RowB[j] = A_Kj (row-major),
   //    ColT[i] = A_iK^T
   const int bstride = 2 * nb * 256 + 512;
   const bool dbuf = 2 * bstride <= SIDE_LDS;
   const int kq = lane >> 4, cl = lane & 15;
-  bool bad = false;
   for (int K = 0; K < nb; ++K) {
     double* Pb = lds + (dbuf ? (K & 1) * bstride : 0);
     double* PbT = Pb + 256;
@@ -1239,8 +1362,7 @@ __device__ inline void side_serial(const SideArgs& sa, double* lds, double* dmax
     double* ColT = RowB + nb * 256;
 #pragma unroll
     for (int s = 0; s < MAXT; ++s) {
-      const int t = wave + NW * s;
-      if (t < ntile) {
+      if (TV[s]) {
         const int ti = TI[s], tj = TJ[s];
         if (ti == K && tj == K) {
           bad |= wave_gj16(A[s], lane, tol, d - 16 * K);
@@ -1264,8 +1386,7 @@ __device__ inline void side_serial(const SideArgs& sa, double* lds, double* dmax
     __syncthreads();
 #pragma unroll
     for (int s = 0; s < MAXT; ++s) {
-      const int t = wave + NW * s;
-      if (t < ntile) {
+      if (TV[s]) {
         const int ti = TI[s], tj = TJ[s];
         if (ti == K && tj == K) {
           // holds P already
@@ -1308,10 +1429,11 @@ __device__ inline void side_serial(const SideArgs& sa, double* lds, double* dmax
     }
     if (!dbuf) __syncthreads();
   }
+  }
+  const int cl = lane & 15;
 #pragma unroll
   for (int s = 0; s < MAXT; ++s) {
-    const int t = wave + NW * s;
-    if (t < ntile) {
+    if (TV[s]) {
       const int ti = TI[s], tj = TJ[s];
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
@@ -1494,14 +1616,10 @@ hipError_t launch_mode(const Geom& g, const MttkrpPlan& p, const void* X, int xd
   const int64_t gspan = (g.I[f] - 1) * cv.si[f] + (g.R[f] - 1) * cv.sr[f] +
                         (g.R[(f + 1) % g.N] - 1) * cv.ss[f] + 1;
   if (xspan >= ((int64_t)1 << 31) || gspan >= ((int64_t)1 << 31)) return hipErrorInvalidValue;
-  const int nb = (sa.Ra * sa.Rb + 15) / 16;
-  const bool small = nb * nb <= 4;
-  if (xdt == F64)
-    return small ? launch_mode_j<double, 1>(g, p, X, cv, part, sa, st)
-                 : launch_mode_j<double, 4>(g, p, X, cv, part, sa, st);
-  if (xdt == F32)
-    return small ? launch_mode_j<float, 1>(g, p, X, cv, part, sa, st)
-                 : launch_mode_j<float, 4>(g, p, X, cv, part, sa, st);
+  // four tiles per wave: the side step's column-owner elimination holds a
+  // tile column (nb <= 4, guaranteed by mode_fusable) per wave
+  if (xdt == F64) return launch_mode_j<double, 4>(g, p, X, cv, part, sa, st);
+  if (xdt == F32) return launch_mode_j<float, 4>(g, p, X, cv, part, sa, st);
   return hipErrorInvalidValue;
 }
 
