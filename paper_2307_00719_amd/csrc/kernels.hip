@@ -441,87 +441,82 @@ hipError_t launch_mttkrp(const Geom& g, const MttkrpPlan& p, const void* X, int 
 
 // ---------------------------------------------------------------------------
 // Split reduction (fixed order), P accumulation and the right-multiply by
-// Q_n^{-1}: G_{n(2)} = P_n Q_n^dagger (Alg. 4).  RB rows per workgroup; TPO
-// consecutive lanes share one output, each summing every TPO-th split in
-// increasing order, then a fixed shuffle tree combines them.
+// Q_n^{-1}: G_{n(2)} = P_n Q_n^dagger (Alg. 4).  One row per workgroup (the
+// work is latency-bound: a few loads per thread, all in flight at once).
+// Wave q sums the splits q, q+4, q+8, ... of every column (a wave reads 64
+// consecutive columns of one split), the four wave sums are added in a fixed
+// order; the product with Q_n^{-1} splits the inner index over the waves the
+// same way.
 // ---------------------------------------------------------------------------
 template <typename PT>
 __global__ __launch_bounds__(256) void k_reduce_solve(const PT* __restrict__ part, int nsplit,
-                                                      int64_t In, int d, int RB, double* P,
+                                                      int64_t In, int d, double* P,
                                                       int accumulate,
                                                       const double* __restrict__ Minv,
                                                       double* __restrict__ out) {
-  extern __shared__ double prow[];                      // [RB][d+1]
-  const int tid = threadIdx.x;
-  const int64_t r0 = (int64_t)blockIdx.x * RB;
-  const int rows = (int)(In - r0 < RB ? In - r0 : RB);
-  const int nout = rows * d;
-  int TPO = 1;
-  while (TPO < 16 && TPO * 2 * nout <= 256) TPO *= 2;
-  const int OPP = 256 / TPO;
-  const int lane = tid & (TPO - 1);
+  extern __shared__ double sh[];                        // [4][d] wave sums, [d] row
+  double* red = sh;
+  double* prow = sh + 4 * d;
+  const int q = threadIdx.x >> 6, c0 = threadIdx.x & 63;
+  const int64_t row = blockIdx.x;
   const size_t stride = (size_t)In * d;
-  for (int ob = 0; ob < nout; ob += OPP) {
-    const int o = ob + tid / TPO;
+  const PT* __restrict__ src = part + (size_t)row * d;
+  for (int c = c0; c < d; c += 64) {
     double sum = 0.0;
-    int row = 0, c = 0;
-    if (o < nout) {
-      row = o / d;
-      c = o - row * d;
-      const PT* src = part + (size_t)(r0 + row) * d + c;
-      int sp = lane;
-      for (; sp + 3 * TPO < nsplit; sp += 4 * TPO) {
-        const double x0 = (double)src[(size_t)sp * stride];
-        const double x1 = (double)src[(size_t)(sp + TPO) * stride];
-        const double x2 = (double)src[(size_t)(sp + 2 * TPO) * stride];
-        const double x3 = (double)src[(size_t)(sp + 3 * TPO) * stride];
-        sum += x0;
-        sum += x1;
-        sum += x2;
-        sum += x3;
-      }
-      for (; sp < nsplit; sp += TPO) sum += (double)src[(size_t)sp * stride];
+    int sp = q;
+    for (; sp + 28 < nsplit; sp += 32) {
+      double x[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) x[u] = (double)src[(size_t)(sp + 4 * u) * stride + c];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) sum += x[u];
     }
-    for (int off = TPO >> 1; off > 0; off >>= 1) sum += __shfl_down(sum, off, TPO);
-    if (o < nout && lane == 0) {
-      if (P) {
-        const size_t pi = (size_t)(r0 + row) * d + c;
-        if (accumulate) sum += P[pi];
-        P[pi] = sum;
-      }
-      prow[row * (d + 1) + c] = sum;
+    for (; sp < nsplit; sp += 4) sum += (double)src[(size_t)sp * stride + c];
+    red[q * d + c] = sum;
+  }
+  __syncthreads();
+  for (int c = threadIdx.x; c < d; c += 256) {
+    double sum = ((red[c] + red[d + c]) + red[2 * d + c]) + red[3 * d + c];
+    if (P) {
+      const size_t pi = (size_t)row * d + c;
+      if (accumulate) sum += P[pi];
+      P[pi] = sum;
     }
+    prow[c] = sum;
   }
   if (!Minv) return;
   __syncthreads();
-  for (int e = tid; e < nout; e += 256) {
-    const int row = e / d, c2 = e - row * d;
-    const double* pr = prow + row * (d + 1);
+  const int cq = (d + 3) >> 2, cb = q * cq, ce = min(d, cb + cq);
+  for (int c2 = c0; c2 < d; c2 += 64) {
     double g0 = 0.0, g1 = 0.0;
-    int c = 0;
-    for (; c + 1 < d; c += 2) {
-      g0 += pr[c] * Minv[(size_t)c * d + c2];
-      g1 += pr[c + 1] * Minv[(size_t)(c + 1) * d + c2];
+    int c = cb;
+#pragma unroll 4
+    for (; c + 1 < ce; c += 2) {
+      g0 += prow[c] * Minv[(size_t)c * d + c2];
+      g1 += prow[c + 1] * Minv[(size_t)(c + 1) * d + c2];
     }
-    if (c < d) g0 += pr[c] * Minv[(size_t)c * d + c2];
-    out[(size_t)(r0 + row) * d + c2] = g0 + g1;
+    if (c < ce) g0 += prow[c] * Minv[(size_t)c * d + c2];
+    red[q * d + c2] = g0 + g1;
   }
+  __syncthreads();
+  for (int c2 = threadIdx.x; c2 < d; c2 += 256)
+    out[(size_t)row * d + c2] = ((red[c2] + red[d + c2]) + red[2 * d + c2]) + red[3 * d + c2];
 }
 
 hipError_t launch_reduce_solve(const void* part, int psize, int nsplit, int64_t In, int d,
                                double* P, int accumulate, const double* Minv, double* out,
                                hipStream_t st) {
-  int RB = (int)(In / 64);
-  if (RB < 1) RB = 1;
-  if (RB > 16) RB = 16;
-  dim3 grid((unsigned)((In + RB - 1) / RB));
-  const size_t lds = (size_t)RB * (d + 1) * sizeof(double);
+  if (In <= 0) return hipSuccess;
+  if (In > 0x7fffffff || d <= 0) return hipErrorInvalidValue;
+  dim3 grid((unsigned)In);
+  const size_t lds = (size_t)5 * d * sizeof(double);
+  if (lds > 65536) return hipErrorInvalidValue;
   if (psize == 8)
     hipLaunchKernelGGL(k_reduce_solve<double>, grid, dim3(256), lds, st, (const double*)part,
-                       nsplit, In, d, RB, P, accumulate, Minv, out);
+                       nsplit, In, d, P, accumulate, Minv, out);
   else
     hipLaunchKernelGGL(k_reduce_solve<float>, grid, dim3(256), lds, st, (const float*)part,
-                       nsplit, In, d, RB, P, accumulate, Minv, out);
+                       nsplit, In, d, P, accumulate, Minv, out);
   return hipGetLastError();
 }
 
