@@ -1132,6 +1132,9 @@ __device__ inline void gj64_step(d4 (&A)[4], double* lds, int lane, int wave, in
 // one of them with padded rows; room is left on the CU for an MTTKRP
 // workgroup beside it).
 constexpr int SIDE_LDS = 8448;
+// allocation: SIDE_LDS plus the spare slot that takes the staging copy's
+// out-of-range stores
+constexpr int SIDE_LDS_ALLOC = SIDE_LDS + 2;
 
 // Serial part of the side step, for a workgroup of NW waves: the ring
 // product of the transfer-layout factors, the Q tiles (assembly,
@@ -1201,26 +1204,27 @@ __device__ inline void side_serial(const SideArgs& sa, double* lds, double* dmax
     const float rd2 = 1.0f / (float)d2, rnb3 = 1.0f / (float)nb3;
     const bool staged = d1 * d2p + d2 * d3 <= SIDE_LDS;
     if (staged) {
-      // [M (padded rows) | F] copied to LDS with all loads in flight at once
+      // [M (padded rows) | F] copied to LDS with all loads in flight at once:
+      // one load per element (the source pointer is selected, both sources
+      // clamped in range) and one unconditional LDS store (elements past the
+      // end go to the spare slot SIDE_LDS), so the copy has no branches
       const int n1 = d1 * d2, n2 = d2 * d3;
       constexpr int PER = (SIDE_LDS + 64 * NW - 1) / (64 * NW);
       double x[PER];
 #pragma unroll
       for (int q = 0; q < PER; ++q) {
         const int e = tid + 64 * NW * q;
-        const double a = M[min(e, n1 - 1)];
-        const double b = F[min(max(e - n1, 0), n2 - 1)];
-        x[q] = e < n1 ? a : b;
+        const double* src = e < n1 ? M + min(e, n1 - 1) : F + min(max(e - n1, 0), n2 - 1);
+        x[q] = *src;
       }
 #pragma unroll
       for (int q = 0; q < PER; ++q) {
         const int e = tid + 64 * NW * q;
-        if (e < n1) {
-          const int r = small_div(e, rd2);
-          lds[r * d2p + (e - r * d2)] = x[q];
-        } else if (e < n1 + n2) {
-          lds[d1 * d2p + (e - n1)] = x[q];
-        }
+        const int em = min(e, n1 - 1);
+        const int r = small_div(em, rd2);
+        const int dst = e < n1 ? r * d2p + (em - r * d2)
+                               : (e < n1 + n2 ? d1 * d2p + (e - n1) : SIDE_LDS);
+        lds[dst] = x[q];
       }
       __syncthreads();
     }
@@ -1574,7 +1578,7 @@ static hipError_t launch_mode_t(const Geom& g, const MttkrpPlan& p, const void* 
   const int wst = 16 * ((Rn1 * Rf1 + 15) / 16);
   const size_t lmt = (size_t)(3 * 256 + 16 * g.d + 16 * wst) * sizeof(double) +
                      (size_t)(16 * dfp) * p.KS * sizeof(PT);
-  const size_t lds = std::max(lmt, (size_t)SIDE_LDS * sizeof(double));
+  const size_t lds = std::max(lmt, (size_t)SIDE_LDS_ALLOC * sizeof(double));
   auto fn = k_mode<T, double, NJ, MAXT>;
   if (lds > 65536) {
     hipError_t e = hipFuncSetAttribute((const void*)fn,
@@ -1620,7 +1624,7 @@ hipError_t launch_mode(const Geom& g, const MttkrpPlan& p, const void* X, int xd
 
 template <int MAXT>
 static hipError_t launch_side_mf(const SideArgs& a, int nb, hipStream_t st) {
-  const size_t lds = (size_t)SIDE_LDS * sizeof(double);
+  const size_t lds = (size_t)SIDE_LDS_ALLOC * sizeof(double);
   auto fn = k_side_mf<MAXT>;
   if (lds > 65536) {
     hipError_t e = hipFuncSetAttribute((const void*)fn,
