@@ -1260,11 +1260,18 @@ __device__ inline void side_serial(const SideArgs& sa, double* lds, double* dmax
         }
       }
       if (kfull < d2) {
-        // ragged last k-step: lanes past d2 contribute zeros
+        // ragged last k-step: lanes past d2 contribute zeros (LDS and global
+        // reads kept apart so neither becomes a generic-address load)
         const int k = kfull + ak;
         const int kc = min(k, d2 - 1);
-        const double av = staged ? lds[arow * d2p + kc] : M[(size_t)arow * d2 + kc];
-        const double bv = staged ? lds[d1 * d2p + kc * d3 + bcol] : F[(size_t)kc * d3 + bcol];
+        double av, bv;
+        if (staged) {
+          av = lds[arow * d2p + kc];
+          bv = lds[d1 * d2p + kc * d3 + bcol];
+        } else {
+          av = M[(size_t)arow * d2 + kc];
+          bv = F[(size_t)kc * d3 + bcol];
+        }
         acc = mfma16(k < d2 ? av : 0.0, k < d2 ? bv : 0.0, acc);
       }
       return acc;
@@ -1301,37 +1308,51 @@ __device__ inline void side_serial(const SideArgs& sa, double* lds, double* dmax
       M = out;
     }
   }
-  // 3. Q tiles: assembly from the chain product, accumulation, store
+  // 3. Q tiles: assembly from the chain product, accumulation, store.  All
+  //    chain-product reads first (from LDS or from global memory: two
+  //    separate loops, so neither becomes a generic-address load), then the
+  //    accumulation and stores.
+  const bool storeQ = sa.Q && sa.store_Q;
+  int MI[MAXT][4];
+  double mv[MAXT][4];
+#pragma unroll
+  for (int s = 0; s < MAXT; ++s) {
+    const int tj = TJ[s], ti = TI[s];
+    const int s2 = small_div(tj * 16 + ar, rRa), r2 = tj * 16 + ar - s2 * Ra;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int gi = ti * 16 + Acc<double>::row(lane, v), gj = tj * 16 + ar;
+      const int s1 = small_div(gi, rRa), r = gi - s1 * Ra;
+      const bool ok = TV[s] && gi < d && gj < d;
+      MI[s][v] = ok ? (s1 + Rb * s2) * (Ra * Ra) + (r + Ra * r2) : 0;
+    }
+  }
+  if (m_lds) {
+#pragma unroll
+    for (int s = 0; s < MAXT; ++s)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) mv[s][v] = lds[MI[s][v]];
+  } else {
+#pragma unroll
+    for (int s = 0; s < MAXT; ++s)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) mv[s][v] = M[MI[s][v]];
+  }
   d4 A[MAXT];
   double mx = 0.0;
 #pragma unroll
   for (int s = 0; s < MAXT; ++s) {
-    d4 x = {0, 0, 0, 0};
-    if (TV[s]) {
-      const int ti = TI[s], tj = TJ[s];
-      const int s2 = small_div(tj * 16 + ar, rRa), r2 = tj * 16 + ar - s2 * Ra;
+    const int ti = TI[s], tj = TJ[s];
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int gi = ti * 16 + Acc<double>::row(lane, v), gj = tj * 16 + ar;
-        double val;
-        if (gi < d && gj < d) {
-          const int e = gi * d + gj;
-          const int s1 = small_div(gi, rRa), r = gi - s1 * Ra;
-          const int mi = (s1 + Rb * s2) * (Ra * Ra) + (r + Ra * r2);
-          if (m_lds)
-            val = lds[mi];
-          else
-            val = M[mi];
-          if (qacc) val += qpre[s][v];
-          if (sa.Q && sa.store_Q) sa.Q[e] = val;
-          if (gi == gj) mx = fmax(mx, val);
-        } else {
-          val = gi == gj ? 1.0 : 0.0;
-        }
-        x[v] = val;
-      }
+    for (int v = 0; v < 4; ++v) {
+      const int gi = ti * 16 + Acc<double>::row(lane, v), gj = tj * 16 + ar;
+      const bool ok = TV[s] && gi < d && gj < d;
+      double val = mv[s][v];
+      if (qacc) val += qpre[s][v];
+      if (ok && storeQ) sa.Q[gi * d + gj] = val;
+      if (ok && gi == gj) mx = fmax(mx, val);
+      A[s][v] = ok ? val : (gi == gj ? 1.0 : 0.0);
     }
-    A[s] = x;
   }
   if (!sa.Qinv) return;
   for (int off = 32; off > 0; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off, 64));
