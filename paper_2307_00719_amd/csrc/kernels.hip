@@ -1313,30 +1313,25 @@ __device__ inline void side_serial(const SideArgs& sa, double* lds, double* dmax
   //    separate loops, so neither becomes a generic-address load), then the
   //    accumulation and stores.
   const bool storeQ = sa.Q && sa.store_Q;
-  int MI[MAXT][4];
   double mv[MAXT][4];
-#pragma unroll
-  for (int s = 0; s < MAXT; ++s) {
+  auto m_index = [&](int s, int v) {
     const int tj = TJ[s], ti = TI[s];
-    const int s2 = small_div(tj * 16 + ar, rRa), r2 = tj * 16 + ar - s2 * Ra;
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int gi = ti * 16 + Acc<double>::row(lane, v), gj = tj * 16 + ar;
-      const int s1 = small_div(gi, rRa), r = gi - s1 * Ra;
-      const bool ok = TV[s] && gi < d && gj < d;
-      MI[s][v] = ok ? (s1 + Rb * s2) * (Ra * Ra) + (r + Ra * r2) : 0;
-    }
-  }
+    const int gi = ti * 16 + Acc<double>::row(lane, v), gj = tj * 16 + ar;
+    const int s1 = small_div(gi, rRa), r = gi - s1 * Ra;
+    const int s2 = small_div(gj, rRa), r2 = gj - s2 * Ra;
+    const bool ok = TV[s] && gi < d && gj < d;
+    return ok ? (s1 + Rb * s2) * (Ra * Ra) + (r + Ra * r2) : 0;
+  };
   if (m_lds) {
 #pragma unroll
     for (int s = 0; s < MAXT; ++s)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) mv[s][v] = lds[MI[s][v]];
+      for (int v = 0; v < 4; ++v) mv[s][v] = lds[m_index(s, v)];
   } else {
 #pragma unroll
     for (int s = 0; s < MAXT; ++s)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) mv[s][v] = M[MI[s][v]];
+      for (int v = 0; v < 4; ++v) mv[s][v] = M[m_index(s, v)];
   }
   d4 A[MAXT];
   double mx = 0.0;
@@ -1486,11 +1481,15 @@ __device__ inline void gram_tile(const SideArgs& sa, double* lds, int tid, int t
   const int64_t nks = (rows + 3) / 4;
   const double* __restrict__ Gp = sa.Gp;
   const int c1 = min(rb * 16 + ar, dp - 1), c2 = min(cb * 16 + ar, dp - 1);
-  d4 acc = {0, 0, 0, 0};
-  for (int64_t k0 = wave; k0 < nks; k0 += 8 * NW) {
-    double av[8], bv[8];
+  // KB k-steps of loads in flight per wave (16 with four waves, 8 with the
+  // 16-wave kernel's register budget); with four waves two accumulators
+  // (even and odd k-steps) halve the dependent MFMA chains
+  constexpr int KB = NW <= 4 ? 16 : 8;
+  d4 acc0 = {0, 0, 0, 0}, acc1 = {0, 0, 0, 0};
+  for (int64_t k0 = wave; k0 < nks; k0 += KB * NW) {
+    double av[KB], bv[KB];
 #pragma unroll
-    for (int q = 0; q < 8; ++q) {
+    for (int q = 0; q < KB; ++q) {
       const int64_t ks = k0 + NW * q;
       const int64_t i = ks * 4 + ak;
       const int64_t ic = i < rows ? i : rl;
@@ -1499,11 +1498,20 @@ __device__ inline void gram_tile(const SideArgs& sa, double* lds, int tid, int t
       av[q] = ok ? xa : 0.0;
       bv[q] = ok ? xb : 0.0;
     }
+    if constexpr (NW <= 4) {
 #pragma unroll
-    for (int q = 0; q < 8; ++q) acc = mfma16(av[q], bv[q], acc);
+      for (int q = 0; q < KB; q += 2) {
+        acc0 = mfma16(av[q], bv[q], acc0);
+        acc1 = mfma16(av[q + 1], bv[q + 1], acc1);
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < KB; ++q) acc0 = mfma16(av[q], bv[q], acc0);
+    }
   }
 #pragma unroll
-  for (int v = 0; v < 4; ++v) lds[wave * 256 + Acc<double>::row(lane, v) * 16 + ar] = acc[v];
+  for (int v = 0; v < 4; ++v)
+    lds[wave * 256 + Acc<double>::row(lane, v) * 16 + ar] = acc0[v] + acc1[v];
   __syncthreads();
   for (int e = tid; e < 256; e += 64 * NW) {
     double sum = 0.0;
