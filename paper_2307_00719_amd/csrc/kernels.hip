@@ -118,7 +118,7 @@ __device__ inline int64_t decode_column(const Geom& g, int64_t k, int* idx) {
   return off;
 }
 
-MttkrpPlan plan_mttkrp(const Geom& g, int xdtype) {
+MttkrpPlan plan_mttkrp(const Geom& g, int xdtype, int max_wg) {
   MttkrpPlan p;
   const int N = g.N;
   p.MT = 16;
@@ -145,6 +145,7 @@ MttkrpPlan plan_mttkrp(const Geom& g, int xdtype) {
   int64_t chunks = (512 + p.mtiles - 1) / p.mtiles;
   const int64_t by_bytes = xbytes / (2 * (int64_t)g.In * g.d * p.psize);
   if (chunks > by_bytes) chunks = by_bytes;
+  if (max_wg > 0 && chunks > max_wg / p.mtiles) chunks = max_wg / p.mtiles;
   if (chunks > p.Kout) chunks = p.Kout;
   if (chunks < 1) chunks = 1;
   if (const char* e = getenv("TRSTREAM_NSPLIT")) {
@@ -1595,6 +1596,21 @@ __global__ __launch_bounds__(256, 2) void k_mode(Geom g, MttkrpPlan p, const T* 
 
 bool mode_fusable(const Geom& g, const SideArgs& sa) {
   return sa.Ra * sa.Rb <= 64 && g.d <= 64;
+}
+
+// The side step is latency-bound on one compute unit and slows down by
+// about a tenth when an MTTKRP workgroup shares that unit.  When the batch
+// is small enough that the MTTKRP, spread one workgroup per compute unit,
+// still ends before the side step (measured on the 256 x 256 x 20 FP64
+// batch: 26 us for 10.5 MB of X against 34 us for the side step; up to
+// about 12 MB of X), the launch holds at most one workgroup per compute
+// unit; larger batches keep the plan of about 512 workgroups.
+MttkrpPlan plan_mode(const Geom& g, int xdtype, const SideArgs& sa, int ncu) {
+  const int nbp = (sa.Rpa * sa.Rpb + 15) / 16;
+  const int ngram = sa.Gp ? nbp * (nbp + 1) / 2 : 1;
+  const int64_t xbytes = g.L * g.Rr * g.In * (xdtype == F64 ? 8 : (xdtype == F32 ? 4 : 2));
+  if (ncu > ngram && xbytes <= ((int64_t)12 << 20)) return plan_mttkrp(g, xdtype, ncu - ngram);
+  return plan_mttkrp(g, xdtype);
 }
 
 template <typename T, int NJ, int MAXT>

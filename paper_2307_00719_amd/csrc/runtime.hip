@@ -37,6 +37,7 @@ struct tr_stream {
   int rescale = 1, temporal_literal = 0, check_finite = 0;
   uint64_t seed = 0;
   int device = 0;
+  int ncu = 0;                  // compute units of the device
   hipStream_t st = nullptr;
   bool own_stream = false;
   int64_t t_total = 0, cap = 0;
@@ -684,6 +685,7 @@ tr_status tr_stream_init(const tr_config* cfg, const double* X_init, int64_t t_i
   *out = s;
 
   TR_HIP(hipSetDevice(s->device));
+  TR_HIP(hipDeviceGetAttribute(&s->ncu, hipDeviceAttributeMultiprocessorCount, s->device));
   if (cfg->hip_stream) {
     s->st = (hipStream_t)cfg->hip_stream;
   } else {
@@ -896,12 +898,13 @@ tr_status tr_stream_update(tr_stream* s, const void* X_new, int32_t x_dtype, int
       const int n = j == 0 ? N - 1 : j - 1;
       const bool temporal = n == N - 1;
       Geom g = make_geom(N, gd.data(), s->R, n);
-      MttkrpPlan p = plan_mttkrp(g, s->dt);
+      const SideArgs sa = side_of(n);
+      MttkrpPlan p = plan_mode(g, s->dt, sa, s->ncu);
       c = ensure_partials(s, g, p);
       if (c != TR_OK) return c;
       const CoreView cv = state_view(s, Gnew);
       pr = prof_begin(s, temporal ? PK_MTT_T : PK_MTT_N);
-      TR_HIP(launch_mode(g, p, Xd, s->dt, cv, F64, s->part, side_of(n), s->st));
+      TR_HIP(launch_mode(g, p, Xd, s->dt, cv, F64, s->part, sa, s->st));
       prof_end(s, pr);
       pr = prof_begin(s, PK_SOLVE);
       if (temporal)

@@ -52,7 +52,8 @@ struct MttkrpPlan {
   int64_t sf, sm;  // X strides of i_f and of the row index i_n
 };
 
-MttkrpPlan plan_mttkrp(const Geom& g, int xdtype);
+// max_wg > 0 caps the workgroup count (nsplit * mtiles) at about max_wg.
+MttkrpPlan plan_mttkrp(const Geom& g, int xdtype, int max_wg = 0);
 size_t mttkrp_partial_bytes(const Geom& g, const MttkrpPlan& p);
 
 // ---- launchers (all asynchronous on `st`) --------------------------------
@@ -116,6 +117,8 @@ hipError_t launch_side(const SideArgs& a, hipStream_t st);
 // mode_fusable (R_nR_{n+1} <= 64 for the mode and its side step); state
 // cores in FP64.
 bool mode_fusable(const Geom& g, const SideArgs& sa);
+// MTTKRP plan of the fused launch on a device with ncu compute units.
+MttkrpPlan plan_mode(const Geom& g, int xdtype, const SideArgs& sa, int ncu);
 hipError_t launch_mode(const Geom& g, const MttkrpPlan& p, const void* X, int xdt,
                        const CoreView& cv, int cdt, void* part, const SideArgs& sa,
                        hipStream_t st);

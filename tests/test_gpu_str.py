@@ -69,6 +69,8 @@ SHAPES = [
     ((5, 4, 3, 3), (2, 2, 3, 2, 2), 6, 2, 3),
     ((130, 17), (1, 2, 1), 5, 5, 2),
     ((21, 19), (5, 4, 6), 40, 11, 2),
+    # Q of 42 x 42 and 49 x 49: three and four ragged 16 x 16 tiles a side
+    ((24, 22), (7, 6, 7), 20, 6, 2),
 ]
 
 
