@@ -118,6 +118,38 @@ tr_status tr_stream_get_PQ(tr_stream *s, int32_t n, double *P, double *Q);
  * row indexing the newest batch), as drawn by the counter-based generator. */
 tr_status tr_stream_get_samples(tr_stream *s, int32_t *idxs);
 
+/* Test hook (randomized variants, Alg. 3's Randsample bypassed): replaces
+ * the current sample indices with a host N x m int32 row-major array laid
+ * out as tr_stream_get_samples returns it.  Row q < N-1 indexes core q
+ * (0 <= idx < I_q); row N-1 indexes the newest temporal block
+ * (0 <= idx < t of the last update, or t_init).  The next update uses the
+ * injected rows until each is redrawn right after its core is updated,
+ * exactly where drawn indices would be used.  Out-of-range entries give
+ * TR_ERR_ARG and change nothing; no sketch configured gives TR_ERR_ARG.
+ * Synchronous: the caller may reuse idxs on return.                       */
+tr_status tr_stream_set_samples(tr_stream *s, const int32_t *idxs);
+
+/* Checkpoint of the streaming state between time steps (the quantities
+ * Alg. 4 / Algs. 7-9 carry from one step to the next: the cores, the Gram
+ * tensors Z_k, P_n and Q_n, and for the randomized variants the step
+ * counter, the sample indices and the leverage distributions) written to a
+ * host file at `path` (written to path.tmp, then renamed).  Synchronises
+ * the handle's stream.  A stream resumed by tr_stream_load produces the
+ * same results, bit for bit, as the uninterrupted one.  The file is a
+ * private binary format for the same library build and byte order.
+ * Errors: TR_ERR_ARG if the file cannot be written.                       */
+tr_status tr_stream_save(tr_stream *s, const char *path);
+
+/* Creates a handle from a file written by tr_stream_save.  cfg may be NULL
+ * (device 0, library-owned stream, default capacity).  Otherwise its
+ * device, hip_stream and max_slices are used, and when cfg->order is
+ * non-zero its order, dims, ranks, compute_dtype, sketch and sketch_size
+ * must equal the saved ones (TR_ERR_SHAPE if not).  A missing, truncated or
+ * altered file (checked by a 64-bit hash of its contents) gives TR_ERR_ARG
+ * before any device work.  On a failure after the handle exists, *out holds
+ * it so that tr_last_error can explain; destroy it.                       */
+tr_status tr_stream_load(const char *path, const tr_config *cfg, tr_stream **out);
+
 /* Blocks until the handle's stream has finished all submitted work and
  * reports any device-side failure.                                        */
 tr_status tr_stream_sync(tr_stream *s);

@@ -10,7 +10,8 @@ every compute call does, and a missing library raises ImportError.
 from ._lib import (LIB_PATH, TRError, declared_functions, load, tr_fit_loss_bwd,  # noqa: F401
                    tr_fit_loss_fwd, tr_gram_chain, tr_last_error, tr_mttkrp,
                    tr_reconstruct_error, tr_stream_destroy, tr_stream_get_cores,
-                   tr_stream_get_PQ, tr_stream_get_samples, tr_stream_init, tr_stream_num_slices, tr_stream_profile,
-                   tr_stream_profile_read, tr_stream_sync,
+                   tr_stream_get_PQ, tr_stream_get_samples, tr_stream_init, tr_stream_load,
+                   tr_stream_num_slices, tr_stream_profile, tr_stream_profile_read,
+                   tr_stream_save, tr_stream_set_samples, tr_stream_sync,
                    tr_stream_update, tr_workspace_bytes)
 from .stream import TRStream  # noqa: F401

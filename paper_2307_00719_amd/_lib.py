@@ -70,6 +70,9 @@ def load():
         "tr_stream_get_PQ": ([P, c_int32, P, P], c_int32),
         "tr_stream_sync": ([P], c_int32),
         "tr_stream_get_samples": ([P, P], c_int32),
+        "tr_stream_set_samples": ([P, P], c_int32),
+        "tr_stream_save": ([P, c_char_p], c_int32),
+        "tr_stream_load": ([c_char_p, POINTER(tr_config), POINTER(c_void_p)], c_int32),
         "tr_stream_num_slices": ([P], c_int64),
         "tr_stream_profile": ([P, c_int32], c_int32),
         "tr_stream_profile_read": ([P, c_int32, POINTER(c_double), POINTER(c_int64)], c_int32),
@@ -226,6 +229,45 @@ def tr_stream_get_samples(handle, N, m):
     out = np.zeros((N, m), dtype=np.int32)
     _check(load().tr_stream_get_samples(handle, out.ctypes.data), handle)
     return out
+
+
+def tr_stream_set_samples(handle, idxs):
+    """idxs: N x m integer array (row q = indices into core q)."""
+    a = np.ascontiguousarray(idxs, dtype=np.int32)
+    _check(load().tr_stream_set_samples(handle, a.ctypes.data), handle)
+
+
+def tr_stream_save(handle, path):
+    _check(load().tr_stream_save(handle, os.fsencode(path)), handle)
+
+
+def tr_stream_load(path, dims=None, ranks=None, compute_dtype="f64", sketch=None,
+                   sketch_size=0, device=0, hip_stream=None, max_slices=0):
+    """Returns a handle resumed from a file written by tr_stream_save.  With
+    dims (I_1..I_{N-1}) and ranks given, the library checks them, the dtype
+    and the sketch against the saved state."""
+    lib = load()
+    keep = []
+    cfg = tr_config(order=0, max_slices=int(max_slices), device=int(device),
+                    hip_stream=hip_stream)
+    if dims is not None:
+        N = len(ranks)
+        d = (c_int64 * (N - 1))(*[int(i) for i in dims])
+        r = (c_int32 * N)(*[int(x) for x in ranks])
+        keep += [d, r]
+        cfg.order, cfg.dims, cfg.ranks = N, d, r
+        cfg.compute_dtype, cfg.sketch = DTYPES[compute_dtype], SKETCHES[sketch]
+        cfg.sketch_size = int(sketch_size)
+    handle = c_void_p()
+    code = lib.tr_stream_load(os.fsencode(path), ctypes.byref(cfg), ctypes.byref(handle))
+    if code != 0:
+        msg = ""
+        if handle:
+            m = lib.tr_last_error(handle)
+            msg = m.decode() if m else ""
+            lib.tr_stream_destroy(handle)
+        raise TRError(code, msg)
+    return handle
 
 
 def tr_stream_sync(handle):

@@ -41,6 +41,7 @@ struct tr_stream {
   hipStream_t st = nullptr;
   bool own_stream = false;
   int64_t t_total = 0, cap = 0;
+  int64_t last_t = 0;           // slices of the newest temporal block (init or last batch)
   double* G[MAXN] = {};
   double* E[MAXN] = {};
   double* P[MAXN] = {};
@@ -631,18 +632,12 @@ tr_status ksrft_update(tr_stream* s, const void* Xd, int64_t t_new, double* Gnew
   return TR_OK;
 }
 
-}  // namespace
-
-extern "C" {
-
-tr_status tr_stream_init(const tr_config* cfg, const double* X_init, int64_t t_init,
-                         int32_t x_is_device, const double* const* cores_init,
-                         int32_t cores_on_device, tr_stream** out) {
-  if (!cfg || !out || !X_init || !cores_init) return TR_ERR_ARG;
-  *out = nullptr;
+// Validates a configuration whose first temporal block holds t_first slices
+// (t_init at initialisation; the newest batch when a saved state is loaded).
+tr_status check_config(const tr_config* cfg, int64_t t_first) {
   const int N = cfg->order;
   if (N < 3 || N > MAXN || !cfg->dims || !cfg->ranks) return TR_ERR_ARG;
-  if (t_init < 1) return TR_ERR_SHAPE;
+  if (t_first < 1) return TR_ERR_SHAPE;
   for (int k = 0; k < N - 1; ++k)
     if (cfg->dims[k] < 1) return TR_ERR_SHAPE;
   for (int k = 0; k < N; ++k)
@@ -659,7 +654,7 @@ tr_status tr_stream_init(const tr_config* cfg, const double* X_init, int64_t t_i
     // the mixing kernels take modes of up to 256 indices per batch
     for (int k = 0; k < N - 1; ++k)
       if (cfg->dims[k] > 256) return TR_ERR_UNSUPPORTED;
-    if (t_init > 256) return TR_ERR_UNSUPPORTED;
+    if (t_first > 256) return TR_ERR_UNSUPPORTED;
   }
   if (cfg->sketch != TR_SKETCH_NONE) {
     if (cfg->sketch_size < 1 || cfg->sketch_size > (1 << 24)) return TR_ERR_ARG;
@@ -669,7 +664,14 @@ tr_status tr_stream_init(const tr_config* cfg, const double* X_init, int64_t t_i
   }
   for (int k = 0; k < N; ++k)
     if (cfg->ranks[k] * cfg->ranks[(k + 1) % N] > 256) return TR_ERR_UNSUPPORTED;
+  return TR_OK;
+}
 
+// Creates a handle for a validated configuration and allocates its device
+// state, with room for at least t_slices temporal slices.  *out receives
+// the handle even on failure (the caller destroys it).
+tr_status create_handle(const tr_config* cfg, int64_t t_slices, tr_stream** out) {
+  const int N = cfg->order;
   tr_stream* s = new tr_stream();
   s->N = N;
   for (int k = 0; k < N - 1; ++k) s->I[k] = cfg->dims[k];
@@ -696,7 +698,7 @@ tr_status tr_stream_init(const tr_config* cfg, const double* X_init, int64_t t_i
 
   int dmax = 0;
   for (int k = 0; k < N; ++k) dmax = std::max(dmax, s->d(k));
-  s->cap = std::max<int64_t>(cfg->max_slices, t_init + 1024);
+  s->cap = std::max<int64_t>(cfg->max_slices, t_slices + 1024);
   for (int k = 0; k < N - 1; ++k) {
     TR_HIP(dev_alloc(&s->G[k], (size_t)s->I[k] * s->d(k)));
     TR_HIP(dev_alloc(&s->P[k], (size_t)s->I[k] * s->d(k)));
@@ -750,6 +752,79 @@ tr_status tr_stream_init(const tr_config* cfg, const double* X_init, int64_t t_i
     TR_HIP(dev_alloc(&s->Bst, (size_t)4 * s->m * dmax));
     TR_HIP(dev_alloc(&s->Sw2, (size_t)2 * s->m));
   }
+  return TR_OK;
+}
+
+// ---- saved state (tr_stream_save / tr_stream_load) --------------------------
+
+const char kSaveMagic[8] = {'T', 'R', 'S', 'T', 'A', 'T', 'E', '1'};
+
+struct SaveHeader {
+  char magic[8];
+  int32_t N, dt, sketch, rescale, temporal_literal, check_finite;
+  int64_t m, t_total, step, last_t;
+  uint64_t seed;
+  int64_t dims[MAXN];
+  int32_t ranks[MAXN];
+  uint64_t payload_bytes, checksum;
+};
+
+struct SaveArray {
+  void* dev;
+  size_t bytes;
+};
+
+// The device arrays that carry the state from one time step to the next, in
+// file order: per core k < N-1 its rows, P_k and Q_k; the temporal rows; the
+// Gram matrices; the sample indices (randomized variants) and the leverage
+// distributions of the non-temporal cores.  Everything else is rebuilt by
+// the next update (inverses, scratch, signs, sampled mixed slices).
+std::vector<SaveArray> save_arrays(const tr_stream* s) {
+  const int N = s->N;
+  std::vector<SaveArray> v;
+  for (int k = 0; k < N - 1; ++k) {
+    const size_t rows = (size_t)s->I[k] * s->d(k) * sizeof(double);
+    v.push_back({s->G[k], rows});
+    v.push_back({s->P[k], rows});
+    v.push_back({s->Q[k], (size_t)s->d(k) * s->d(k) * sizeof(double)});
+  }
+  v.push_back({s->G[N - 1], (size_t)s->t_total * s->d(N - 1) * sizeof(double)});
+  for (int k = 0; k < N; ++k) {
+    const size_t a = (size_t)s->R[k] * s->R[k], b = (size_t)s->R[(k + 1) % N] * s->R[(k + 1) % N];
+    v.push_back({s->E[k], a * b * sizeof(double)});
+  }
+  if (s->sketch != TR_SKETCH_NONE) v.push_back({s->idxs, (size_t)N * s->m * sizeof(int32_t)});
+  if (s->sketch == TR_SKETCH_LEVERAGE)
+    for (int k = 0; k < N - 1; ++k) v.push_back({s->probs[k], (size_t)s->I[k] * sizeof(double)});
+  return v;
+}
+
+// 64-bit FNV-1a hash (Fowler, Noll, Vo) of the payload, to reject a torn or
+// altered file before any device state is created.
+uint64_t fnv1a(const char* p, size_t n) {
+  uint64_t h = 1469598103934665603ull;
+  for (size_t i = 0; i < n; ++i) {
+    h ^= (unsigned char)p[i];
+    h *= 1099511628211ull;
+  }
+  return h;
+}
+
+}  // namespace
+
+extern "C" {
+
+tr_status tr_stream_init(const tr_config* cfg, const double* X_init, int64_t t_init,
+                         int32_t x_is_device, const double* const* cores_init,
+                         int32_t cores_on_device, tr_stream** out) {
+  if (!cfg || !out || !X_init || !cores_init) return TR_ERR_ARG;
+  *out = nullptr;
+  tr_status c = check_config(cfg, t_init);
+  if (c != TR_OK) return c;
+  c = create_handle(cfg, t_init, out);
+  tr_stream* s = *out;
+  if (c != TR_OK) return c;
+  const int N = s->N;
 
   // cores: column-major FP64 (host or device) -> slice-major state
   std::vector<int64_t> dims(N);
@@ -773,6 +848,7 @@ tr_status tr_stream_init(const tr_config* cfg, const double* X_init, int64_t t_i
   }
   if (tmp) TR_HIP(hipFree(tmp));
   s->t_total = t_init;
+  s->last_t = t_init;
 
   // Gram matrices (Alg. 4 initialisation; Z_N over the initial temporal rows)
   for (int k = 0; k < N; ++k) {
@@ -783,7 +859,7 @@ tr_status tr_stream_init(const tr_config* cfg, const double* X_init, int64_t t_i
   int64_t J = 1;
   for (int k = 0; k < N - 1; ++k) J *= s->I[k];
   const void* Xd = nullptr;
-  tr_status c = stage_batch(s, X_init, F64, J * t_init, x_is_device, &Xd);
+  c = stage_batch(s, X_init, F64, J * t_init, x_is_device, &Xd);
   if (c != TR_OK) return c;
 
   std::vector<int64_t> gd(dims);
@@ -847,6 +923,7 @@ tr_status tr_stream_update(tr_stream* s, const void* X_new, int32_t x_dtype, int
     if (c != TR_OK) return c;
     prof_end(s, pst);
     s->t_total += t_new;
+    s->last_t = t_new;
     return TR_OK;
   }
   // Per mode: the side step (Gram refresh of the core updated just before,
@@ -917,6 +994,7 @@ tr_status tr_stream_update(tr_stream* s, const void* X_new, int32_t x_dtype, int
     }
     prof_end(s, pstep);
     s->t_total += t_new;
+    s->last_t = t_new;
     return TR_OK;
   }
   // otherwise two streams.  Modes in order: temporal (its side kernel also
@@ -956,6 +1034,7 @@ tr_status tr_stream_update(tr_stream* s, const void* X_new, int32_t x_dtype, int
   TR_HIP(hipStreamWaitEvent(s->st, s->ev_join, 0));
   prof_end(s, pstep);
   s->t_total += t_new;
+  s->last_t = t_new;
   return TR_OK;
 }
 
@@ -1082,6 +1161,136 @@ tr_status tr_stream_get_samples(tr_stream* s, int32_t* idxs) {
   TR_HIP(hipSetDevice(s->device));
   TR_HIP(hipStreamSynchronize(s->st));
   TR_HIP(hipMemcpy(idxs, s->idxs, (size_t)s->N * s->m * sizeof(int32_t), hipMemcpyDeviceToHost));
+  return TR_OK;
+}
+
+tr_status tr_stream_set_samples(tr_stream* s, const int32_t* idxs) {
+  if (!s || !idxs) return TR_ERR_ARG;
+  if (s->poisoned != TR_OK) return s->poisoned;
+  if (s->sketch == TR_SKETCH_NONE) return fail(s, TR_ERR_ARG, "no sketch configured");
+  const int N = s->N;
+  for (int k = 0; k < N; ++k) {
+    const int64_t size = k == N - 1 ? s->last_t : s->I[k];
+    for (int64_t j = 0; j < s->m; ++j) {
+      const int32_t v = idxs[(size_t)k * s->m + j];
+      if (v < 0 || v >= size) return fail(s, TR_ERR_ARG, "sample index out of range");
+    }
+  }
+  TR_HIP(hipSetDevice(s->device));
+  TR_HIP(hipMemcpyAsync(s->idxs, idxs, (size_t)N * s->m * sizeof(int32_t),
+                        hipMemcpyHostToDevice, s->st));
+  TR_HIP(hipStreamSynchronize(s->st));
+  return TR_OK;
+}
+
+tr_status tr_stream_save(tr_stream* s, const char* path) {
+  if (!s || !path) return TR_ERR_ARG;
+  if (s->poisoned != TR_OK) return s->poisoned;
+  TR_HIP(hipSetDevice(s->device));
+  tr_status c = read_status(s);  // synchronises the stream
+  if (c != TR_OK) return c;
+  s->copy_pending = false;
+  SaveHeader h;
+  std::memset(&h, 0, sizeof(h));
+  std::memcpy(h.magic, kSaveMagic, sizeof(h.magic));
+  h.N = s->N;
+  h.dt = s->dt;
+  h.sketch = s->sketch;
+  h.rescale = s->rescale;
+  h.temporal_literal = s->temporal_literal;
+  h.check_finite = s->check_finite;
+  h.m = s->m;
+  h.t_total = s->t_total;
+  h.step = s->step;
+  h.last_t = s->last_t;
+  h.seed = s->seed;
+  for (int k = 0; k < s->N - 1; ++k) h.dims[k] = s->I[k];
+  for (int k = 0; k < s->N; ++k) h.ranks[k] = s->R[k];
+  std::vector<char> payload;
+  for (const SaveArray& a : save_arrays(s)) {
+    const size_t off = payload.size();
+    payload.resize(off + a.bytes);
+    TR_HIP(hipMemcpy(payload.data() + off, a.dev, a.bytes, hipMemcpyDeviceToHost));
+  }
+  h.payload_bytes = payload.size();
+  h.checksum = fnv1a(payload.data(), payload.size());
+  const std::string tmp = std::string(path) + ".tmp";
+  FILE* f = std::fopen(tmp.c_str(), "wb");
+  if (!f) return fail(s, TR_ERR_ARG, "cannot open " + tmp + " for writing");
+  bool ok = std::fwrite(&h, sizeof(h), 1, f) == 1 &&
+            (payload.empty() || std::fwrite(payload.data(), payload.size(), 1, f) == 1);
+  ok = (std::fclose(f) == 0) && ok;
+  if (!ok || std::rename(tmp.c_str(), path) != 0) {
+    std::remove(tmp.c_str());
+    return fail(s, TR_ERR_ARG, std::string("writing ") + path + " failed");
+  }
+  return TR_OK;
+}
+
+tr_status tr_stream_load(const char* path, const tr_config* cfg, tr_stream** out) {
+  if (!path || !out) return TR_ERR_ARG;
+  *out = nullptr;
+  FILE* f = std::fopen(path, "rb");
+  if (!f) return TR_ERR_ARG;
+  SaveHeader h;
+  std::vector<char> payload;
+  bool ok = std::fread(&h, sizeof(h), 1, f) == 1 &&
+            std::memcmp(h.magic, kSaveMagic, sizeof(h.magic)) == 0 && h.N >= 3 && h.N <= MAXN &&
+            h.payload_bytes < ((uint64_t)1 << 40);
+  if (ok) {
+    payload.resize(h.payload_bytes);
+    ok = payload.empty() || std::fread(payload.data(), payload.size(), 1, f) == 1;
+    char extra;
+    ok = ok && std::fread(&extra, 1, 1, f) == 0;
+  }
+  std::fclose(f);
+  if (!ok || fnv1a(payload.data(), payload.size()) != h.checksum) return TR_ERR_ARG;
+  tr_config fc;
+  std::memset(&fc, 0, sizeof(fc));
+  fc.order = h.N;
+  fc.dims = h.dims;
+  fc.ranks = h.ranks;
+  fc.compute_dtype = h.dt;
+  fc.sketch = h.sketch;
+  fc.sketch_size = h.m;
+  fc.rescale = h.rescale;
+  fc.temporal_literal = h.temporal_literal;
+  fc.seed = h.seed;
+  fc.check_finite = h.check_finite;
+  if (cfg) {
+    if (cfg->order != 0) {
+      if (cfg->order != h.N || !cfg->dims || !cfg->ranks) return TR_ERR_SHAPE;
+      for (int k = 0; k < h.N - 1; ++k)
+        if (cfg->dims[k] != h.dims[k]) return TR_ERR_SHAPE;
+      for (int k = 0; k < h.N; ++k)
+        if (cfg->ranks[k] != h.ranks[k]) return TR_ERR_SHAPE;
+      if (cfg->compute_dtype != h.dt || cfg->sketch != h.sketch ||
+          (h.sketch != TR_SKETCH_NONE && cfg->sketch_size != h.m))
+        return TR_ERR_SHAPE;
+    }
+    fc.max_slices = cfg->max_slices;
+    fc.device = cfg->device;
+    fc.hip_stream = cfg->hip_stream;
+  }
+  if (h.t_total < 1 || h.last_t < 1 || h.last_t > h.t_total || h.step < 0) return TR_ERR_ARG;
+  tr_status c = check_config(&fc, h.last_t);
+  if (c != TR_OK) return c;
+  c = create_handle(&fc, h.t_total, out);
+  tr_stream* s = *out;
+  if (c != TR_OK) return c;
+  s->t_total = h.t_total;
+  s->last_t = h.last_t;
+  s->step = h.step;
+  size_t need = 0;
+  const std::vector<SaveArray> arrs = save_arrays(s);
+  for (const SaveArray& a : arrs) need += a.bytes;
+  if (need != payload.size()) return fail(s, TR_ERR_ARG, "saved state does not match its header");
+  size_t off = 0;
+  for (const SaveArray& a : arrs) {
+    TR_HIP(hipMemcpy(a.dev, payload.data() + off, a.bytes, hipMemcpyHostToDevice));
+    off += a.bytes;
+  }
+  TR_HIP(hipStreamSynchronize(s->st));
   return TR_OK;
 }
 

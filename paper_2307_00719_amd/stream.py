@@ -27,6 +27,30 @@ class TRStream:
         self.sketch_size = int(sketch_size)
         self._keep = None
 
+    @classmethod
+    def load(cls, path, dims, ranks, compute_dtype="f64", sketch=None, sketch_size=0,
+             device=0, hip_stream=None, max_slices=0):
+        """A stream resumed from a file written by ``save``; the shape and
+        options given must be the saved ones (the library checks them)."""
+        self = cls.__new__(cls)
+        self.handle = None
+        self.dims = [int(i) for i in dims]
+        self.ranks = [int(r) for r in ranks]
+        self.N = len(self.ranks)
+        self.sketch_size = int(sketch_size)
+        self._keep = None
+        self.handle = _lib.tr_stream_load(path, dims=self.dims, ranks=self.ranks,
+                                          compute_dtype=compute_dtype, sketch=sketch,
+                                          sketch_size=sketch_size, device=device,
+                                          hip_stream=hip_stream, max_slices=max_slices)
+        return self
+
+    def save(self, path):
+        _lib.tr_stream_save(self.handle, path)
+
+    def set_samples(self, idxs):
+        _lib.tr_stream_set_samples(self.handle, idxs)
+
     def d(self, n):
         return self.ranks[n] * self.ranks[(n + 1) % self.N]
 

@@ -81,3 +81,22 @@ def test_product_path_does_not_import_oracle():
             if f.endswith((".py", ".hip", ".h", ".cpp")):
                 text = open(os.path.join(dirpath, f)).read()
                 assert "import oracle" not in text and "from oracle" not in text, f
+
+
+def test_checkpoint_entry_points_validate_without_device(tmp_path):
+    """tr_stream_load rejects a missing, foreign or truncated file before any
+    device work; save / set_samples reject null arguments."""
+    lib = P.load()
+    h = ctypes.c_void_p()
+    assert lib.tr_stream_load(None, None, ctypes.byref(h)) == 1
+    assert lib.tr_stream_load(os.fsencode(str(tmp_path / "missing.bin")), None,
+                              ctypes.byref(h)) == 1
+    junk = tmp_path / "junk.bin"
+    junk.write_bytes(b"not a saved tensor-ring stream" * 10)
+    assert lib.tr_stream_load(os.fsencode(str(junk)), None, ctypes.byref(h)) == 1
+    empty = tmp_path / "empty.bin"
+    empty.write_bytes(b"")
+    assert lib.tr_stream_load(os.fsencode(str(empty)), None, ctypes.byref(h)) == 1
+    assert not h
+    assert lib.tr_stream_save(None, b"x") == 1
+    assert lib.tr_stream_set_samples(None, None) == 1
