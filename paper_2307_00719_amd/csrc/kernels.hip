@@ -950,6 +950,18 @@ __global__ __launch_bounds__(1024) void k_side(SideArgs sa) {
 // the integer division sequence on the latency-bound side path.
 __device__ inline int small_div(int a, float rb) { return (int)(((float)a + 0.5f) * rb); }
 
+// Device-coherent access to data that other workgroups of the same launch
+// write: agent-scope relaxed atomic stores and loads are coherent across the
+// whole device (every XCD's L2) by themselves, so the Gram tiles handed from
+// the Gram workgroups to the side step need no cache write-back or
+// invalidation fences.
+__device__ inline void coherent_store(double* p, double v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline double coherent_load(const double* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // Cross-lane moves of the pivot step, all on the VALU (no LDS round trip):
 // group_bcast<K> gives every lane the value held by the lane of the same
 // column in row group K (lanes 16K..16K+15): a 16-lane-row swap picks rows
@@ -1142,7 +1154,8 @@ constexpr int SIDE_LDS_ALLOC = SIDE_LDS + 2;
 // accumulation, store) and the blocked Gauss-Jordan inverse.  MAXT >=
 // ceil(nb^2 / NW) tiles per wave.
 template <int NW, int MAXT>
-__device__ inline void side_serial(const SideArgs& sa, double* lds, double* dmax, int tid) {
+__device__ inline void side_serial(const SideArgs& sa, double* lds, double* dmax, int tid,
+                                   bool pre = false) {
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
   const int ar = lane & 15, ak = lane >> 4;
   const int Ra = sa.Ra, Rb = sa.Rb, d = Ra * Rb;
@@ -1204,7 +1217,22 @@ __device__ inline void side_serial(const SideArgs& sa, double* lds, double* dmax
     const int d2p = d2 + 1;
     const float rd2 = 1.0f / (float)d2, rnb3 = 1.0f / (float)nb3;
     const bool staged = d1 * d2p + d2 * d3 <= SIDE_LDS;
-    if (staged) {
+    if (staged && pre && j == 1) {
+      // M is already in LDS (loaded by prestage_first_factor while the Gram
+      // tile was computed): copy F only
+      const int n2 = d2 * d3;
+      constexpr int PER = (SIDE_LDS + 64 * NW - 1) / (64 * NW);
+      double x[PER];
+#pragma unroll
+      for (int q = 0; q < PER; ++q)
+        if (q * 64 * NW < n2) x[q] = coherent_load(F + min(tid + 64 * NW * q, n2 - 1));
+#pragma unroll
+      for (int q = 0; q < PER; ++q) {
+        const int e = tid + 64 * NW * q;
+        if (q * 64 * NW < n2) lds[e < n2 ? d1 * d2p + e : SIDE_LDS] = x[q];
+      }
+      __syncthreads();
+    } else if (staged) {
       // [M (padded rows) | F] copied to LDS with all loads in flight at once:
       // one load per element (the source pointer is selected, both sources
       // clamped in range) and one unconditional LDS store (elements past the
@@ -1216,7 +1244,7 @@ __device__ inline void side_serial(const SideArgs& sa, double* lds, double* dmax
       for (int q = 0; q < PER; ++q) {
         const int e = tid + 64 * NW * q;
         const double* src = e < n1 ? M + min(e, n1 - 1) : F + min(max(e - n1, 0), n2 - 1);
-        x[q] = *src;
+        x[q] = coherent_load(src);
       }
 #pragma unroll
       for (int q = 0; q < PER; ++q) {
@@ -1249,15 +1277,16 @@ __device__ inline void side_serial(const SideArgs& sa, double* lds, double* dmax
 #pragma unroll
           for (int q = 0; q < 8; ++q) {
             const int k = k0 + 4 * q + ak;
-            av[q] = M[(size_t)arow * d2 + k];
-            bv[q] = F[(size_t)k * d3 + bcol];
+            av[q] = coherent_load(M + (size_t)arow * d2 + k);
+            bv[q] = coherent_load(F + (size_t)k * d3 + bcol);
           }
 #pragma unroll
           for (int q = 0; q < 8; ++q) acc = mfma16(av[q], bv[q], acc);
         }
         for (; k0 < kfull; k0 += 4) {
           const int k = k0 + ak;
-          acc = mfma16(M[(size_t)arow * d2 + k], F[(size_t)k * d3 + bcol], acc);
+          acc = mfma16(coherent_load(M + (size_t)arow * d2 + k),
+                       coherent_load(F + (size_t)k * d3 + bcol), acc);
         }
       }
       if (kfull < d2) {
@@ -1270,19 +1299,24 @@ __device__ inline void side_serial(const SideArgs& sa, double* lds, double* dmax
           av = lds[arow * d2p + kc];
           bv = lds[d1 * d2p + kc * d3 + bcol];
         } else {
-          av = M[(size_t)arow * d2 + kc];
-          bv = F[(size_t)kc * d3 + bcol];
+          av = coherent_load(M + (size_t)arow * d2 + kc);
+          bv = coherent_load(F + (size_t)kc * d3 + bcol);
         }
         acc = mfma16(k < d2 ? av : 0.0, k < d2 ? bv : 0.0, acc);
       }
       return acc;
     };
-    auto store_tile = [&](int b, const d4& acc, double* dst) {
+    auto store_tile = [&](int b, const d4& acc, bool to_lds) {
       const int rb = small_div(b, rnb3), cb = b - rb * nb3;
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int r = rb * 16 + Acc<double>::row(lane, v), c = cb * 16 + ar;
-        if (r < d1 && c < d3) dst[(size_t)r * d3 + c] = acc[v];
+        if (r < d1 && c < d3) {
+          if (to_lds)
+            lds[r * d3 + c] = acc[v];
+          else
+            coherent_store(out + (size_t)r * d3 + c, acc[v]);
+        }
       }
     };
     constexpr int RM = (16 + NW - 1) / NW;
@@ -1298,13 +1332,13 @@ __device__ inline void side_serial(const SideArgs& sa, double* lds, double* dmax
 #pragma unroll
       for (int t = 0; t < RM; ++t) {
         const int b = wave + NW * t;
-        if (b < ntile) store_tile(b, res[t], keep ? lds : out);
+        if (b < ntile) store_tile(b, res[t], keep);
       }
       __syncthreads();
       M = out;
       m_lds = keep;
     } else {
-      for (int b = wave; b < ntile; b += NW) store_tile(b, tile_mm(b), out);
+      for (int b = wave; b < ntile; b += NW) store_tile(b, tile_mm(b), false);
       __syncthreads();
       M = out;
     }
@@ -1332,7 +1366,7 @@ __device__ inline void side_serial(const SideArgs& sa, double* lds, double* dmax
 #pragma unroll
     for (int s = 0; s < MAXT; ++s)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) mv[s][v] = M[m_index(s, v)];
+      for (int v = 0; v < 4; ++v) mv[s][v] = coherent_load(M + m_index(s, v));
   }
   d4 A[MAXT];
   double mx = 0.0;
@@ -1522,24 +1556,70 @@ __device__ inline void gram_tile(const SideArgs& sa, double* lds, int tid, int t
     if (r < dp && c < dp) {
       const float rRa = 1.0f / (float)Ra;
       const int b1 = small_div(r, rRa), a1 = r - b1 * Ra, b2 = small_div(c, rRa), a2 = c - b2 * Ra;
-      sa.Ep[(size_t)(a1 + Ra * a2) * (Rb * Rb) + (b1 + Rb * b2)] = sum;
-      sa.Ep[(size_t)(a2 + Ra * a1) * (Rb * Rb) + (b2 + Rb * b1)] = sum;
+      coherent_store(sa.Ep + (size_t)(a1 + Ra * a2) * (Rb * Rb) + (b1 + Rb * b2), sum);
+      coherent_store(sa.Ep + (size_t)(a2 + Ra * a1) * (Rb * Rb) + (b2 + Rb * b1), sum);
     }
   }
 }
 
-// Arrival of a Gram workgroup: release its tile, count it in; true for the
-// last of `total` to arrive (which also resets the counter and acquires the
-// other tiles).
+// The first factor of the side step's ring product is never the Gram matrix
+// that the launch's Gram tiles refresh (that one is always the last factor),
+// so every Gram workgroup loads it while its tile is computed and leaves it
+// in LDS in the padded-row layout of the staged product; the workgroup that
+// goes on with the side step then copies only the second factor.  Not done
+// when the first product is not staged or the factor exceeds one register
+// batch (FirstFactor::ok false).
+struct FirstFactor {
+  static constexpr int PER = 16;            // 4096 doubles over 256 threads
+  double x[PER];
+  bool ok;
+};
+
+__device__ inline void prestage_first_factor_load(const SideArgs& sa, FirstFactor& ff, int tid) {
+  ff.ok = false;
+  if (sa.nfac < 2 || !sa.fac[0] || sa.fac[0] == sa.Ep) return;
+  const int d1 = sa.fr[0], d2 = sa.fc[0], d3 = sa.fc[1];
+  ff.ok = d1 * d2 <= 256 * FirstFactor::PER && d1 * (d2 + 1) + d2 * d3 <= SIDE_LDS;
+  if (!ff.ok) return;
+  const double* __restrict__ M = sa.fac[0];
+  const int n1 = d1 * d2;
+#pragma unroll
+  for (int q = 0; q < FirstFactor::PER; ++q) ff.x[q] = M[min(tid + 256 * q, n1 - 1)];
+}
+
+// After the Gram tile (its LDS use must be over): the loaded factor to LDS.
+__device__ inline void prestage_first_factor_store(const SideArgs& sa, const FirstFactor& ff,
+                                                   double* lds, int tid) {
+  if (!ff.ok) return;
+  const int d2 = sa.fc[0], d2p = d2 + 1, n1 = sa.fr[0] * d2;
+  const float rd2 = 1.0f / (float)d2;
+#pragma unroll
+  for (int q = 0; q < FirstFactor::PER; ++q) {
+    const int e = tid + 256 * q;
+    const int em = min(e, n1 - 1);
+    const int r = small_div(em, rd2);
+    lds[e < n1 ? r * d2p + (em - r * d2) : SIDE_LDS] = ff.x[q];
+  }
+}
+
+// Arrival of a Gram workgroup: count it in once its tile is stored; true for
+// the last of `total` to arrive (which also resets the counter).  The tile
+// stores are device-coherent atomic stores: each thread waits for its own to
+// complete (vmcnt covers stores on gfx9) before the barrier, so every tile is
+// in place before its workgroup's count, and the last workgroup, which reads
+// the tiles with device-coherent loads issued after it has seen the full
+// count, needs no fence on either side (a __threadfence here writes back and
+// invalidates the L2 of the workgroup's XCD, several microseconds).
 __device__ inline bool gram_arrive(unsigned* counter, unsigned total, int tid) {
   __shared__ int sh_last;
-  __threadfence();
+  __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
-  if (tid == 0) sh_last = atomicAdd(counter, 1u) == total - 1;
+  if (tid == 0)
+    sh_last = __hip_atomic_fetch_add(counter, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ==
+              total - 1;
   __syncthreads();
   if (!sh_last) return false;
-  __threadfence();
-  if (tid == 0) *counter = 0u;
+  if (tid == 0) __hip_atomic_store(counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   return true;
 }
 
@@ -1583,11 +1663,17 @@ __global__ __launch_bounds__(256, 2) void k_mode(Geom g, MttkrpPlan p, const T* 
     // the MTTKRP waves sharing the compute unit
     __builtin_amdgcn_s_setprio(3);
     double* lds = (double*)smem;
+    bool pre = false;
     if (sa.Gp) {
+      FirstFactor ff;
+      prestage_first_factor_load(sa, ff, threadIdx.x);
       gram_tile<4>(sa, lds, threadIdx.x, blockIdx.x);
+      __syncthreads();
+      prestage_first_factor_store(sa, ff, lds, threadIdx.x);
+      pre = ff.ok;
       if (!gram_arrive(sa.counter, (unsigned)ngram, threadIdx.x)) return;
     }
-    side_serial<4, MAXT>(sa, lds, dmax, threadIdx.x);
+    side_serial<4, MAXT>(sa, lds, dmax, threadIdx.x, pre);
     return;
   }
   const int w = blockIdx.x - ngram;
@@ -1599,18 +1685,29 @@ bool mode_fusable(const Geom& g, const SideArgs& sa) {
 }
 
 // The side step is latency-bound on one compute unit and slows down by
-// about a tenth when an MTTKRP workgroup shares that unit.  When the batch
-// is small enough that the MTTKRP, spread one workgroup per compute unit,
-// still ends before the side step (measured on the 256 x 256 x 20 FP64
-// batch: 26 us for 10.5 MB of X against 34 us for the side step; up to
-// about 12 MB of X), the launch holds at most one workgroup per compute
-// unit; larger batches keep the plan of about 512 workgroups.
+// about a tenth when an MTTKRP workgroup shares that unit, while an MTTKRP
+// workgroup costs about 11 us per outer index (FP64 operands; 17 us with
+// FP32 operands, whose core operand is still read in FP64) and is latency-
+// rather than throughput-bound.  Measured on the 256 x 256 x 20 batch
+// (side step about 33 us): with FP64 operands one workgroup per compute
+// unit wins while it leaves each workgroup at most two outer indices
+// (modes 1 and 2: 26-28 us of MTTKRP); otherwise (FP32 operands, the
+// temporal mode) one outer index per workgroup, up to four workgroups per
+// compute unit; larger batches keep the plan of about 512 workgroups.
 MttkrpPlan plan_mode(const Geom& g, int xdtype, const SideArgs& sa, int ncu) {
   const int nbp = (sa.Rpa * sa.Rpb + 15) / 16;
   const int ngram = sa.Gp ? nbp * (nbp + 1) / 2 : 1;
-  const int64_t xbytes = g.L * g.Rr * g.In * (xdtype == F64 ? 8 : (xdtype == F32 ? 4 : 2));
-  if (ncu > ngram && xbytes <= ((int64_t)12 << 20)) return plan_mttkrp(g, xdtype, ncu - ngram);
-  return plan_mttkrp(g, xdtype);
+  if (xdtype == F64 && ncu > ngram) {
+    const MttkrpPlan p = plan_mttkrp(g, xdtype, ncu - ngram);
+    if (p.upw <= 2) return p;
+  }
+  MttkrpPlan p = plan_mttkrp(g, xdtype);
+  const int64_t wg1 = (int64_t)p.mtiles * p.Kout;   // one outer index per workgroup
+  if (p.upw > 1 && wg1 <= 4 * (int64_t)ncu && !getenv("TRSTREAM_NSPLIT")) {
+    p.upw = 1;
+    p.nsplit = (int)p.Kout;
+  }
+  return p;
 }
 
 template <typename T, int NJ, int MAXT>
