@@ -182,34 +182,37 @@ __device__ inline int outer_index(const Geom& g, int64_t o, int q) {
 
 // Ring product of nfac slices from mode q0 on, at the indices of outer index
 // o, into the 16 x 16 LDS matrix M (zero padded); tmp is 256 doubles of
-// scratch.  Ends with a workgroup barrier.
+// scratch.  Every slice is staged in LDS with one load per thread (zero
+// padded), so a product is a fixed 16-term sum over LDS.  Ends with a
+// workgroup barrier.
 template <typename TC>
 __device__ inline void ring_product_lds(const Geom& g, const CoreView& cv, int64_t o, int q0,
                                         int nfac, double* M, double* tmp, int tid) {
   const int N = g.N;
+  const int a = tid >> 4, b = tid & 15;
   int q = q0;
   {
-    const int a = tid >> 4, b = tid & 15;
     const int Ra = g.R[q], Rb = g.R[q + 1 == N ? 0 : q + 1];
     const bool ok = a < Ra && b < Rb;
     const TC* G = (const TC*)cv.ptr[q] + (int64_t)outer_index(g, o, q) * cv.si[q];
     const double v = (double)G[ok ? a * cv.sr[q] + b * cv.ss[q] : 0];
     M[tid] = ok ? v : 0.0;
   }
-  __syncthreads();
   for (int j = 1; j < nfac; ++j) {
     q = q + 1 == N ? 0 : q + 1;
-    const int a = tid >> 4, c = tid & 15;
     const int Rq = g.R[q], Rc = g.R[q + 1 == N ? 0 : q + 1];
+    const bool ok = a < Rq && b < Rc;
     const TC* H = (const TC*)cv.ptr[q] + (int64_t)outer_index(g, o, q) * cv.si[q];
+    const double v = (double)H[ok ? a * cv.sr[q] + b * cv.ss[q] : 0];
+    tmp[tid] = ok ? v : 0.0;
+    __syncthreads();
     double acc = 0.0;
-    if (c < Rc)
-      for (int b = 0; b < Rq; ++b) acc += M[a * 16 + b] * (double)H[b * cv.sr[q] + c * cv.ss[q]];
-    tmp[tid] = acc;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) acc = fma(M[a * 16 + k], tmp[k * 16 + b], acc);
     __syncthreads();
-    M[tid] = tmp[tid];
-    __syncthreads();
+    M[tid] = acc;
   }
+  __syncthreads();
 }
 
 // X offset of (i_f = 0, i_n = 0) for outer index o of mode n.
@@ -264,8 +267,7 @@ __device__ inline void mttkrp_body(const Geom& g, const MttkrpPlan& p, const T* 
   double* Us = (double*)smem;               // [16][16]
   double* Vs = Us + 256;                    // [16][16]
   double* tmp = Vs + 256;                   // [256]
-  double* Pa = tmp + 256;                   // [16][dn] accumulated result
-  double* Ws = Pa + 16 * dn;                // [16][wst]
+  double* Ws = tmp + 256;                   // [16][wst]
   PT* Ys = (PT*)(Ws + 16 * wst);            // [16][dfp]
   PT* red = Ys + 16 * dfp;                  // [KS-1][16][dfp]
 
@@ -286,7 +288,9 @@ __device__ inline void mttkrp_body(const Geom& g, const MttkrpPlan& p, const T* 
   const int mrow = (int)(m0 + l16 < g.In ? m0 + l16 : g.In - 1);
   const bool mok = m0 + l16 < g.In;
   const int arow = (int)(mrow * p.sm);
-  for (int e = tid; e < 16 * dn; e += 256) Pa[e] = 0.0;
+  d4 pacc[4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) pacc[t] = d4{0, 0, 0, 0};
 
   for (int64_t o = o0; o < o1; ++o) {
     const T* __restrict__ Xo = X + outer_offset(g, o);
@@ -349,38 +353,69 @@ __device__ inline void mttkrp_body(const Geom& g, const MttkrpPlan& p, const T* 
       }
     }
     __syncthreads();
-    // W[m][s + Rn1 b] = sum_a U[s][a] Y[m][a + Rf b]
+    // Contraction with U and V on FP64 MFMAs (16x16x4; the K index a or b
+    // padded to 16 with zeros, U and V are zero-padded 16 x 16 in LDS):
+    //   W_b = Y_b U^T       (W[m][s + Rn1 b] = sum_a U[s][a] Y[m][a + Rf b]),
+    //   P_s += W_s V        (P[m][r + Rn s] += sum_b W[m][s + Rn1 b] V[b][r]),
+    // tile b and tile s owned by wave b % 4 and s % 4; P_s stays in
+    // registers across the chunk's outer indices.
     if (nU > 0) {
-      for (int e = tid; e < 16 * Rn1 * Rf1; e += 256) {
-        const int m = e / (Rn1 * Rf1), w = e - m * (Rn1 * Rf1);
-        const int s = w % Rn1, b = w / Rn1;
-        double acc2 = 0.0;
-        for (int a = 0; a < Rf; ++a) acc2 += Us[s * 16 + a] * (double)Ys[m * dfp + a + Rf * b];
-        Ws[m * wst + s + Rn1 * b] = acc2;
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int bb = wave + 4 * t;
+        if (bb < Rf1) {
+          d4 wt = {0, 0, 0, 0};
+#pragma unroll
+          for (int k0 = 0; k0 < 16; k0 += 4) {
+            const int ka = k0 + g4;
+            const double av = ka < Rf ? (double)Ys[l16 * dfp + ka + Rf * bb] : 0.0;
+            wt = mfma16(av, Us[l16 * 16 + ka], wt);
+          }
+#pragma unroll
+          for (int v = 0; v < 4; ++v)
+            if (l16 < Rn1) Ws[Acc<double>::row(lane, v) * wst + l16 + Rn1 * bb] = wt[v];
+        }
       }
       __syncthreads();
     }
-    // P[m][r + Rn s] += sum_b W[m][s + Rn1 b] V[b][r]
-    for (int e = tid; e < 16 * dn; e += 256) {
-      const int m = e / dn, c = e - m * dn;
-      const int r = c % Rn, s = c / Rn;
-      double val;
-      if (nV > 0) {
-        val = 0.0;
-        for (int b = 0; b < Rf1; ++b) {
-          const double w = nU > 0 ? Ws[m * wst + s + Rn1 * b] : (double)Ys[m * dfp + s + Rn1 * b];
-          val += w * Vs[b * 16 + r];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int ss = wave + 4 * t;
+      if (ss < Rn1) {
+        if (nV > 0) {
+#pragma unroll
+          for (int k0 = 0; k0 < 16; k0 += 4) {
+            const int kb = k0 + g4;
+            double av = 0.0;
+            if (kb < Rf1)
+              av = nU > 0 ? Ws[l16 * wst + ss + Rn1 * kb] : (double)Ys[l16 * dfp + ss + Rn1 * kb];
+            pacc[t] = mfma16(av, Vs[kb * 16 + l16], pacc[t]);
+          }
+        } else {
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int m = Acc<double>::row(lane, v);
+            double wv = 0.0;
+            if (l16 < Rn)
+              wv = nU > 0 ? Ws[m * wst + ss + Rn1 * l16] : (double)Ys[m * dfp + ss + Rn1 * l16];
+            pacc[t][v] += wv;
+          }
         }
-      } else {
-        val = nU > 0 ? Ws[m * wst + s + Rn1 * r] : (double)Ys[m * dfp + s + Rn1 * r];
       }
-      Pa[e] += val;
     }
     __syncthreads();
   }
-  for (int e = tid; e < 16 * dn; e += 256) {
-    const int m = e / dn;
-    if (m0 + m < g.In) part[((size_t)chunk * g.In + m0) * dn + e] = (PT)Pa[e];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    const int ss = wave + 4 * t;
+    if (ss < Rn1 && l16 < Rn) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int m = Acc<double>::row(lane, v);
+        if (m0 + m < g.In)
+          part[((size_t)chunk * g.In + m0 + m) * dn + l16 + Rn * ss] = (PT)pacc[t][v];
+      }
+    }
   }
 }
 
@@ -399,7 +434,7 @@ static hipError_t launch_mttkrp_t(const Geom& g, const MttkrpPlan& p, const void
   const int dfp = 16 * p.nbf;
   const int Rn1 = g.R[(g.n + 1) % g.N], Rf1 = g.R[(p.f + 1) % g.N];
   const int wst = 16 * ((Rn1 * Rf1 + 15) / 16);
-  const size_t lds = (size_t)(3 * 256 + 16 * g.d + 16 * wst) * sizeof(double) +
+  const size_t lds = (size_t)(3 * 256 + 16 * wst) * sizeof(double) +
                      (size_t)(16 * dfp) * p.KS * sizeof(PT);
   auto fn = k_mttkrp<T, TC, NJ>;
   if (lds > 65536) {
@@ -1718,7 +1753,7 @@ static hipError_t launch_mode_t(const Geom& g, const MttkrpPlan& p, const void* 
   const int dfp = 16 * p.nbf;
   const int Rn1 = g.R[(g.n + 1) % g.N], Rf1 = g.R[(p.f + 1) % g.N];
   const int wst = 16 * ((Rn1 * Rf1 + 15) / 16);
-  const size_t lmt = (size_t)(3 * 256 + 16 * g.d + 16 * wst) * sizeof(double) +
+  const size_t lmt = (size_t)(3 * 256 + 16 * wst) * sizeof(double) +
                      (size_t)(16 * dfp) * p.KS * sizeof(PT);
   const size_t lds = std::max(lmt, (size_t)SIDE_LDS_ALLOC * sizeof(double));
   auto fn = k_mode<T, double, NJ, MAXT>;
