@@ -369,6 +369,38 @@ tr_status ensure_temporal_probs(tr_stream* s, int64_t t) {
   return TR_OK;
 }
 
+// Q (+)= M for a d x d Gram matrix M already in the Q layout and exactly
+// symmetric (the sketched Grams), then Qinv = Q^{-1} when Qinv is given:
+// the 16x16-pivot-block MFMA Gauss-Jordan of the side kernel (one
+// workgroup of 16 waves, the Gram passed as a single ring-product factor
+// with R_a = d, R_b = 1) for d <= 192, the scalar elimination beyond.
+tr_status gram_update_invert(tr_stream* s, const double* M, int Ra, int Rb, double* Q,
+                             int accumulate, double* Qinv) {
+  const int d = Ra * Rb;
+  if (d <= 192) {
+    SideArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.nfac = 1;
+    a.fac[0] = M;
+    a.fr[0] = d;
+    a.fc[0] = 1;
+    a.cbuf[0] = s->chain[0];
+    a.cbuf[1] = s->chain[1];
+    a.Ra = d;
+    a.Rb = 1;
+    a.Q = Q;
+    a.accumulate = accumulate;
+    a.store_Q = 1;
+    a.Qinv = Qinv;
+    a.status = s->dstatus;
+    a.counter = s->sidecnt;
+    TR_HIP(launch_side(a, s->st));
+    return TR_OK;
+  }
+  TR_HIP(launch_invert_spd(M, Ra, Rb, Q, accumulate, 1, Qinv, s->dstatus, s->st, 1));
+  return TR_OK;
+}
+
 // One sketched P/Q increment of mode n (Alg. 5: P_n += X_S G_S, Q_n += G_S^T G_S
 // with the rescaling of the sketch), X of `t` slices, temporal rows Gt.
 tr_status sketch_increment(tr_stream* s, int n, const void* Xd, int64_t t, const double* Gt,
@@ -386,8 +418,9 @@ tr_status sketch_increment(tr_stream* s, int n, const void* Xd, int64_t t, const
   TR_HIP(launch_sample_rows(g, cv, s->idxs, m, lev ? (const double* const*)s->dprobs : nullptr,
                             wconst, s->SA, s->Sw, s->st));
   TR_HIP(launch_wgram(s->SA, s->Sw, m, g.d, s->Zb, s->st));
-  TR_HIP(launch_invert_spd(s->Zb, s->R[n], s->R[(n + 1) % N], s->Q[n], accumulate, 1,
-                           Minv_solve ? s->Minv : nullptr, s->dstatus, s->st, 1));
+  tr_status c = gram_update_invert(s, s->Zb, s->R[n], s->R[(n + 1) % N], s->Q[n], accumulate,
+                                   Minv_solve ? s->Minv : nullptr);
+  if (c != TR_OK) return c;
   SketchPlan sp = plan_sketch(g, m, s->dt);
   const size_t pb = (size_t)sp.nsplit * g.In * g.d * sp.psize;
   TR_HIP(ensure(&s->part, &s->part_bytes, pb));
@@ -439,8 +472,8 @@ tr_status sketch_update(tr_stream* s, const void* Xd, int64_t t_new, double* Gne
     TR_HIP(launch_sample_rows(g, cv, s->idxs, m, lev ? (const double* const*)s->dprobs : nullptr,
                               wconst, s->SA, s->Sw, s->st));
     TR_HIP(launch_wgram(s->SA, s->Sw, m, dN, s->Zb, s->st));
-    TR_HIP(launch_invert_spd(s->Zb, s->R[N - 1], s->R[0], nullptr, 0, 0, s->Minv, s->dstatus,
-                             s->st, 1));
+    tr_status c0 = gram_update_invert(s, s->Zb, s->R[N - 1], s->R[0], nullptr, 0, s->Minv);
+    if (c0 != TR_OK) return c0;
     SketchPlan sp = plan_sketch(g, m, s->dt);
     TR_HIP(ensure(&s->part, &s->part_bytes, (size_t)sp.nsplit * g.In * g.d * sp.psize));
     TR_HIP(launch_sketch_gemm(g, sp, Xd, s->dt, s->idxs, m, s->SA, s->Sw, s->part, s->st));
@@ -560,12 +593,13 @@ tr_status ksrft_increment(tr_stream* s, int n, const void* xhat, int64_t t, int 
     TR_HIP(launch_wgram(s->Ast, nullptr, m, d, s->Zb, s->st));
   else
     TR_HIP(launch_wgram(s->Ast, s->Sw2, 2 * (int64_t)m, d, s->Zb, s->st));
-  if (temporal)
-    TR_HIP(launch_invert_spd(s->Zb, s->R[n], s->R[(n + 1) % N], nullptr, 0, 0, s->Minv,
-                             s->dstatus, s->st, 1));
-  else
-    TR_HIP(launch_invert_spd(s->Zb, s->R[n], s->R[(n + 1) % N], s->Q[n], accumulate, 1,
-                             solve ? s->Minv : nullptr, s->dstatus, s->st, 1));
+  {
+    tr_status c0 = temporal
+                       ? gram_update_invert(s, s->Zb, s->R[n], s->R[(n + 1) % N], nullptr, 0, s->Minv)
+                       : gram_update_invert(s, s->Zb, s->R[n], s->R[(n + 1) % N], s->Q[n],
+                                            accumulate, solve ? s->Minv : nullptr);
+    if (c0 != TR_OK) return c0;
+  }
   SgemmPlan sp = plan_sgemm(g, m, 2 * d, s->dt);
   TR_HIP(ensure(&s->part, &s->part_bytes, (size_t)sp.nsplit * g.In * 2 * d * sp.psize));
   TR_HIP(launch_sgemm(g, sp, 2 * d, total, xhat, s->dt, s->idxs, m, s->Bst, s->part, s->st));

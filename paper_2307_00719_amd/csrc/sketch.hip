@@ -361,38 +361,73 @@ hipError_t launch_sketch_gemm(const Geom& g, const SketchPlan& p, const void* X,
 }
 
 // out[c1*d + c2] = sum_s w[s] A[s][c1] A[s][c2] (w == nullptr: weights 1),
-// 16x16 output tile per workgroup, rows staged 64 at a time.
-__global__ __launch_bounds__(256) void k_wgram(const double* __restrict__ A,
-                                               const double* __restrict__ w, int64_t rows, int d,
-                                               double* __restrict__ out) {
-  __shared__ double A1[64][17], A2[64][17];
-  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
-  const int c1 = blockIdx.y * 16 + ty, c2 = blockIdx.x * 16 + tx;
-  double s0 = 0.0, s1 = 0.0;
-  for (int64_t i0 = 0; i0 < rows; i0 += 64) {
-    for (int e = threadIdx.x; e < 64 * 16; e += 256) {
-      const int r = e >> 4, c = e & 15;
-      const int64_t i = i0 + r;
-      const int ca = blockIdx.y * 16 + c, cb = blockIdx.x * 16 + c;
-      const double wi = (i < rows && w) ? w[i] : 1.0;
-      A1[r][c] = (i < rows && ca < d) ? wi * A[i * d + ca] : 0.0;
-      A2[r][c] = (i < rows && cb < d) ? A[i * d + cb] : 0.0;
-    }
-    __syncthreads();
-#pragma unroll 8
-    for (int r = 0; r < 64; r += 2) {
-      s0 += A1[r][ty] * A2[r][tx];
-      s1 += A1[r + 1][ty] * A2[r + 1][tx];
-    }
-    __syncthreads();
+// the weighted Gram of the sampled rows (the sketched Q_n of Alg. 5).  One
+// workgroup of 16 waves per upper-triangle 16x16 tile: wave j takes the
+// k-steps (4 rows each) j, j+16, ... on FP64 16x16x4 MFMAs with 8 k-steps of
+// loads in flight and two accumulators; the 16 wave sums are added in LDS
+// in a fixed order and the tile and its mirror are written, so the result
+// is exactly symmetric.
+constexpr int WG_WAVES = 16;
+
+__global__ __launch_bounds__(64 * WG_WAVES) void k_wgram(const double* __restrict__ A,
+                                                         const double* __restrict__ w,
+                                                         int64_t rows, int d,
+                                                         double* __restrict__ out) {
+  __shared__ double red[WG_WAVES][256];
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int l16 = lane & 15, g4 = lane >> 4;
+  const int nb = (d + 15) >> 4;
+  int rb = 0, cb = blockIdx.x;
+  while (cb >= nb - rb) {
+    cb -= nb - rb;
+    ++rb;
   }
-  if (c1 < d && c2 < d) out[(size_t)c1 * d + c2] = s0 + s1;
+  cb += rb;
+  const int c1 = min(rb * 16 + l16, d - 1), c2 = min(cb * 16 + l16, d - 1);
+  const int64_t nks = (rows + 3) / 4, rl = rows > 0 ? rows - 1 : 0;
+  constexpr int KB = 8;
+  d4s acc0 = {0, 0, 0, 0}, acc1 = {0, 0, 0, 0};
+  for (int64_t k0 = wave; k0 < nks; k0 += KB * WG_WAVES) {
+    double av[KB], bv[KB];
+#pragma unroll
+    for (int q = 0; q < KB; ++q) {
+      const int64_t i = (k0 + WG_WAVES * q) * 4 + g4;
+      const int64_t ic = i < rows ? i : rl;
+      const double wi = w ? w[ic] : 1.0;
+      const double xa = A[ic * d + c1], xb = A[ic * d + c2];
+      const bool ok = i < rows;
+      av[q] = ok ? wi * xa : 0.0;
+      bv[q] = ok ? xb : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < KB; q += 2) {
+      acc0 = mfma_s(av[q], bv[q], acc0);
+      acc1 = mfma_s(av[q + 1], bv[q + 1], acc1);
+    }
+  }
+#pragma unroll
+  for (int v = 0; v < 4; ++v) red[wave][SAcc<double>::row(lane, v) * 16 + l16] = acc0[v] + acc1[v];
+  __syncthreads();
+  if (tid < 256) {
+    double sum = 0.0;
+#pragma unroll
+    for (int j = 0; j < WG_WAVES; ++j) sum += red[j][tid];
+    const int r = rb * 16 + (tid >> 4), c = cb * 16 + (tid & 15);
+    // on a diagonal tile only the upper entry of each pair writes (both
+    // positions): one writer per element, exactly symmetric
+    if (r < d && c < d && r <= c) {
+      out[(size_t)r * d + c] = sum;
+      out[(size_t)c * d + r] = sum;
+    }
+  }
 }
 
 hipError_t launch_wgram(const double* A, const double* w, int64_t rows, int d, double* out,
                         hipStream_t st) {
-  const int tiles = (d + 15) / 16;
-  hipLaunchKernelGGL(k_wgram, dim3(tiles, tiles), dim3(256), 0, st, A, w, rows, d, out);
+  const int nb = (d + 15) / 16;
+  hipLaunchKernelGGL(k_wgram, dim3(nb * (nb + 1) / 2), dim3(64 * WG_WAVES), 0, st, A, w, rows, d,
+                     out);
   return hipGetLastError();
 }
 
