@@ -1911,22 +1911,34 @@ hipError_t launch_check_finite(const void* x, int dt, int64_t n, int* flag, hipS
 }
 
 // ---------------------------------------------------------------------------
-// Reconstruction error: per workgroup, JT columns j of the temporal-mode
+// Reconstruction error: per workgroup, 16 columns j of the temporal-mode
 // unfolding X_[N] (j = lin(i_0..i_{N-2})), all T slices:
 //   Xhat[j, t] = sum_c G_{N(2)}[t, c] G^{!=N}_[2][j, c]
-// (the identity X_[N] = G_{N(2)} (G^{!=N}_[2])^T of eq. tr_als).
+// (the identity X_[N] = G_{N(2)} (G^{!=N}_[2])^T of eq. tr_als).  The 16
+// subchain rows are formed in LDS; the product with the temporal core runs
+// on FP64 16x16x4 MFMAs (A = subchain rows from LDS, B = the temporal core
+// from a slice-major FP64 copy GNs[t * d + c]), one 16-slice tile per wave
+// at a time with 8 k-steps of loads in flight, and the squared residual and
+// norm are taken from the accumulators.
 // ---------------------------------------------------------------------------
+constexpr int RECON_JT = 16;
+
 template <typename TX, typename TC, int RM>
-__global__ __launch_bounds__(256) void k_recon_err(Geom g, int JT, const TX* __restrict__ X,
-                                                   CoreView cv, double* __restrict__ wg_out) {
+__global__ __launch_bounds__(256) void k_recon_err(Geom g, const TX* __restrict__ X, CoreView cv,
+                                                   const double* __restrict__ GNs,
+                                                   double* __restrict__ wg_out) {
+  constexpr int JT = RECON_JT;
   extern __shared__ __align__(16) char smem[];
   double* Bt = (double*)smem;                        // [JT][d+1]
   int* idx = (int*)(Bt + (size_t)JT * (g.d + 1));    // [JT][MAXN]
   __shared__ double red[2][256];
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int l16 = lane & 15, g4 = lane >> 4;
   const int d = g.d;
   const int Rn = g.R[g.n], Rn1 = g.R[0];
   const int64_t J = g.L;                             // columns of X_[N]
+  const int64_t T = g.In;
   const int64_t j0 = (int64_t)blockIdx.x * JT;
   for (int jj = tid; jj < JT; jj += 256) {
     const int64_t j = j0 + jj;
@@ -1935,30 +1947,50 @@ __global__ __launch_bounds__(256) void k_recon_err(Geom g, int JT, const TX* __r
   __syncthreads();
   for (int w = tid; w < JT * Rn1; w += 256) {
     const int jj = w / Rn1, s = w - jj * Rn1;
+    TC v[RM];
     if (j0 + jj < J) {
-      TC v[RM];
       subchain_row<TC, RM>(g, cv, idx + jj * MAXN, s, v);
+    } else {
 #pragma unroll
-      for (int r = 0; r < RM; ++r)
-        if (r < Rn) Bt[jj * (d + 1) + r + Rn * s] = (double)v[r];
+      for (int r = 0; r < RM; ++r) v[r] = TC(0);
     }
+#pragma unroll
+    for (int r = 0; r < RM; ++r)
+      if (r < Rn) Bt[jj * (d + 1) + r + Rn * s] = (double)v[r];
   }
   __syncthreads();
-  const int jl = tid % JT, tq = tid / JT, TQ = 256 / JT;
-  const int64_t j = j0 + jl;
+  const int nks = (d + 3) >> 2;
+  const int64_t ntt = (T + 15) >> 4;
   double err = 0.0, nrm = 0.0;
-  const TC* GN = (const TC*)cv.ptr[g.n];
-  const int64_t sr = cv.sr[g.n], si = cv.si[g.n], ss = cv.ss[g.n];
-  if (j < J) {
-    for (int64_t t = tq; t < g.In; t += TQ) {
-      double xh = 0.0;
-      for (int s = 0; s < Rn1; ++s)
-        for (int r = 0; r < Rn; ++r)
-          xh += Bt[jl * (d + 1) + r + Rn * s] * (double)GN[r * sr + t * si + s * ss];
-      const double x = (double)X[j + J * t];
-      const double e = x - xh;
-      err += e * e;
-      nrm += x * x;
+  for (int64_t tt = wave; tt < ntt; tt += 4) {
+    const int64_t t = tt * 16 + l16;
+    const int64_t tc = t < T ? t : T - 1;
+    const double* __restrict__ gcol = GNs + tc * d;
+    d4 acc = {0, 0, 0, 0};
+    for (int k0 = 0; k0 < nks; k0 += 8) {
+      double av[8], bv[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const int k = (k0 + q) * 4 + g4;
+        const bool ok = k < d && k0 + q < nks;
+        const int kc = k < d ? k : d - 1;
+        const double b = gcol[kc];
+        av[q] = ok ? Bt[l16 * (d + 1) + kc] : 0.0;
+        bv[q] = ok && t < T ? b : 0.0;
+      }
+#pragma unroll
+      for (int q = 0; q < 8; ++q) acc = mfma16(av[q], bv[q], acc);
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int jr = Acc<double>::row(lane, v);
+      const int64_t j = j0 + jr;
+      if (j < J && t < T) {
+        const double x = (double)X[j + J * t];
+        const double e = x - acc[v];
+        err += e * e;
+        nrm += x * x;
+      }
     }
   }
   red[0][tid] = err;
@@ -1977,36 +2009,35 @@ __global__ __launch_bounds__(256) void k_recon_err(Geom g, int JT, const TX* __r
   }
 }
 
-static int recon_jt(int d) { return d <= 64 ? 64 : (d <= 128 ? 32 : 16); }
-
-int recon_err_blocks(const Geom& g) {
-  const int JT = recon_jt(g.d);
-  return (int)((g.L + JT - 1) / JT);
-}
+int recon_err_blocks(const Geom& g) { return (int)((g.L + RECON_JT - 1) / RECON_JT); }
 
 template <typename TX, typename TC>
 static hipError_t launch_recon_t(const Geom& g, const void* X, const CoreView& cv,
-                                 double* wg_out, int* nwg, hipStream_t st) {
-  const int JT = recon_jt(g.d);
+                                 const double* GNs, double* wg_out, int* nwg, hipStream_t st) {
   const int blocks = recon_err_blocks(g);
-  const size_t lds = (size_t)JT * (g.d + 1) * sizeof(double) + (size_t)JT * MAXN * sizeof(int);
+  const size_t lds =
+      (size_t)RECON_JT * (g.d + 1) * sizeof(double) + (size_t)RECON_JT * MAXN * sizeof(int);
   int rmax = 1;
   for (int k = 0; k < g.N; ++k) rmax = g.R[k] > rmax ? g.R[k] : rmax;
   if (rmax <= 8)
-    hipLaunchKernelGGL((k_recon_err<TX, TC, 8>), dim3(blocks), dim3(256), lds, st, g, JT,
-                       (const TX*)X, cv, wg_out);
+    hipLaunchKernelGGL((k_recon_err<TX, TC, 8>), dim3(blocks), dim3(256), lds, st, g,
+                       (const TX*)X, cv, GNs, wg_out);
   else
-    hipLaunchKernelGGL((k_recon_err<TX, TC, 16>), dim3(blocks), dim3(256), lds, st, g, JT,
-                       (const TX*)X, cv, wg_out);
+    hipLaunchKernelGGL((k_recon_err<TX, TC, 16>), dim3(blocks), dim3(256), lds, st, g,
+                       (const TX*)X, cv, GNs, wg_out);
   *nwg = blocks;
   return hipGetLastError();
 }
 
 hipError_t launch_recon_err(const Geom& g, const void* X, int xdt, const CoreView& cv, int cdt,
-                            double* wg_out, int* nwg, hipStream_t st) {
-  if (xdt == F64 && cdt == F64) return launch_recon_t<double, double>(g, X, cv, wg_out, nwg, st);
-  if (xdt == F32 && cdt == F32) return launch_recon_t<float, float>(g, X, cv, wg_out, nwg, st);
-  if (xdt == F32 && cdt == F64) return launch_recon_t<float, double>(g, X, cv, wg_out, nwg, st);
+                            const double* GNs, double* wg_out, int* nwg, hipStream_t st) {
+  if (g.In <= 0 || g.L <= 0 || !GNs) return hipErrorInvalidValue;
+  if (xdt == F64 && cdt == F64)
+    return launch_recon_t<double, double>(g, X, cv, GNs, wg_out, nwg, st);
+  if (xdt == F32 && cdt == F32)
+    return launch_recon_t<float, float>(g, X, cv, GNs, wg_out, nwg, st);
+  if (xdt == F32 && cdt == F64)
+    return launch_recon_t<float, double>(g, X, cv, GNs, wg_out, nwg, st);
   return hipErrorInvalidValue;
 }
 

@@ -1110,7 +1110,8 @@ tr_status tr_reconstruct_error(tr_stream* s, const double* X_all, int64_t t_all,
     s->wg_n = (size_t)nwg * 2;
   }
   int got = 0;
-  TR_HIP(launch_recon_err(g, Xd, F64, state_view(s, s->G[N - 1]), F64, s->wg, &got, s->st));
+  TR_HIP(launch_recon_err(g, Xd, F64, state_view(s, s->G[N - 1]), F64, s->G[N - 1], s->wg, &got,
+                          s->st));
   TR_HIP(launch_sum_pairs(s->wg, got, s->pair, s->st));
   double h[2];
   TR_HIP(hipMemcpyAsync(h, s->pair, sizeof(h), hipMemcpyDeviceToHost, s->st));
@@ -1513,8 +1514,14 @@ tr_status tr_fit_loss_fwd(int32_t N, const int64_t* dims, const int32_t* ranks, 
   char* base = (char*)ws;
   Geom g = make_geom(N, dims, ranks, N - 1);
   CoreView cv = colmajor_view(N, dims, ranks, cores);
+  // the temporal core as slice-major FP64 rows for the MFMA product
+  double* gns = (double*)(base + w.slices[N - 1]);
+  const int RaN = ranks[N - 1], RbN = ranks[0];
+  if (launch_core_to_slices(cores[N - 1], dt, 1, RaN, (int64_t)RaN * dims[N - 1], dims[N - 1], RaN,
+                            RbN, gns, st) != hipSuccess)
+    return TR_ERR_DEVICE;
   int nwg = 0;
-  if (launch_recon_err(g, X, dt, cv, dt, (double*)(base + w.wg), &nwg, st) != hipSuccess)
+  if (launch_recon_err(g, X, dt, cv, dt, gns, (double*)(base + w.wg), &nwg, st) != hipSuccess)
     return TR_ERR_DEVICE;
   if (launch_sum_pairs((double*)(base + w.wg), nwg, (double*)(base + w.pair), st) != hipSuccess)
     return TR_ERR_DEVICE;

@@ -128,9 +128,12 @@ hipError_t launch_cast(const void* src, int sdt, void* dst, int ddt, int64_t n, 
 
 // Per-workgroup sums of (X - Xhat)^2 and X^2 over a tensor whose last mode
 // has T slices, with Xhat from the cores in cv (temporal core slices are
-// the T rows of core N-1); writes nwg pairs into wg_out and returns nwg.
+// the T rows of core N-1); GNs is the temporal core as slice-major FP64
+// rows (GNs[t * d + r + R_{N-1} s] = G_{N-1}[r, t, s]); writes nwg pairs
+// into wg_out and returns nwg.
 hipError_t launch_recon_err(const Geom& gN, const void* X, int xdt, const CoreView& cv,
-                            int cdt, double* wg_out, int* nwg_out, hipStream_t st);
+                            int cdt, const double* GNs, double* wg_out, int* nwg_out,
+                            hipStream_t st);
 int recon_err_blocks(const Geom& gN);
 
 // out[0..1] = fixed-order sums of the pairs in wg_out.
