@@ -1940,23 +1940,58 @@ __global__ __launch_bounds__(256) void k_recon_err(Geom g, const TX* __restrict_
   const int64_t J = g.L;                             // columns of X_[N]
   const int64_t T = g.In;
   const int64_t j0 = (int64_t)blockIdx.x * JT;
-  for (int jj = tid; jj < JT; jj += 256) {
-    const int64_t j = j0 + jj;
-    if (j < J) decode_column(g, j, idx + jj * MAXN);
-  }
-  __syncthreads();
-  for (int w = tid; w < JT * Rn1; w += 256) {
-    const int jj = w / Rn1, s = w - jj * Rn1;
-    TC v[RM];
-    if (j0 + jj < J) {
-      subchain_row<TC, RM>(g, cv, idx + jj * MAXN, s, v);
-    } else {
+  // S(j) = G_0(i_0) V(o) with j = i_0 + I_0 o and V(o) the ring product of
+  // the slices of modes 1..N-2 at o.  When the workgroup's columns share one
+  // o, V(o) is formed once (in red[0], scratch red[1]) and each row tile is
+  // a 16x16x16 product on MFMAs (wave w: columns 4w..4w+3); otherwise each
+  // subchain row is formed on its own.
+  const int64_t I0 = g.I[0];
+  const int64_t oA = j0 / I0, oB = (j0 + JT - 1 < J ? j0 + JT - 1 : J - 1) / I0;
+  if (oA == oB) {
+    double* Vs = red[0];
+    ring_product_lds<TC>(g, cv, oA, 1, g.N - 2, Vs, red[1], tid);
+    const int R0 = g.R[0], R1 = g.R[1];
+    const TC* __restrict__ G0 = (const TC*)cv.ptr[0];
+    const int64_t sr0 = cv.sr[0], si0 = cv.si[0], ss0 = cv.ss[0];
 #pragma unroll
-      for (int r = 0; r < RM; ++r) v[r] = TC(0);
+    for (int t4 = 0; t4 < 4; ++t4) {
+      const int jj = wave * 4 + t4;
+      const int64_t j = j0 + jj;
+      const int64_t i0 = j < J ? j - oA * I0 : 0;
+      d4 acc = {0, 0, 0, 0};
+#pragma unroll
+      for (int k0 = 0; k0 < 16; k0 += 4) {
+        const int b = k0 + g4;
+        const bool ok = l16 < R0 && b < R1 && j < J;
+        const double av =
+            (double)G0[i0 * si0 + (ok ? l16 : 0) * sr0 + (ok ? b : 0) * ss0];
+        acc = mfma16(ok ? av : 0.0, Vs[b * 16 + l16], acc);
+      }
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int sv = Acc<double>::row(lane, v);
+        if (sv < R0 && l16 < Rn) Bt[jj * (d + 1) + l16 + Rn * sv] = acc[v];
+      }
     }
+  } else {
+    for (int jj = tid; jj < JT; jj += 256) {
+      const int64_t j = j0 + jj;
+      if (j < J) decode_column(g, j, idx + jj * MAXN);
+    }
+    __syncthreads();
+    for (int w = tid; w < JT * Rn1; w += 256) {
+      const int jj = w / Rn1, s = w - jj * Rn1;
+      TC v[RM];
+      if (j0 + jj < J) {
+        subchain_row<TC, RM>(g, cv, idx + jj * MAXN, s, v);
+      } else {
 #pragma unroll
-    for (int r = 0; r < RM; ++r)
-      if (r < Rn) Bt[jj * (d + 1) + r + Rn * s] = (double)v[r];
+        for (int r = 0; r < RM; ++r) v[r] = TC(0);
+      }
+#pragma unroll
+      for (int r = 0; r < RM; ++r)
+        if (r < Rn) Bt[jj * (d + 1) + r + Rn * s] = (double)v[r];
+    }
   }
   __syncthreads();
   const int nks = (d + 3) >> 2;
