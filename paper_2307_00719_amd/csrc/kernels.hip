@@ -759,6 +759,30 @@ __global__ __launch_bounds__(TG* TG) void k_invert_spd(const double* __restrict_
   if (bad && tid == 0 && status) status[0] = 1;
 }
 
+// Q-layout assembly alone (no inverse), one thread per element:
+//   Q[r + Ra s, r' + Ra s'] (+)= M[s + Rb s', r + Ra r']
+// with M the Rb^2 x Ra^2 Gram-chain product (row-major).
+__global__ __launch_bounds__(256) void k_assemble_q(const double* __restrict__ M, int Ra, int Rb,
+                                                    double* __restrict__ Q, int accumulate) {
+  const int d = Ra * Rb;
+  const int e = blockIdx.x * 256 + threadIdx.x;
+  if (e >= d * d) return;
+  const int gi = e / d, gj = e - gi * d;
+  const int r = gi % Ra, s1 = gi / Ra, r2 = gj % Ra, s2 = gj / Ra;
+  double v = M[(size_t)(s1 + Rb * s2) * (Ra * Ra) + (r + Ra * r2)];
+  if (accumulate) v += Q[e];
+  Q[e] = v;
+}
+
+hipError_t launch_assemble_q(const double* M, int Ra, int Rb, double* Q, int accumulate,
+                             hipStream_t st) {
+  const int d = Ra * Rb;
+  if (d <= 0 || d > 256) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_assemble_q, dim3((d * d + 255) / 256), dim3(256), 0, st, M, Ra, Rb, Q,
+                     accumulate);
+  return hipGetLastError();
+}
+
 hipError_t launch_invert_spd(const double* M, int Ra, int Rb, double* Q, int accumulate,
                              int store_Q, double* Qinv, int* status, hipStream_t st,
                              int m_plain) {

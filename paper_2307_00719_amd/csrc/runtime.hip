@@ -916,8 +916,7 @@ tr_status tr_stream_init(const tr_config* cfg, const double* X_init, int64_t t_i
     hipError_t he;
     const double* M = chain_product(s, n, s->E[N - 1], &he);
     TR_HIP(he);
-    TR_HIP(launch_invert_spd(M, s->R[n], s->R[(n + 1) % N], s->Q[n], 0, 1, nullptr, nullptr,
-                             s->st));
+    TR_HIP(launch_assemble_q(M, s->R[n], s->R[(n + 1) % N], s->Q[n], 0, s->st));
   }
   TR_HIP(hipStreamSynchronize(s->st));
   s->copy_pending = false;
@@ -1487,8 +1486,7 @@ static tr_status gram_chain_into(int32_t N, const int64_t* dims, const int32_t* 
     pp ^= 1;
     cols = c2;
   }
-  if (launch_invert_spd(cur, ranks[n], ranks[(n + 1) % N], Q_dev, 0, 1, nullptr, nullptr, st) !=
-      hipSuccess)
+  if (launch_assemble_q(cur, ranks[n], ranks[(n + 1) % N], Q_dev, 0, st) != hipSuccess)
     return TR_ERR_DEVICE;
   return TR_OK;
 }

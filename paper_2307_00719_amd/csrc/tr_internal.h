@@ -84,6 +84,10 @@ hipError_t launch_matmul(const double* A, const double* B, double* C, int d1, in
 // inverted in place by Gauss-Jordan into Qinv.  status[0] is set to 1 on a
 // non-positive or tiny pivot.
 // With m_plain = 1, M is already a d x d matrix in the Q layout.
+// Q (+)= the Q-layout image of the Gram-chain product M (Rb^2 x Ra^2),
+// no inverse.
+hipError_t launch_assemble_q(const double* M, int Ra, int Rb, double* Q, int accumulate,
+                             hipStream_t st);
 hipError_t launch_invert_spd(const double* M, int Ra, int Rb, double* Q, int accumulate,
                              int store_Q, double* Qinv, int* status, hipStream_t st,
                              int m_plain = 0);
