@@ -2131,7 +2131,10 @@ hipError_t launch_sum_pairs(const double* wg_out, int nwg, double* out, hipStrea
 
 // ---------------------------------------------------------------------------
 // Fit-loss gradient assembly: out = scale * (G_(2) Q - P) in the caller's
-// core layout (strides sr, si, ss) and dtype.
+// core layout (strides sr, si, ss) and dtype.  Workgroup: 16 rows i x 64
+// columns; the 16 rows of G_(2) are staged in LDS (FP64), the product with
+// Q runs on FP64 16x16x4 MFMAs (wave w: columns 16w..16w+15 of the block,
+// 8 k-steps of Q loads in flight), P is subtracted from the accumulators.
 // ---------------------------------------------------------------------------
 template <typename TC>
 __global__ __launch_bounds__(256) void k_grad_combine(const TC* __restrict__ G, int64_t sr,
@@ -2140,31 +2143,59 @@ __global__ __launch_bounds__(256) void k_grad_combine(const TC* __restrict__ G, 
                                                       const double* __restrict__ Q,
                                                       const double* __restrict__ P,
                                                       double scale, TC* __restrict__ out) {
+  extern __shared__ double Gs[];                       // [16][d + 1]
   const int d = Ra * Rb;
-  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (e >= In * d) return;
-  const int64_t i = e / d;
-  const int c2 = (int)(e - i * d);
-  double s = 0.0;
-  for (int c = 0; c < d; ++c) {
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int l16 = lane & 15, g4 = lane >> 4;
+  const int64_t i0 = (int64_t)blockIdx.x * 16;
+  for (int e = tid; e < 16 * d; e += 256) {
+    const int ii = e / d, c = e - ii * d;
     const int r = c % Ra, q = c / Ra;
-    s += (double)G[r * sr + i * si + q * ss] * Q[(size_t)c * d + c2];
+    const int64_t i = i0 + ii;
+    Gs[ii * (d + 1) + c] = i < In ? (double)G[r * sr + i * si + q * ss] : 0.0;
   }
-  s -= P[i * d + c2];
+  __syncthreads();
+  const int c2 = blockIdx.y * 64 + wave * 16 + l16;
+  if (blockIdx.y * 64 + wave * 16 >= d) return;
+  const int c2c = c2 < d ? c2 : d - 1;
+  const int nks = (d + 3) >> 2;
+  d4 acc = {0, 0, 0, 0};
+  for (int k0 = 0; k0 < nks; k0 += 8) {
+    double av[8], bv[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int k = (k0 + q) * 4 + g4;
+      const bool ok = k < d && k0 + q < nks;
+      const int kc = k < d ? k : d - 1;
+      const double b = Q[(size_t)kc * d + c2c];
+      av[q] = ok ? Gs[l16 * (d + 1) + kc] : 0.0;
+      bv[q] = ok ? b : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < 8; ++q) acc = mfma16(av[q], bv[q], acc);
+  }
+  if (c2 >= d) return;
   const int r2 = c2 % Ra, q2 = c2 / Ra;
-  out[r2 * sr + i * si + q2 * ss] = (TC)(scale * s);
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int64_t i = i0 + Acc<double>::row(lane, v);
+    if (i < In) out[r2 * sr + i * si + q2 * ss] = (TC)(scale * (acc[v] - P[i * d + c2]));
+  }
 }
 
 hipError_t launch_grad_combine(const void* Gsrc, int cdt, int64_t sr, int64_t si, int64_t ss,
                                int64_t In, int Ra, int Rb, const double* Q, const double* P,
                                double scale, void* out, hipStream_t st) {
-  const int64_t n = In * Ra * Rb;
-  dim3 grid((unsigned)((n + 255) / 256));
+  const int d = Ra * Rb;
+  if (In <= 0 || d <= 0 || d > 256) return hipErrorInvalidValue;
+  dim3 grid((unsigned)((In + 15) / 16), (unsigned)((d + 63) / 64));
+  const size_t lds = (size_t)16 * (d + 1) * sizeof(double);
   if (cdt == F64)
-    hipLaunchKernelGGL(k_grad_combine<double>, grid, dim3(256), 0, st, (const double*)Gsrc, sr,
+    hipLaunchKernelGGL(k_grad_combine<double>, grid, dim3(256), lds, st, (const double*)Gsrc, sr,
                        si, ss, In, Ra, Rb, Q, P, scale, (double*)out);
   else
-    hipLaunchKernelGGL(k_grad_combine<float>, grid, dim3(256), 0, st, (const float*)Gsrc, sr, si,
+    hipLaunchKernelGGL(k_grad_combine<float>, grid, dim3(256), lds, st, (const float*)Gsrc, sr, si,
                        ss, In, Ra, Rb, Q, P, scale, (float*)out);
   return hipGetLastError();
 }
