@@ -239,7 +239,7 @@ __device__ inline int64_t outer_offset(const Geom& g, int64_t o) {
 // The K parts are summed in LDS in a fixed order, then U and V are applied
 // in FP64 and the result accumulated over the chunk.
 // ---------------------------------------------------------------------------
-template <typename T, typename TC, int NJ>
+template <typename T, typename TC, int NJ, int BQ = 0>
 __device__ inline void mttkrp_body(const Geom& g, const MttkrpPlan& p, const T* __restrict__ X,
                                    const CoreView& cv, typename Acc<T>::type* __restrict__ part,
                                    int chunk, int mtile, char* smem) {
@@ -291,6 +291,23 @@ __device__ inline void mttkrp_body(const Geom& g, const MttkrpPlan& p, const T* 
   d4 pacc[4];
 #pragma unroll
   for (int t = 0; t < 4; ++t) pacc[t] = d4{0, 0, 0, 0};
+  // BQ > 0 (Q <= BQ, checked by the launcher): the wave's G_f operands are
+  // the same for every outer index, so they are loaded once into registers
+  // and only the X tile is loaded per outer index
+  T bres[BQ > 0 ? BQ : 1][NJ];
+  if constexpr (BQ > 0) {
+#pragma unroll
+    for (int q = 0; q < BQ; ++q) {
+      const int k = kbase + q;
+      const bool ok = q < Q && k < If;
+      const int kcl = k < If ? k : If - 1;
+#pragma unroll
+      for (int j = 0; j < NJ; ++j) {
+        const TC b = Gf[kcl * fsi + boff[j]];
+        bres[q][j] = ok ? (T)b : T(0);
+      }
+    }
+  }
 
   for (int64_t o = o0; o < o1; ++o) {
     const T* __restrict__ Xo = X + outer_offset(g, o);
@@ -302,8 +319,24 @@ __device__ inline void mttkrp_body(const Geom& g, const MttkrpPlan& p, const T* 
     V4 acc[NJ];
 #pragma unroll
     for (int j = 0; j < NJ; ++j) acc[j] = V4{0, 0, 0, 0};
+    if constexpr (BQ > 0) {
+      T av[BQ];
+#pragma unroll
+      for (int q = 0; q < BQ; ++q) {
+        const int k = kbase + q;
+        const bool ok = q < Q && k < If;
+        const int kcl = k < If ? k : If - 1;
+        const T x = Xo[arow + kcl * sf];
+        av[q] = ok && mok ? x : T(0);
+      }
+#pragma unroll
+      for (int q = 0; q < BQ; ++q) {
+#pragma unroll
+        for (int j = 0; j < NJ; ++j) acc[j] = mfma16(av[q], bres[q][j], acc[j]);
+      }
+    }
 #pragma unroll 1
-    for (int kc = 0; kc < Q; kc += KG) {
+    for (int kc = 0; kc < (BQ > 0 ? 0 : Q); kc += KG) {
       T av[KG], bv[KG][NJ];
 #pragma unroll
       for (int q = 0; q < KG; ++q) {
@@ -419,12 +452,12 @@ __device__ inline void mttkrp_body(const Geom& g, const MttkrpPlan& p, const T* 
   }
 }
 
-template <typename T, typename TC, int NJ>
+template <typename T, typename TC, int NJ, int BQ>
 __global__ __launch_bounds__(256, 2) void k_mttkrp(Geom g, MttkrpPlan p, const T* __restrict__ X,
                                                    CoreView cv,
                                                    typename Acc<T>::type* __restrict__ part) {
   extern __shared__ __align__(16) char smem[];
-  mttkrp_body<T, TC, NJ>(g, p, X, cv, part, blockIdx.x, blockIdx.y, smem);
+  mttkrp_body<T, TC, NJ, BQ>(g, p, X, cv, part, blockIdx.x, blockIdx.y, smem);
 }
 
 template <typename T, typename TC, int NJ>
@@ -436,7 +469,12 @@ static hipError_t launch_mttkrp_t(const Geom& g, const MttkrpPlan& p, const void
   const int wst = 16 * ((Rn1 * Rf1 + 15) / 16);
   const size_t lds = (size_t)(3 * 256 + 16 * wst) * sizeof(double) +
                      (size_t)(16 * dfp) * p.KS * sizeof(PT);
-  auto fn = k_mttkrp<T, TC, NJ>;
+  // FP32 operands with at most 16 k-steps per lane group: the G_f operands
+  // stay in registers across the outer indices (64 VGPRs at NJ = 4)
+  auto fn = k_mttkrp<T, TC, NJ, 0>;
+  if constexpr (sizeof(T) == 4) {
+    if (p.Q <= 16) fn = k_mttkrp<T, TC, NJ, 16>;
+  }
   if (lds > 65536) {
     hipError_t e = hipFuncSetAttribute((const void*)fn,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
