@@ -212,7 +212,75 @@ def cpu_baseline(w, budget_s):
             f"({done * w.t_new} slices, {el:.1f} s)", "rel_fit_error": err, "batches": done}
 
 
+def pmc_summary(fetch_dir, write_dir):
+    """Turns two rocprofv3 counter runs of this script (``--pmc FETCH_SIZE``,
+    then ``--pmc WRITE_SIZE``, each with ``--steps 5 --warmup 2 --no-cpu
+    --no-extra``) into profiles/mode_c2_{f64,f32}_pmc.json: HBM bytes per
+    launch of the fused per-mode kernel.  Counter KiB are scaled by what the
+    same counters read for torch's FP64 -> FP32 copy of the whole stream
+    (known bytes: 8 and 4 per element)."""
+    import csv
+    import glob
+
+    def rows(d):
+        fs = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)
+        if not fs:
+            raise SystemExit(f"no counter_collection.csv under {d}")
+        out = []
+        for f in fs:
+            out += list(csv.DictReader(open(f)))
+        return out
+
+    def grid(r):
+        return int(r.get("Grid_Size") or r.get("Grid_Size_X"))
+
+    numel = 256 * 256 * 1000
+    res = {}
+    for cname, d in (("FETCH_SIZE", fetch_dir), ("WRITE_SIZE", write_dir)):
+        rs = [r for r in rows(d) if r["Counter_Name"] == cname]
+        copy = [float(r["Counter_Value"]) for r in rs if "at::native" in r["Kernel_Name"]]
+        known = 8 * numel if cname == "FETCH_SIZE" else 4 * numel
+        scale = known / (max(copy) * 1024.0)
+        per = {}
+        for dt, tag in (("f64", "k_mode<double"), ("f32", "k_mode<float")):
+            groups = {}
+            for r in rs:
+                if tag in r["Kernel_Name"]:
+                    groups.setdefault(grid(r), []).append(float(r["Counter_Value"]) * 1024 * scale)
+            per[dt] = groups
+        res[cname] = (scale, per)
+    for dt in ("f64", "f32"):
+        f_scale, f_per = res["FETCH_SIZE"]
+        w_scale, w_per = res["WRITE_SIZE"]
+        grids = sorted(f_per[dt], key=lambda gsz: len(f_per[dt][gsz]))
+        gt, gn = grids[0], grids[-1]         # temporal: one launch per update
+        avg = lambda v: sum(v) / len(v)      # noqa: E731
+        rec = {"kernel": "k_mode", "instance": f"k_mode<{'double' if dt == 'f64' else 'float'}, double, 4, 4>",
+               "workload": f"256x256 x 20-slice batch, TR-ranks 8, {dt} operands",
+               "source_hash": kernel_source_hash(),
+               "temporal": {"read": avg(f_per[dt][gt]), "write": avg(w_per[dt][gt]),
+                            "launches": len(f_per[dt][gt]), "grid_workitems": gt},
+               "non_temporal": {"read": avg(f_per[dt][gn]), "write": avg(w_per[dt][gn]),
+                                "launches": len(f_per[dt][gn]), "grid_workitems": gn},
+               "fetch_scale": f_scale, "write_scale": w_scale}
+        rec["read_bytes_per_launch"] = (rec["temporal"]["read"] + 2 * rec["non_temporal"]["read"]) / 3
+        rec["write_bytes_per_launch"] = (rec["temporal"]["write"] + 2 * rec["non_temporal"]["write"]) / 3
+        rec["hbm_bytes_per_launch"] = rec["read_bytes_per_launch"] + rec["write_bytes_per_launch"]
+        rec["command"] = ("cd /tmp && export TMPDIR=/tmp && rocprofv3 --pmc FETCH_SIZE -d <repo>/gpurun_out/pmc_fetch "
+                          "-o f --output-format csv -- python3 <repo>/bench.py --steps 5 --warmup 2 --no-cpu "
+                          "--no-extra ; then the same with --pmc WRITE_SIZE (-d <repo>/gpurun_out/pmc_write -o w); "
+                          "python3 bench.py --pmc-summary <repo>/gpurun_out/pmc_fetch <repo>/gpurun_out/pmc_write")
+        path = os.path.join(ROOT, "profiles", f"mode_c2_{dt}_pmc.json")
+        json.dump(rec, open(path, "w"), indent=1)
+        print(path, json.dumps({k: rec[k] for k in ("read_bytes_per_launch", "write_bytes_per_launch",
+                                                    "hbm_bytes_per_launch", "fetch_scale", "write_scale")}))
+        print("  temporal", rec["temporal"], "\n  non_temporal", rec["non_temporal"])
+
+
 def main():
+    if len(sys.argv) == 4 and sys.argv[1] == "--pmc-summary":
+        pmc_summary(sys.argv[2], sys.argv[3])
+        return
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=40)
