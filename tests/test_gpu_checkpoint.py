@@ -167,3 +167,22 @@ def test_set_samples_rejects_out_of_range(trlib):
     with pytest.raises(trlib.TRError):
         h.set_samples(before)
     h.close()
+
+
+@pytest.mark.parametrize("sketch", [None, "uniform", "ksrft"])
+def test_singular_normal_equations_are_reported(trlib, sketch):
+    """A zero core makes every Gram chain through it zero, so the first
+    update's normal-equation matrix has a zero pivot: the update reports
+    TR_ERR_SINGULAR when the stream is synchronised, and the handle then
+    answers TR_ERR_STATE."""
+    init, X = _problem((14, 12), (2, 3, 2), 8, 1, 4, 6)
+    init[1] = np.zeros_like(init[1])
+    g = trlib.TRStream(X[..., :8], init, sketch=sketch, sketch_size=40 if sketch else 0, seed=2)
+    g.update(X[..., 8:12])
+    with pytest.raises(trlib.TRError) as e:
+        g.sync()
+    assert e.value.code == 7
+    with pytest.raises(trlib.TRError) as e:
+        g.update(X[..., 8:12])
+    assert e.value.code == 6
+    g.close()
