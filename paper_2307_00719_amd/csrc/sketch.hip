@@ -120,57 +120,59 @@ hipError_t launch_leverage(const double* G, int64_t I, int d, const double* Zinv
 //   A[s][r + R_n*srow] = (G_{n+1}(.) ... G_{n-1}(.))[srow, r]
 // and its weight w[s] (the diagonal of D_n^2): wconst for the uniform sketch,
 // 1 / (m prod_{q != n} p_q[idx_q[s]]) when `probs` is given.
-template <int RM>
+// One sampled row per 16-lane group (lane b of the group holds column b of
+// the running row product), so a slice product is 16 independent column
+// loads per lane and 16 shuffles inside the group.
 __global__ __launch_bounds__(256) void k_sample_rows(Geom g, CoreView cv,
                                                      const int* __restrict__ idxs, int m,
                                                      const double* const* probs, double wconst,
                                                      double* __restrict__ A,
                                                      double* __restrict__ w) {
-  const int Rn = g.R[g.n], Rn1 = g.R[g.n + 1 == g.N ? 0 : g.n + 1];
+  const int N = g.N;
+  const int Rn = g.R[g.n], Rn1 = g.R[g.n + 1 == N ? 0 : g.n + 1];
   const int d = g.d;
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= m * Rn1) return;
-  const int s = e / Rn1, srow = e - s * Rn1;
-  int idx[MAXN];
-  for (int q = 0; q < g.N; ++q) idx[q] = q == g.n ? 0 : idxs[(size_t)q * m + s];
-  double v[RM];
-  // row srow of G_{n+1}(.) ... G_{n-1}(.)
+  const int tid = blockIdx.x * blockDim.x + threadIdx.x;
+  const int b = threadIdx.x & 15;
+  const int e = tid >> 4;                              // (sample, row) pair
+  const bool live = e < m * Rn1;
+  const int ec = live ? e : 0;
+  const int s = ec / Rn1, srow = ec - s * Rn1;
+  // row srow of G_{n+1}(.) ... G_{n-1}(.), column b in this lane
+  int q = g.n + 1 == N ? 0 : g.n + 1;
+  double v;
   {
-    const int N = g.N;
-    int q = g.n + 1 == N ? 0 : g.n + 1;
-    const double* G0 = (const double*)cv.ptr[q] + idx[q] * cv.si[q] + srow * cv.sr[q];
+    const int iq = idxs[(size_t)q * m + s];
     const int Rq1 = g.R[q + 1 == N ? 0 : q + 1];
-#pragma unroll
-    for (int b = 0; b < RM; ++b) v[b] = (b < Rq1) ? G0[b * cv.ss[q]] : 0.0;
-    for (int j = 1; j < N - 1; ++j) {
-      q = q + 1 == N ? 0 : q + 1;
-      const double* H = (const double*)cv.ptr[q] + idx[q] * cv.si[q];
-      const int Rq = g.R[q], Rq2 = g.R[q + 1 == N ? 0 : q + 1];
-      double u[RM];
-#pragma unroll
-      for (int b = 0; b < RM; ++b) {
-        double acc = 0.0;
-        if (b < Rq2) {
-#pragma unroll
-          for (int a = 0; a < RM; ++a)
-            if (a < Rq) acc += v[a] * H[a * cv.sr[q] + b * cv.ss[q]];
-        }
-        u[b] = acc;
-      }
-#pragma unroll
-      for (int b = 0; b < RM; ++b) v[b] = u[b];
-    }
+    const double* G0 = (const double*)cv.ptr[q] + iq * cv.si[q] + srow * cv.sr[q];
+    const double x = G0[(b < Rq1 ? b : 0) * cv.ss[q]];
+    v = b < Rq1 ? x : 0.0;
   }
+  for (int j = 1; j < N - 1; ++j) {
+    q = q + 1 == N ? 0 : q + 1;
+    const int iq = idxs[(size_t)q * m + s];
+    const double* H = (const double*)cv.ptr[q] + iq * cv.si[q];
+    const int Rq = g.R[q], Rq2 = g.R[q + 1 == N ? 0 : q + 1];
+    const int bc = b < Rq2 ? b : 0;
+    double h[16];
 #pragma unroll
-  for (int r = 0; r < RM; ++r)
-    if (r < Rn) A[(size_t)s * d + r + Rn * srow] = v[r];
-  if (srow == 0) {
+    for (int a = 0; a < 16; ++a) {
+      const int ac = a < Rq ? a : 0;                 // loads stay inside the slice
+      const double x = H[ac * cv.sr[q] + bc * cv.ss[q]];
+      h[a] = (a < Rq && b < Rq2) ? x : 0.0;
+    }
+    double u = 0.0;
+#pragma unroll
+    for (int a = 0; a < 16; ++a) u = fma(__shfl(v, a, 16), h[a], u);
+    v = u;
+  }
+  if (live && b < Rn) A[(size_t)s * d + b + Rn * srow] = v;
+  if (live && srow == 0 && b == 0) {
     double ws = wconst;
     if (probs) {
-      double q = 1.0;
-      for (int k = 0; k < g.N; ++k)
-        if (k != g.n) q *= probs[k][idx[k]];
-      ws = 1.0 / ((double)m * q);
+      double qq = 1.0;
+      for (int k = 0; k < N; ++k)
+        if (k != g.n) qq *= probs[k][idxs[(size_t)k * m + s]];
+      ws = 1.0 / ((double)m * qq);
     }
     w[s] = ws;
   }
@@ -179,17 +181,12 @@ __global__ __launch_bounds__(256) void k_sample_rows(Geom g, CoreView cv,
 hipError_t launch_sample_rows(const Geom& g, const CoreView& cv, const int* idxs, int m,
                               const double* const* probs, double wconst, double* A, double* w,
                               hipStream_t st) {
-  int rmax = 1;
-  for (int k = 0; k < g.N; ++k) rmax = g.R[k] > rmax ? g.R[k] : rmax;
+  for (int k = 0; k < g.N; ++k)
+    if (g.R[k] > 16) return hipErrorInvalidValue;
   const int Rn1 = g.R[g.n + 1 == g.N ? 0 : g.n + 1];
-  const int nthr = m * Rn1;
-  dim3 grid((nthr + 255) / 256);
-  if (rmax <= 8)
-    hipLaunchKernelGGL(k_sample_rows<8>, grid, dim3(256), 0, st, g, cv, idxs, m, probs, wconst,
-                       A, w);
-  else
-    hipLaunchKernelGGL(k_sample_rows<16>, grid, dim3(256), 0, st, g, cv, idxs, m, probs, wconst,
-                       A, w);
+  const int64_t nthr = (int64_t)m * Rn1 * 16;
+  dim3 grid((unsigned)((nthr + 255) / 256));
+  hipLaunchKernelGGL(k_sample_rows, grid, dim3(256), 0, st, g, cv, idxs, m, probs, wconst, A, w);
   return hipGetLastError();
 }
 
