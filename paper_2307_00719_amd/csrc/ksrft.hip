@@ -350,7 +350,9 @@ hipError_t launch_mix_slices(const double* G, int64_t I, int d, const double* D,
 // Bst = [[w Re A, -w Im A], [w Im A, w Re A]] (2m x 2d) and the 2m weights;
 // with `literal` (the literal temporal reading) Bst = [[Re A, 0], [0, Re A]].
 // ---------------------------------------------------------------------------
-template <int RM>
+// One sampled row per 16-lane group: lane b holds column b (both planes) of
+// the running product; a slice product is 16 independent column loads per
+// plane and 16 shuffles inside the group.
 __global__ __launch_bounds__(256) void k_sample_rows_c(Geom g, const double* const* GS, int m,
                                                        double w, int literal,
                                                        double* __restrict__ Ast,
@@ -359,60 +361,59 @@ __global__ __launch_bounds__(256) void k_sample_rows_c(Geom g, const double* con
   const int N = g.N, n = g.n;
   const int Rn = g.R[n], Rn1 = g.R[n + 1 == N ? 0 : n + 1];
   const int d = g.d;
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= m * Rn1) return;
-  const int s = e / Rn1, srow = e - s * Rn1;
-  double vr[RM], vi[RM];
+  const int tid = blockIdx.x * blockDim.x + threadIdx.x;
+  const int b = threadIdx.x & 15;
+  const int e = tid >> 4;
+  const bool live = e < m * Rn1;
+  const int ec = live ? e : 0;
+  const int s = ec / Rn1, srow = ec - s * Rn1;
+  double vr, vi;
   int q = n + 1 == N ? 0 : n + 1;
   {
     const int Ra = g.R[q], Rb = g.R[q + 1 == N ? 0 : q + 1], dq = Ra * Rb;
     const double* re = GS[q] + (size_t)s * dq;
     const double* im = GS[q] + (size_t)m * dq + (size_t)s * dq;
-#pragma unroll
-    for (int b = 0; b < RM; ++b) {
-      vr[b] = b < Rb ? re[srow + Ra * b] : 0.0;
-      vi[b] = b < Rb ? im[srow + Ra * b] : 0.0;
-    }
+    const int bc = b < Rb ? b : 0;
+    const double xr = re[srow + Ra * bc], xi = im[srow + Ra * bc];
+    vr = b < Rb ? xr : 0.0;
+    vi = b < Rb ? xi : 0.0;
   }
   for (int j = 1; j < N - 1; ++j) {
     q = q + 1 == N ? 0 : q + 1;
     const int Ra = g.R[q], Rb = g.R[q + 1 == N ? 0 : q + 1], dq = Ra * Rb;
     const double* re = GS[q] + (size_t)s * dq;
     const double* im = GS[q] + (size_t)m * dq + (size_t)s * dq;
-    double ur[RM], ui[RM];
+    const int bc = b < Rb ? b : 0;
+    double hr[16], hi[16];
 #pragma unroll
-    for (int b = 0; b < RM; ++b) {
-      double ar = 0.0, ai = 0.0;
-      if (b < Rb) {
-        for (int a = 0; a < Ra; ++a) {
-          const double hr = re[a + Ra * b], hi = im[a + Ra * b];
-          ar += vr[a] * hr - vi[a] * hi;
-          ai += vr[a] * hi + vi[a] * hr;
-        }
-      }
-      ur[b] = ar;
-      ui[b] = ai;
+    for (int a = 0; a < 16; ++a) {
+      const int ac = a < Ra ? a : 0;                 // loads stay inside the slice
+      const double xr = re[ac + Ra * bc], xi = im[ac + Ra * bc];
+      const bool ok = a < Ra && b < Rb;
+      hr[a] = ok ? xr : 0.0;
+      hi[a] = ok ? xi : 0.0;
     }
+    double ur = 0.0, ui = 0.0;
 #pragma unroll
-    for (int b = 0; b < RM; ++b) {
-      vr[b] = ur[b];
-      vi[b] = ui[b];
+    for (int a = 0; a < 16; ++a) {
+      const double pr = __shfl(vr, a, 16), pi = __shfl(vi, a, 16);
+      ur = fma(pr, hr[a], fma(-pi, hi[a], ur));
+      ui = fma(pr, hi[a], fma(pi, hr[a], ui));
     }
+    vr = ur;
+    vi = ui;
   }
-#pragma unroll
-  for (int r = 0; r < RM; ++r) {
-    if (r < Rn) {
-      const int c = r + Rn * srow;
-      const double are = vr[r], aim = vi[r];
-      Ast[(size_t)s * d + c] = are;
-      Ast[(size_t)(m + s) * d + c] = aim;
-      Bst[(size_t)s * 2 * d + c] = literal ? are : w * are;
-      Bst[(size_t)s * 2 * d + d + c] = literal ? 0.0 : -w * aim;
-      Bst[(size_t)(m + s) * 2 * d + c] = literal ? 0.0 : w * aim;
-      Bst[(size_t)(m + s) * 2 * d + d + c] = literal ? are : w * are;
-    }
+  if (live && b < Rn) {
+    const int c = b + Rn * srow;
+    const double are = vr, aim = vi;
+    Ast[(size_t)s * d + c] = are;
+    Ast[(size_t)(m + s) * d + c] = aim;
+    Bst[(size_t)s * 2 * d + c] = literal ? are : w * are;
+    Bst[(size_t)s * 2 * d + d + c] = literal ? 0.0 : -w * aim;
+    Bst[(size_t)(m + s) * 2 * d + c] = literal ? 0.0 : w * aim;
+    Bst[(size_t)(m + s) * 2 * d + d + c] = literal ? are : w * are;
   }
-  if (srow == 0) {
+  if (live && srow == 0 && b == 0) {
     w2[s] = w;
     w2[m + s] = w;
   }
@@ -421,16 +422,12 @@ __global__ __launch_bounds__(256) void k_sample_rows_c(Geom g, const double* con
 hipError_t launch_sample_rows_c(const Geom& g, const double* const* GS, int m, double w,
                                 int literal, double* Ast, double* Bst, double* w2,
                                 hipStream_t st) {
-  int rmax = 1;
-  for (int k = 0; k < g.N; ++k) rmax = g.R[k] > rmax ? g.R[k] : rmax;
+  for (int k = 0; k < g.N; ++k)
+    if (g.R[k] > 16) return hipErrorInvalidValue;
   const int Rn1 = g.R[g.n + 1 == g.N ? 0 : g.n + 1];
-  const unsigned grid = (unsigned)((m * Rn1 + 255) / 256);
-  if (rmax <= 8)
-    hipLaunchKernelGGL(k_sample_rows_c<8>, dim3(grid), dim3(256), 0, st, g, GS, m, w, literal, Ast,
-                       Bst, w2);
-  else
-    hipLaunchKernelGGL(k_sample_rows_c<16>, dim3(grid), dim3(256), 0, st, g, GS, m, w, literal,
-                       Ast, Bst, w2);
+  const unsigned grid = (unsigned)(((int64_t)m * Rn1 * 16 + 255) / 256);
+  hipLaunchKernelGGL(k_sample_rows_c, dim3(grid), dim3(256), 0, st, g, GS, m, w, literal, Ast, Bst,
+                     w2);
   return hipGetLastError();
 }
 
