@@ -486,19 +486,45 @@ __global__ __launch_bounds__(256) void k_sgemm(Geom g, int MT, int dB, int64_t p
       off[tid] = o;
     }
     __syncthreads();
-    for (int e = tid; e < KCH * NTP; e += 256) {
-      const int kk = e / NTP, c = e - kk * NTP;
-      const int k = kb + kk;
-      double v = 0.0;
-      if (k < k_end && c < dB) v = B[(size_t)k * dB + c];
-      Bs[c * KCP + kk] = from_double<TM>(v);
+    // staging in batches of 8 elements per thread with every load of a
+    // batch in flight (indices clamped in range, the selects after the loads)
+    for (int e0 = tid; e0 < KCH * NTP; e0 += 256 * 8) {
+      double v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int e = e0 + 256 * u;
+        const int kk = e / NTP, c = e - kk * NTP;
+        const int k = kb + kk;
+        const bool ok = e < KCH * NTP && k < k_end && c < dB;
+        const int kc = k < k_end ? k : k_end - 1, cc = c < dB ? c : dB - 1;
+        const double x = B[(size_t)kc * dB + cc];
+        v[u] = ok ? x : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int e = e0 + 256 * u;
+        const int kk = e / NTP, c = e - kk * NTP;
+        if (e < KCH * NTP) Bs[c * KCP + kk] = from_double<TM>(v[u]);
+      }
     }
-    for (int e = tid; e < MT * KCH; e += 256) {
-      const int kk = e % KCH, mm = e / KCH;
-      const int64_t mg = m0 + mm;
-      double v = 0.0;
-      if (mg < g.In && off[kk] >= 0) v = (double)X[off[kk] + mg * stride[g.n]];
-      As[mm * KCP + kk] = from_double<TM>(v);
+    for (int e0 = tid; e0 < MT * KCH; e0 += 256 * 8) {
+      double v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int e = e0 + 256 * u;
+        const int kk = e % KCH, mm = e / KCH;
+        const int64_t mg = m0 + mm;
+        const bool ok = e < MT * KCH && mg < g.In && off[kk] >= 0;
+        const int64_t o = ok ? off[kk] + mg * stride[g.n] : 0;
+        const double x = (double)X[o];
+        v[u] = ok ? x : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int e = e0 + 256 * u;
+        const int kk = e % KCH, mm = e / KCH;
+        if (e < MT * KCH) As[mm * KCP + kk] = from_double<TM>(v[u]);
+      }
     }
     __syncthreads();
 #pragma unroll
