@@ -333,9 +333,55 @@ __global__ __launch_bounds__(256) void k_mix_slices(const double* __restrict__ G
   GS[(int64_t)m * d + e] = im * sc;
 }
 
+// Tiled form for I <= 448: a workgroup owns 16 samples x 16 columns and
+// stages the twiddles and D G for its columns in LDS once, so G is read once
+// per workgroup instead of once per sample; same sum, same order.
+constexpr int MIX_TILE_MAXI = 448;     // (2 + 16) * 448 doubles fit the 64 KiB default
+
+__global__ __launch_bounds__(256) void k_mix_slices_t(const double* __restrict__ G, int I, int d,
+                                                      const double* __restrict__ D,
+                                                      const int* __restrict__ idx, int m,
+                                                      double* __restrict__ GS) {
+  extern __shared__ double sm[];
+  double* tw = sm;                          // [I] cos, [I] sin
+  double* dg = sm + 2 * I;                  // [I][16]: D[i] G[i][c0 + j]
+  const int tid = threadIdx.x;
+  const int c0 = blockIdx.x * 16, s0 = blockIdx.y * 16;
+  for (int r = tid; r < I; r += 256) twiddle(r, I, &tw[r], &tw[I + r]);
+  for (int e = tid; e < I * 16; e += 256) {
+    const int i = e >> 4, j = e & 15;
+    const int c = c0 + j < d ? c0 + j : d - 1;
+    dg[e] = D[i] * G[(size_t)i * d + c];
+  }
+  __syncthreads();
+  const int j = tid & 15, sl = tid >> 4;
+  const int s = s0 + sl, c = c0 + j;
+  if (s >= m || c >= d) return;
+  const int step = idx[s];
+  double re = 0.0, im = 0.0;
+  int r = 0;
+  for (int i = 0; i < I; ++i) {
+    const double gv = dg[i * 16 + j];
+    re += tw[r] * gv;
+    im -= tw[I + r] * gv;
+    r += step;
+    if (r >= I) r -= I;
+  }
+  const double sc = 1.0 / sqrt((double)I);
+  const int64_t e = (int64_t)s * d + c;
+  GS[e] = re * sc;
+  GS[(int64_t)m * d + e] = im * sc;
+}
+
 hipError_t launch_mix_slices(const double* G, int64_t I, int d, const double* D, const int* idx,
                              int m, double* GS, hipStream_t st) {
   if (I > 4096) return hipErrorInvalidValue;
+  if (I <= MIX_TILE_MAXI) {
+    dim3 grid((unsigned)((d + 15) / 16), (unsigned)((m + 15) / 16));
+    const size_t lds = (size_t)(2 * I + 16 * I) * sizeof(double);
+    hipLaunchKernelGGL(k_mix_slices_t, grid, dim3(256), lds, st, G, (int)I, d, D, idx, m, GS);
+    return hipGetLastError();
+  }
   const unsigned grid = (unsigned)(((int64_t)m * d + 255) / 256);
   hipLaunchKernelGGL(k_mix_slices, dim3(grid), dim3(256), (size_t)2 * I * sizeof(double), st, G,
                      I, d, D, idx, m, GS);
