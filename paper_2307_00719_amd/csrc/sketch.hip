@@ -262,19 +262,43 @@ __global__ __launch_bounds__(256) void k_sketch_gemm(Geom g, int MT, int cpw, co
       off[tid] = o;
     }
     __syncthreads();
-    for (int e = tid; e < KC * NTP; e += 256) {
-      const int kk = e / NTP, c = e - kk * NTP;
-      const int s = sb + kk;
-      T val = T(0);
-      if (s < s_end && c < d) val = (T)(w[s] * A[(size_t)s * d + c]);
-      Bs[e] = val;
+    // staging in batches of 8 elements per thread with every load of a
+    // batch in flight (indices clamped in range, the selects after the loads)
+    for (int e0 = tid; e0 < KC * NTP; e0 += 256 * 8) {
+      T v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int e = e0 + 256 * u;
+        const int kk = e / NTP, c = e - kk * NTP;
+        const int s = sb + kk;
+        const bool ok = e < KC * NTP && s < s_end && c < d;
+        const int sc = s < s_end ? s : s_end - 1, cc = c < d ? c : d - 1;
+        const double x = w[sc] * A[(size_t)sc * d + cc];
+        v[u] = ok ? (T)x : T(0);
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int e = e0 + 256 * u;
+        if (e < KC * NTP) Bs[e] = v[u];
+      }
     }
-    for (int e = tid; e < MT * KC; e += 256) {
-      const int kk = e % KC, mm = e / KC;
-      const int64_t mg = m0 + mm;
-      T val = T(0);
-      if (mg < g.In && off[kk] >= 0) val = X[off[kk] + mg * stride[g.n]];
-      As[mm * KCP + kk] = val;
+    for (int e0 = tid; e0 < MT * KC; e0 += 256 * 8) {
+      T v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int e = e0 + 256 * u;
+        const int kk = e % KC, mm = e / KC;
+        const int64_t mg = m0 + mm;
+        const bool ok = e < MT * KC && mg < g.In && off[kk] >= 0;
+        const T x = X[ok ? off[kk] + mg * stride[g.n] : 0];
+        v[u] = ok ? x : T(0);
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int e = e0 + 256 * u;
+        const int kk = e % KC, mm = e / KC;
+        if (e < MT * KC) As[mm * KCP + kk] = v[u];
+      }
     }
     __syncthreads();
     const int ar = lane & 15, ak = lane >> 4;
