@@ -374,8 +374,9 @@ tr_status ensure_temporal_probs(tr_stream* s, int64_t t) {
 // the 16x16-pivot-block MFMA Gauss-Jordan of the side kernel (one
 // workgroup of 16 waves, the Gram passed as a single ring-product factor
 // with R_a = d, R_b = 1) for d <= 192, the scalar elimination beyond.
-tr_status gram_update_invert(tr_stream* s, const double* M, int Ra, int Rb, double* Q,
-                             int accumulate, double* Qinv) {
+// Launched on stream `on`.
+tr_status gram_update_invert(tr_stream* s, hipStream_t on, const double* M, int Ra, int Rb,
+                             double* Q, int accumulate, double* Qinv) {
   const int d = Ra * Rb;
   if (d <= 192) {
     SideArgs a;
@@ -394,10 +395,28 @@ tr_status gram_update_invert(tr_stream* s, const double* M, int Ra, int Rb, doub
     a.Qinv = Qinv;
     a.status = s->dstatus;
     a.counter = s->sidecnt;
-    TR_HIP(launch_side(a, s->st));
+    TR_HIP(launch_side(a, on));
     return TR_OK;
   }
-  TR_HIP(launch_invert_spd(M, Ra, Rb, Q, accumulate, 1, Qinv, s->dstatus, s->st, 1));
+  TR_HIP(launch_invert_spd(M, Ra, Rb, Q, accumulate, 1, Qinv, s->dstatus, on, 1));
+  return TR_OK;
+}
+
+// The sketched Gram's Q update and inverse occupy one compute unit and are
+// latency-bound, and the sketched product does not read what they write: in
+// rSTR-K, whose mixed product, reduction and unmixing take about half as long
+// as the inverse, the inverse goes to the second stream once the Gram is
+// formed on the main one (fork), and the main stream waits for it before the
+// solve (join).  rSTR-U/L keep one stream: their product (about 16 us) does
+// not pay for the two cross-stream waits.
+tr_status fork_side(tr_stream* s) {
+  TR_HIP(hipEventRecord(s->ev_fork, s->st));
+  TR_HIP(hipStreamWaitEvent(s->side, s->ev_fork, 0));
+  return TR_OK;
+}
+tr_status join_side(tr_stream* s) {
+  TR_HIP(hipEventRecord(s->ev_join, s->side));
+  TR_HIP(hipStreamWaitEvent(s->st, s->ev_join, 0));
   return TR_OK;
 }
 
@@ -418,12 +437,12 @@ tr_status sketch_increment(tr_stream* s, int n, const void* Xd, int64_t t, const
   TR_HIP(launch_sample_rows(g, cv, s->idxs, m, lev ? (const double* const*)s->dprobs : nullptr,
                             wconst, s->SA, s->Sw, s->st));
   TR_HIP(launch_wgram(s->SA, s->Sw, m, g.d, s->Zb, s->st));
-  tr_status c = gram_update_invert(s, s->Zb, s->R[n], s->R[(n + 1) % N], s->Q[n], accumulate,
-                                   Minv_solve ? s->Minv : nullptr);
-  if (c != TR_OK) return c;
   SketchPlan sp = plan_sketch(g, m, s->dt);
   const size_t pb = (size_t)sp.nsplit * g.In * g.d * sp.psize;
   TR_HIP(ensure(&s->part, &s->part_bytes, pb));
+  tr_status c = gram_update_invert(s, s->st, s->Zb, s->R[n], s->R[(n + 1) % N], s->Q[n],
+                                   accumulate, Minv_solve ? s->Minv : nullptr);
+  if (c != TR_OK) return c;
   TR_HIP(launch_sketch_gemm(g, sp, Xd, s->dt, s->idxs, m, s->SA, s->Sw, s->part, s->st));
   TR_HIP(launch_reduce_solve(s->part, sp.psize, sp.nsplit, g.In, g.d, s->P[n], accumulate,
                              Minv_solve ? s->Minv : nullptr, s->G[n], s->st));
@@ -472,10 +491,10 @@ tr_status sketch_update(tr_stream* s, const void* Xd, int64_t t_new, double* Gne
     TR_HIP(launch_sample_rows(g, cv, s->idxs, m, lev ? (const double* const*)s->dprobs : nullptr,
                               wconst, s->SA, s->Sw, s->st));
     TR_HIP(launch_wgram(s->SA, s->Sw, m, dN, s->Zb, s->st));
-    tr_status c0 = gram_update_invert(s, s->Zb, s->R[N - 1], s->R[0], nullptr, 0, s->Minv);
-    if (c0 != TR_OK) return c0;
     SketchPlan sp = plan_sketch(g, m, s->dt);
     TR_HIP(ensure(&s->part, &s->part_bytes, (size_t)sp.nsplit * g.In * g.d * sp.psize));
+    tr_status c0 = gram_update_invert(s, s->st, s->Zb, s->R[N - 1], s->R[0], nullptr, 0, s->Minv);
+    if (c0 != TR_OK) return c0;
     TR_HIP(launch_sketch_gemm(g, sp, Xd, s->dt, s->idxs, m, s->SA, s->Sw, s->part, s->st));
     TR_HIP(launch_reduce_solve(s->part, sp.psize, sp.nsplit, g.In, g.d, nullptr, 0, s->Minv, Gnew,
                                s->st));
@@ -593,21 +612,27 @@ tr_status ksrft_increment(tr_stream* s, int n, const void* xhat, int64_t t, int 
     TR_HIP(launch_wgram(s->Ast, nullptr, m, d, s->Zb, s->st));
   else
     TR_HIP(launch_wgram(s->Ast, s->Sw2, 2 * (int64_t)m, d, s->Zb, s->st));
-  {
-    tr_status c0 = temporal
-                       ? gram_update_invert(s, s->Zb, s->R[n], s->R[(n + 1) % N], nullptr, 0, s->Minv)
-                       : gram_update_invert(s, s->Zb, s->R[n], s->R[(n + 1) % N], s->Q[n],
-                                            accumulate, solve ? s->Minv : nullptr);
-    if (c0 != TR_OK) return c0;
-  }
   SgemmPlan sp = plan_sgemm(g, m, 2 * d, s->dt);
   TR_HIP(ensure(&s->part, &s->part_bytes, (size_t)sp.nsplit * g.In * 2 * d * sp.psize));
-  TR_HIP(launch_sgemm(g, sp, 2 * d, total, xhat, s->dt, s->idxs, m, s->Bst, s->part, s->st));
   TR_HIP(ensure((void**)&s->Zk, &s->Zk_bytes, (size_t)g.In * 2 * d * sizeof(double)));
   TR_HIP(ensure((void**)&s->dPk, &s->dPk_bytes, (size_t)g.In * d * sizeof(double)));
+  {
+    tr_status c0 = fork_side(s);
+    if (c0 != TR_OK) return c0;
+    c0 = temporal ? gram_update_invert(s, s->side, s->Zb, s->R[n], s->R[(n + 1) % N], nullptr, 0,
+                                       s->Minv)
+                  : gram_update_invert(s, s->side, s->Zb, s->R[n], s->R[(n + 1) % N], s->Q[n],
+                                       accumulate, solve ? s->Minv : nullptr);
+    if (c0 != TR_OK) return c0;
+  }
+  TR_HIP(launch_sgemm(g, sp, 2 * d, total, xhat, s->dt, s->idxs, m, s->Bst, s->part, s->st));
   TR_HIP(launch_reduce_solve(s->part, sp.psize, sp.nsplit, g.In, 2 * d, s->Zk, 0, nullptr,
                              nullptr, s->st));
   TR_HIP(launch_unmix(s->Zk, g.In, d, s->dsign[n], s->dPk, s->st));
+  {
+    tr_status c0 = join_side(s);
+    if (c0 != TR_OK) return c0;
+  }
   TR_HIP(launch_reduce_solve(s->dPk, 8, 1, g.In, d, temporal ? nullptr : s->P[n], accumulate,
                              solve ? s->Minv : nullptr, Gout, s->st));
   return TR_OK;
