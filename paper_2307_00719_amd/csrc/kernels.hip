@@ -1249,24 +1249,25 @@ constexpr int SIDE_LDS_ALLOC = SIDE_LDS + 2;
 // Serial part of the side step, for a workgroup of NW waves: the ring
 // product of the transfer-layout factors, the Q tiles (assembly,
 // accumulation, store) and the blocked Gauss-Jordan inverse.  MAXT >=
-// ceil(nb^2 / NW) tiles per wave.
+// ceil(nb (nb + 1) / 2 / NW) upper-triangle tiles per wave (four tiles of
+// a tile column for the four-wave column-owner form).
 template <int NW, int MAXT>
 __device__ inline void side_serial(const SideArgs& sa, double* lds, double* dmax, int tid,
                                    bool pre = false) {
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
   const int ar = lane & 15, ak = lane >> 4;
   const int Ra = sa.Ra, Rb = sa.Rb, d = Ra * Rb;
-  const int nb = (d + 15) >> 4, ntile = nb * nb;
+  const int nb = (d + 15) >> 4, ntri = nb * (nb + 1) / 2;
   const float rRa = 1.0f / (float)Ra;
   // tile coordinates of the (up to MAXT) Q tiles of this wave: with four
   // waves and MAXT = 4 (nb <= 4, checked by the host) wave w holds tile
-  // column w, as the column-owner elimination needs; otherwise tile
-  // t = wave + NW*s in row-major order
+  // column w, as the column-owner elimination needs; otherwise the tiles
+  // of the upper triangle (ti <= tj), tile t = wave + NW*s in row-major
+  // order over it (the lower triangle follows from the symmetry)
   constexpr bool COLS = NW == 4 && MAXT == 4;
   int TI[MAXT], TJ[MAXT];
   bool TV[MAXT];
   {
-    const float rnb = 1.0f / (float)nb;
 #pragma unroll
     for (int s = 0; s < MAXT; ++s) {
       if (COLS) {
@@ -1275,9 +1276,14 @@ __device__ inline void side_serial(const SideArgs& sa, double* lds, double* dmax
         TV[s] = s < nb && wave < nb;
       } else {
         const int t = wave + NW * s;
-        TI[s] = small_div(t, rnb);
-        TJ[s] = t - TI[s] * nb;
-        TV[s] = t < ntile;
+        TV[s] = t < ntri;
+        int rb = 0, cb = TV[s] ? t : 0;
+        while (cb >= nb - rb) {
+          cb -= nb - rb;
+          ++rb;
+        }
+        TI[s] = rb;
+        TJ[s] = cb + rb;
       }
     }
   }
@@ -1476,7 +1482,12 @@ __device__ inline void side_serial(const SideArgs& sa, double* lds, double* dmax
       const bool ok = TV[s] && gi < d && gj < d;
       double val = mv[s][v];
       if (qacc) val += qpre[s][v];
-      if (ok && storeQ) sa.Q[gi * d + gj] = val;
+      if (ok && storeQ) {
+        sa.Q[gi * d + gj] = val;
+        // the mirror of an upper off-diagonal tile (the upper-triangle
+        // elimination keeps only those; Q stays exactly symmetric)
+        if (!COLS && ti != tj) sa.Q[gj * d + gi] = val;
+      }
       if (ok && gi == gj) mx = fmax(mx, val);
       A[s][v] = ok ? val : (gi == gj ? 1.0 : 0.0);
     }
@@ -1496,9 +1507,15 @@ __device__ inline void side_serial(const SideArgs& sa, double* lds, double* dmax
     gj64_publish<0>(A, lds, lane, wave, nb, d, tol, bad, pinv);
     gj64_step<0>(A, lds, lane, wave, nb, d, tol, bad, pinv);
   } else {
-  // 4. blocked Gauss-Jordan, LDS double-buffered per pivot block:
-  //    Pb = P (row-major), PbT = P^T, RowB[j] = A_Kj (row-major),
-  //    ColT[i] = A_iK^T
+  // 4. blocked Gauss-Jordan over the upper-triangle tiles, LDS
+  //    double-buffered per pivot block: Pb = P (row-major), PbT = P^T,
+  //    RowB[j] = A_Kj (row-major), ColT[i] = A_iK^T.  In-place elimination
+  //    of a symmetric matrix keeps A_ab = A_ba^T when both or neither of the
+  //    blocks a, b have been pivoted and A_ab = -A_ba^T when exactly one has,
+  //    so before pivot block K (pivoted: blocks < K) the strips come from the
+  //    upper tiles alone: for i > K, RowB[i] = ColT[i] = tile (K, i); for
+  //    i < K, ColT[i] = tile(i, K)^T and RowB[i] = -tile(i, K)^T.  The block
+  //    updates below are those of the full elimination restricted to i <= j.
   const int bstride = 2 * nb * 256 + 512;
   const bool dbuf = 2 * bstride <= SIDE_LDS;
   const int kq = lane >> 4, cl = lane & 15;
@@ -1521,12 +1538,18 @@ __device__ inline void side_serial(const SideArgs& sa, double* lds, double* dmax
           }
         } else if (ti == K) {
 #pragma unroll
-          for (int v = 0; v < 4; ++v)
-            RowB[tj * 256 + Acc<double>::row(lane, v) * 16 + cl] = A[s][v];
+          for (int v = 0; v < 4; ++v) {
+            const int o = Acc<double>::row(lane, v) * 16 + cl;
+            RowB[tj * 256 + o] = A[s][v];
+            ColT[tj * 256 + o] = A[s][v];
+          }
         } else if (tj == K) {
 #pragma unroll
-          for (int v = 0; v < 4; ++v)
-            ColT[ti * 256 + cl * 16 + Acc<double>::row(lane, v)] = A[s][v];
+          for (int v = 0; v < 4; ++v) {
+            const int o = cl * 16 + Acc<double>::row(lane, v);
+            ColT[ti * 256 + o] = A[s][v];
+            RowB[ti * 256 + o] = -A[s][v];
+          }
         }
       }
     }
@@ -1585,7 +1608,11 @@ __device__ inline void side_serial(const SideArgs& sa, double* lds, double* dmax
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int gi = ti * 16 + Acc<double>::row(lane, v), gj = tj * 16 + cl;
-        if (gi < d && gj < d) sa.Qinv[gi * d + gj] = A[s][v];
+        if (gi < d && gj < d) {
+          sa.Qinv[gi * d + gj] = A[s][v];
+          // all blocks pivoted: the inverse is symmetric
+          if (!COLS && ti != tj) sa.Qinv[gj * d + gi] = A[s][v];
+        }
       }
     }
   }
@@ -1885,10 +1912,13 @@ hipError_t launch_side(const SideArgs& a, hipStream_t st) {
   const int nb = (d + 15) / 16;
   static const bool scalar_gj = getenv("TRSTREAM_SCALAR_GJ") != nullptr;
   if (nb <= 12 && !scalar_gj) {
-    if (nb * nb <= 16) return launch_side_mf<1>(a, nb, st);
-    if (nb * nb <= 32) return launch_side_mf<2>(a, nb, st);
-    if (nb * nb <= 64) return launch_side_mf<4>(a, nb, st);
-    return launch_side_mf<9>(a, nb, st);
+    // 16 waves over the nb (nb + 1) / 2 upper-triangle tiles
+    const int ntri = nb * (nb + 1) / 2;
+    if (ntri <= 16) return launch_side_mf<1>(a, nb, st);
+    if (ntri <= 32) return launch_side_mf<2>(a, nb, st);
+    if (ntri <= 48) return launch_side_mf<3>(a, nb, st);
+    if (ntri <= 64) return launch_side_mf<4>(a, nb, st);
+    return launch_side_mf<5>(a, nb, st);
   }
   const int B = (d + 31) / 32;
 #define TRK_SIDE(BB) \
