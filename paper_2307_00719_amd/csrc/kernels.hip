@@ -1624,7 +1624,7 @@ __device__ inline void side_serial(const SideArgs& sa, double* lds, double* dmax
 // the NW waves (8 k-steps of loads in flight per wave), the partial tiles
 // summed in LDS in a fixed order, and the tile and its mirror written in the
 // transfer layout.
-template <int NW>
+template <int NW, bool WEIGHTED = false>
 __device__ inline void gram_tile(const SideArgs& sa, double* lds, int tid, int tile) {
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
   const int ar = lane & 15, ak = lane >> 4;
@@ -1653,8 +1653,9 @@ __device__ inline void gram_tile(const SideArgs& sa, double* lds, int tid, int t
       const int64_t i = ks * 4 + ak;
       const int64_t ic = i < rows ? i : rl;
       const double xa = Gp[ic * dp + c1], xb = Gp[ic * dp + c2];
+      const double wa = WEIGHTED ? sa.Gw[ic] : 1.0;
       const bool ok = i < rows && ks < nks;
-      av[q] = ok ? xa : 0.0;
+      av[q] = ok ? (WEIGHTED ? xa * wa : xa) : 0.0;
       bv[q] = ok ? xb : 0.0;
     }
     if constexpr (NW <= 4) {
@@ -1677,7 +1678,9 @@ __device__ inline void gram_tile(const SideArgs& sa, double* lds, int tid, int t
 #pragma unroll
     for (int w = 0; w < NW; ++w) sum += lds[w * 256 + e];
     const int r = rb * 16 + (e >> 4), c = cb * 16 + (e & 15);
-    if (r < dp && c < dp) {
+    // weighted: (w x) y and (w y) x may differ in the last bit, so in the
+    // diagonal tile only r <= c writes (both positions: exactly symmetric)
+    if (r < dp && c < dp && (!WEIGHTED || r <= c)) {
       const float rRa = 1.0f / (float)Ra;
       const int b1 = small_div(r, rRa), a1 = r - b1 * Ra, b2 = small_div(c, rRa), a2 = c - b2 * Ra;
       coherent_store(sa.Ep + (size_t)(a1 + Ra * a2) * (Rb * Rb) + (b1 + Rb * b2), sum);
@@ -1758,7 +1761,10 @@ __global__ __launch_bounds__(1024) void k_side_mf(SideArgs sa) {
   //    tile per workgroup); the last workgroup to finish goes on with the
   //    chain, Q and the inverse while the others exit.
   if (sa.Gp) {
-    gram_tile<16>(sa, lds, tid, blockIdx.x);
+    if (sa.Gw)
+      gram_tile<16, true>(sa, lds, tid, blockIdx.x);
+    else
+      gram_tile<16>(sa, lds, tid, blockIdx.x);
     if (!gram_arrive(sa.counter, gridDim.x, tid)) return;
   }
   side_serial<16, MAXT>(sa, lds, dmax, tid);

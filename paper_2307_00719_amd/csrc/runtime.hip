@@ -374,13 +374,25 @@ tr_status ensure_temporal_probs(tr_stream* s, int64_t t) {
 // the 16x16-pivot-block MFMA Gauss-Jordan of the side kernel (one
 // workgroup of 16 waves, the Gram passed as a single ring-product factor
 // with R_a = d, R_b = 1) for d <= 192, the scalar elimination beyond.
-// Launched on stream `on`.
-tr_status gram_update_invert(tr_stream* s, hipStream_t on, const double* M, int Ra, int Rb,
-                             double* Q, int accumulate, double* Qinv) {
+// With rows A (`rows` x d, row weights w, or weights 1 when w is null) the
+// Gram M = sum_s w_s A_s^T A_s is formed first into M: for d <= 192 by the
+// side kernel's own tile workgroups (the last to finish goes on with the
+// inverse), else by the weighted-Gram kernel.  Launched on stream `on`.
+tr_status gram_update_invert(tr_stream* s, hipStream_t on, double* M, int Ra, int Rb, double* Q,
+                             int accumulate, double* Qinv, const double* A = nullptr,
+                             const double* w = nullptr, int64_t rows = 0) {
   const int d = Ra * Rb;
   if (d <= 192) {
     SideArgs a;
     std::memset(&a, 0, sizeof(a));
+    if (A) {
+      a.Gp = A;
+      a.Gw = w;
+      a.rows_p = rows;
+      a.Rpa = d;
+      a.Rpb = 1;
+      a.Ep = M;
+    }
     a.nfac = 1;
     a.fac[0] = M;
     a.fr[0] = d;
@@ -398,6 +410,7 @@ tr_status gram_update_invert(tr_stream* s, hipStream_t on, const double* M, int 
     TR_HIP(launch_side(a, on));
     return TR_OK;
   }
+  if (A) TR_HIP(launch_wgram(A, w, rows, d, M, on));
   TR_HIP(launch_invert_spd(M, Ra, Rb, Q, accumulate, 1, Qinv, s->dstatus, on, 1));
   return TR_OK;
 }
@@ -436,12 +449,11 @@ tr_status sketch_increment(tr_stream* s, int n, const void* Xd, int64_t t, const
   const bool lev = s->sketch == TR_SKETCH_LEVERAGE && s->rescale;
   TR_HIP(launch_sample_rows(g, cv, s->idxs, m, lev ? (const double* const*)s->dprobs : nullptr,
                             wconst, s->SA, s->Sw, s->st));
-  TR_HIP(launch_wgram(s->SA, s->Sw, m, g.d, s->Zb, s->st));
   SketchPlan sp = plan_sketch(g, m, s->dt);
   const size_t pb = (size_t)sp.nsplit * g.In * g.d * sp.psize;
   TR_HIP(ensure(&s->part, &s->part_bytes, pb));
   tr_status c = gram_update_invert(s, s->st, s->Zb, s->R[n], s->R[(n + 1) % N], s->Q[n],
-                                   accumulate, Minv_solve ? s->Minv : nullptr);
+                                   accumulate, Minv_solve ? s->Minv : nullptr, s->SA, s->Sw, m);
   if (c != TR_OK) return c;
   TR_HIP(launch_sketch_gemm(g, sp, Xd, s->dt, s->idxs, m, s->SA, s->Sw, s->part, s->st));
   TR_HIP(launch_reduce_solve(s->part, sp.psize, sp.nsplit, g.In, g.d, s->P[n], accumulate,
@@ -480,7 +492,6 @@ tr_status sketch_update(tr_stream* s, const void* Xd, int64_t t_new, double* Gne
   for (int k = 0; k < N - 1; ++k) gd[k] = s->I[k];
   gd[N - 1] = t_new;
   const int m = (int)s->m;
-  const int dN = s->d(N - 1);
   // temporal mode: G_N^new = (X_S D)((D G_S)^T)^+ through the normal equations
   {
     Geom g = make_geom(N, gd.data(), s->R, N - 1);
@@ -490,10 +501,10 @@ tr_status sketch_update(tr_stream* s, const void* Xd, int64_t t_new, double* Gne
     const bool lev = s->sketch == TR_SKETCH_LEVERAGE && s->rescale;
     TR_HIP(launch_sample_rows(g, cv, s->idxs, m, lev ? (const double* const*)s->dprobs : nullptr,
                               wconst, s->SA, s->Sw, s->st));
-    TR_HIP(launch_wgram(s->SA, s->Sw, m, dN, s->Zb, s->st));
     SketchPlan sp = plan_sketch(g, m, s->dt);
     TR_HIP(ensure(&s->part, &s->part_bytes, (size_t)sp.nsplit * g.In * g.d * sp.psize));
-    tr_status c0 = gram_update_invert(s, s->st, s->Zb, s->R[N - 1], s->R[0], nullptr, 0, s->Minv);
+    tr_status c0 = gram_update_invert(s, s->st, s->Zb, s->R[N - 1], s->R[0], nullptr, 0, s->Minv,
+                                      s->SA, s->Sw, m);
     if (c0 != TR_OK) return c0;
     TR_HIP(launch_sketch_gemm(g, sp, Xd, s->dt, s->idxs, m, s->SA, s->Sw, s->part, s->st));
     TR_HIP(launch_reduce_solve(s->part, sp.psize, sp.nsplit, g.In, g.d, nullptr, 0, s->Minv, Gnew,
@@ -608,10 +619,10 @@ tr_status ksrft_increment(tr_stream* s, int n, const void* xhat, int64_t t, int 
     w = temporal ? (double)prod_dims_except(s, -1) / m : (double)prod_dims_except(s, n) * t / m;
   TR_HIP(launch_sample_rows_c(g, (const double* const*)s->dGSc, m, w, literal ? 1 : 0, s->Ast,
                               s->Bst, s->Sw2, s->st));
-  if (literal)
-    TR_HIP(launch_wgram(s->Ast, nullptr, m, d, s->Zb, s->st));
-  else
-    TR_HIP(launch_wgram(s->Ast, s->Sw2, 2 * (int64_t)m, d, s->Zb, s->st));
+  // the (re-)Gram of the sampled subchain: both planes with the sketch
+  // weights, or the real plane unweighted for the literal temporal reading
+  const double* gw = literal ? nullptr : s->Sw2;
+  const int64_t grows = literal ? (int64_t)m : 2 * (int64_t)m;
   SgemmPlan sp = plan_sgemm(g, m, 2 * d, s->dt);
   TR_HIP(ensure(&s->part, &s->part_bytes, (size_t)sp.nsplit * g.In * 2 * d * sp.psize));
   TR_HIP(ensure((void**)&s->Zk, &s->Zk_bytes, (size_t)g.In * 2 * d * sizeof(double)));
@@ -620,9 +631,9 @@ tr_status ksrft_increment(tr_stream* s, int n, const void* xhat, int64_t t, int 
     tr_status c0 = fork_side(s);
     if (c0 != TR_OK) return c0;
     c0 = temporal ? gram_update_invert(s, s->side, s->Zb, s->R[n], s->R[(n + 1) % N], nullptr, 0,
-                                       s->Minv)
+                                       s->Minv, s->Ast, gw, grows)
                   : gram_update_invert(s, s->side, s->Zb, s->R[n], s->R[(n + 1) % N], s->Q[n],
-                                       accumulate, solve ? s->Minv : nullptr);
+                                       accumulate, solve ? s->Minv : nullptr, s->Ast, gw, grows);
     if (c0 != TR_OK) return c0;
   }
   TR_HIP(launch_sgemm(g, sp, 2 * d, total, xhat, s->dt, s->idxs, m, s->Bst, s->part, s->st));

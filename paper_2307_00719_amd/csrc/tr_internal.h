@@ -98,8 +98,11 @@ hipError_t launch_invert_spd(const double* M, int Ra, int Rb, double* Q, int acc
 // then the ring product of the nfac transfer-layout factors fac[0..nfac)
 // (fac[j] is fr[j] x fc[j]; a null entry stands for Ep), then the Q-layout
 // assembly / accumulation into Q and the Gauss-Jordan inverse into Qinv.
+// With row weights Gw (rows_p of them) the Gram is sum_s Gw[s] Gp_s^T Gp_s
+// (the weighted sketched Gram, with Rpa = d and Rpb = 1).
 struct SideArgs {
   const double* Gp;
+  const double* Gw;
   int64_t rows_p;
   int Rpa, Rpb;
   double* Ep;
