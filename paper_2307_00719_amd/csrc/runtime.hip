@@ -1005,7 +1005,10 @@ tr_status tr_stream_update(tr_stream* s, const void* X_new, int32_t x_dtype, int
   const long pstep = prof_begin(s, PK_STEP);
   long pr;
   auto side_args = [&](int n, int p, const double* Gp, int64_t rows_p) {
+    // every field not set below (the Gram's row weights Gw among them) is
+    // zero: the kernels test those pointers
     SideArgs a;
+    std::memset(&a, 0, sizeof(a));
     a.Gp = Gp;
     a.rows_p = rows_p;
     a.Rpa = s->R[p];

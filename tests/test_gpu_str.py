@@ -71,6 +71,10 @@ SHAPES = [
     ((21, 19), (5, 4, 6), 40, 11, 2),
     # Q of 42 x 42 and 49 x 49: three and four ragged 16 x 16 tiles a side
     ((24, 22), (7, 6, 7), 20, 6, 2),
+    # Q of 72 x 72 to 90 x 90 (d > 64): past the fused per-mode launch, so the
+    # side kernel (its own Gram tile workgroups, chain, upper-triangle inverse)
+    # runs on the second stream
+    ((20, 18), (9, 8, 10), 25, 6, 2),
 ]
 
 
