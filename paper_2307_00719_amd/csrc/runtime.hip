@@ -324,16 +324,24 @@ int64_t prod_dims_except(const tr_stream* s, int skip) {
 
 // Leverage distribution (Lemma on leverage estimation) of `rows` slice-major
 // rows of core k into p.
+tr_status gram_update_invert(tr_stream* s, hipStream_t on, double* M, int Ra, int Rb, double* Q,
+                             int accumulate, double* Qinv, const double* A = nullptr,
+                             const double* w = nullptr, int64_t rows = 0);
+
 tr_status leverage_probs(tr_stream* s, int k, const double* rows, int64_t I, double* p) {
   const int Ra = s->R[k], Rb = s->R[(k + 1) % s->N], d = Ra * Rb;
   if (I > d) {
-    TR_HIP(launch_wgram(rows, nullptr, I, d, s->Zb, s->st));
-    TR_HIP(launch_invert_spd(s->Zb, Ra, Rb, nullptr, 0, 0, s->Zi, s->dstatus, s->st, 1));
+    // G^T G of the rows and its inverse (one side kernel for d <= 192)
+    tr_status c = gram_update_invert(s, s->st, s->Zb, Ra, Rb, nullptr, 0, s->Zi, rows, nullptr, I);
+    if (c != TR_OK) return c;
     TR_HIP(launch_leverage(rows, I, d, s->Zi, p, s->st));
   } else {
     if (I > 256) return poison(s, TR_ERR_UNSUPPORTED, "leverage rank check needs I <= 256");
+    // full row rank: the row Gram G G^T passes the positivity test of the
+    // elimination (its inverse is not used)
     TR_HIP(launch_row_gram(rows, I, d, s->Zb, s->st));
-    TR_HIP(launch_invert_spd(s->Zb, (int)I, 1, nullptr, 0, 0, s->Zi, s->dstatus, s->st, 1));
+    tr_status c = gram_update_invert(s, s->st, s->Zb, (int)I, 1, nullptr, 0, s->Zi);
+    if (c != TR_OK) return c;
     TR_HIP(launch_leverage(rows, I, d, nullptr, p, s->st));
   }
   return TR_OK;
@@ -379,8 +387,8 @@ tr_status ensure_temporal_probs(tr_stream* s, int64_t t) {
 // side kernel's own tile workgroups (the last to finish goes on with the
 // inverse), else by the weighted-Gram kernel.  Launched on stream `on`.
 tr_status gram_update_invert(tr_stream* s, hipStream_t on, double* M, int Ra, int Rb, double* Q,
-                             int accumulate, double* Qinv, const double* A = nullptr,
-                             const double* w = nullptr, int64_t rows = 0) {
+                             int accumulate, double* Qinv, const double* A, const double* w,
+                             int64_t rows) {
   const int d = Ra * Rb;
   if (d <= 192) {
     SideArgs a;
