@@ -456,17 +456,27 @@ hipError_t launch_wgram(const double* A, const double* w, int64_t rows, int d, d
 // of the leverage distribution when I <= d.
 __global__ __launch_bounds__(256) void k_row_gram(const double* __restrict__ G, int64_t I, int d,
                                                   double* __restrict__ K) {
-  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (e >= I * I) return;
-  const int64_t i = e / I, j = e - i * I;
+  // 16 lanes per entry, each summing every 16th column, then a fixed-order
+  // butterfly over the 16 lanes: the partials of (i, j) and (j, i) are the
+  // same products in the same order, so K is exactly symmetric
+  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t e = t >> 4;
+  const int l = threadIdx.x & 15;
+  const bool ok = e < I * I;
+  const int64_t ec = ok ? e : 0;
+  const int64_t i = ec / I, j = ec - i * I;
   double s = 0.0;
-  for (int c = 0; c < d; ++c) s += G[i * d + c] * G[j * d + c];
-  K[e] = s;
+  for (int c = l; c < d; c += 16) s += G[i * d + c] * G[j * d + c];
+  s += __shfl_xor(s, 8, 16);
+  s += __shfl_xor(s, 4, 16);
+  s += __shfl_xor(s, 2, 16);
+  s += __shfl_xor(s, 1, 16);
+  if (ok && l == 0) K[e] = s;
 }
 
 hipError_t launch_row_gram(const double* G, int64_t I, int d, double* K, hipStream_t st) {
-  hipLaunchKernelGGL(k_row_gram, dim3((unsigned)((I * I + 255) / 256)), dim3(256), 0, st, G, I, d,
-                     K);
+  hipLaunchKernelGGL(k_row_gram, dim3((unsigned)((I * I * 16 + 255) / 256)), dim3(256), 0, st, G,
+                     I, d, K);
   return hipGetLastError();
 }
 
