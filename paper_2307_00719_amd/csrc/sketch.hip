@@ -41,10 +41,42 @@ hipError_t launch_draw_uniform(uint64_t key, int m, int64_t I, int* idx, hipStre
 
 // Randsample(I, m, true, p) (Alg. 8): thread 0 forms the cdf left to right,
 // then every thread inverts its uniform by binary search.
+// distributions of up to this many entries keep their cdf in LDS
+constexpr int DRAW_LDS = 4096;
+
 __global__ __launch_bounds__(256) void k_draw_dist(uint64_t key, int m, int64_t I,
                                                    const double* __restrict__ p,
                                                    double* __restrict__ cdf,
                                                    int* __restrict__ idx) {
+  __shared__ double sc[DRAW_LDS];
+  if (I <= DRAW_LDS) {
+    // the same sequential running sum, in LDS, and every search step an LDS
+    // read (the draws are those of the global-memory form below)
+    for (int64_t i = threadIdx.x; i < I; i += blockDim.x) sc[i] = p[i];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double c = 0.0;
+      for (int64_t i = 0; i < I; ++i) {
+        c += sc[i];
+        sc[i] = c;
+      }
+      sc[I - 1] = 1.0;
+    }
+    __syncthreads();
+    for (int s = threadIdx.x; s < m; s += blockDim.x) {
+      const double u = rng_uniform(key, (uint64_t)s);
+      int lo = 0, hi = (int)I - 1;
+      while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (sc[mid] > u)
+          hi = mid;
+        else
+          lo = mid + 1;
+      }
+      idx[s] = lo;
+    }
+    return;
+  }
   if (threadIdx.x == 0 && blockIdx.x == 0) {
     double c = 0.0;
     for (int64_t i = 0; i < I; ++i) {
