@@ -22,9 +22,17 @@ Readings taken where the paper is silent or ambiguous:
     after each re-mix the sampled mixed cores are re-gathered with the
     existing indices; the P/Q updates read
         P_n += Xhat_S[n] conj(Ghat_S[2]),  Q_n += Ghat_S[2]^T conj(Ghat_S[2])
-    at initialisation and in every step; the temporal rows are
-        G_N^new = Re(Xhat_S conj(Ghat_S)) Re(Ghat_S^T conj(Ghat_S))^dagger
-    (``temporal_literal=True`` gives Re(Xhat_S) (Re(Ghat_S^T))^dagger).
+    at initialisation and in every step; the temporal rows are the printed
+    form of the KSRFT paragraph of Sec. 3.3 and of Alg. 9,
+        G_N^new = Re(Xhat_S) (Re(Ghat_S^T))^dagger
+    (a constant sketch weight does not change this least-squares solution);
+    ``temporal_literal=False`` gives instead the real-constrained normal
+    equations of the complex sketch,
+        G_N^new = Re(Xhat_S conj(Ghat_S)) Re(Ghat_S^T conj(Ghat_S))^dagger,
+    the form the paper uses for the non-temporal cores.
+  * ``set_samples`` replaces the generator's draws (test hook): injected
+    indices are used until each row is redrawn right after its core is
+    updated; injected signs replace the D_j of the next time step.
 """
 
 import numpy as np
@@ -107,7 +115,7 @@ class RSTR:
     """State and steps of rSTR-U / rSTR-L / rSTR-K (Algs. 7 / 8 / 9)."""
 
     def __init__(self, X_init, cores0, m, sketch="uniform", seed=0,
-                 rescale=True, temporal_literal=False):
+                 rescale=True, temporal_literal=True):
         assert sketch in ("uniform", "leverage", "ksrft")
         self.N = N = X_init.ndim
         self.m, self.sketch, self.seed = int(m), sketch, int(seed)
@@ -123,6 +131,7 @@ class RSTR:
             src_X = mix_tensor(X_init, self.D)
         if sketch == "leverage":
             self.p = [leverage_distribution(G) for G in self.cores]
+        self.next_signs = None
         self.idxs = [self._draw(0, k, self.cores[k].shape[1]) for k in range(N)]
         self.GS = [self._gather(k, self.cores[k]) for k in range(N)]
         self.P, self.Q = [], []
@@ -179,7 +188,12 @@ class RSTR:
         t_new = X_new.shape[N - 1]
         src_X = X_new
         if self.sketch == "ksrft":
-            self.D = [rng.signs(self.seed, s, j, X_new.shape[j]) for j in range(N)]
+            if self.next_signs is not None:
+                self.D = [np.asarray(d, dtype=np.float64) for d in self.next_signs]
+                assert all(len(d) == X_new.shape[j] for j, d in enumerate(self.D))
+                self.next_signs = None
+            else:
+                self.D = [rng.signs(self.seed, s, j, X_new.shape[j]) for j in range(N)]
             src_X = mix_tensor(X_new, self.D)
             for k in range(N - 1):
                 self.Ghat[k] = mix_core(self.cores[k], self.D[k])
@@ -228,6 +242,21 @@ class RSTR:
             self.idxs[n] = self._draw(s, n, self.cores[n].shape[1])
             self.GS[n] = self._gather(n, self.cores[n])
         return self
+
+    def set_samples(self, idxs=None, signs=None):
+        """Test hook: ``idxs`` (N rows of m indices; row N-1 indexes the newest
+        temporal block) replaces the current samples and the sampled cores are
+        re-gathered; ``signs`` (N vectors of +-1, the temporal one as long as
+        the next batch) replaces the D_j that the next step would draw."""
+        N = self.N
+        if idxs is not None:
+            self.idxs = [np.asarray(idxs[k], dtype=np.int64).copy() for k in range(N)]
+            for k in range(N - 1):
+                self.GS[k] = self._gather(k, self.cores[k])
+            newest = self.G_new if self.G_new is not None else self.cores[N - 1]
+            self.GS[N - 1] = self._gather(N - 1, newest)
+        if signs is not None:
+            self.next_signs = [np.asarray(d, dtype=np.float64).copy() for d in signs]
 
     def rel_error(self, X_all):
         return tr.rel_error(X_all, self.cores)

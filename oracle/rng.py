@@ -25,12 +25,21 @@ counter-based generator so that their draws coincide:
 
 ``step`` is 0 at initialisation and t at time step t; ``core`` is the 0-based
 core whose samples (kind 0) or signs (kind 1) are drawn.
+
+Initial TR-cores (the random start of the batch TR-ALS that initialises a
+stream, Sec. 4 protocol) use kind 2: entry e of core k (column-major, e =
+r + R_k (i + I_k s)) is the Irwin-Hall approximation of a standard normal,
+    z_e = (u_{12e} + u_{12e+1} + ... + u_{12e+11}) - 6,
+summed left to right in double precision (mean 0, variance 1).  It needs
+no transcendental function, so two independent implementations give the
+same bits.
 """
 
 import numpy as np
 
 KIND_INDEX = 0
 KIND_SIGN = 1
+KIND_INIT = 2
 
 _M64 = (1 << 64) - 1
 
@@ -87,3 +96,27 @@ def signs(seed, step, core, count):
     """Random sign-flip diagonal of D_j (Def. KSRFT): entries +-1."""
     w = words(seed, step, core, KIND_SIGN, count)
     return np.where((w >> np.uint64(63)) == 0, 1.0, -1.0)
+
+
+def irwin_hall_normals(seed, core, count):
+    """Approximately N(0,1) draws of the initial-core stream (kind 2, step 0):
+    z_e = sum_{j<12} u_{12e+j} - 6, summed left to right."""
+    w = words(seed, 0, core, KIND_INIT, 12 * count)
+    u = (w >> np.uint64(11)).astype(np.float64) * (2.0 ** -53)
+    u = u.reshape(count, 12)
+    z = np.zeros(count)
+    for j in range(12):
+        z = z + u[:, j]
+    return z - 6.0
+
+
+def init_cores(seed, dims, ranks):
+    """Initial TR-cores G_k (R_k x I_k x R_{k+1}) filled column-major from the
+    kind-2 stream of core k."""
+    N = len(dims)
+    out = []
+    for k in range(N):
+        shape = (ranks[k], dims[k], ranks[(k + 1) % N])
+        z = irwin_hall_normals(seed, k, int(np.prod(shape)))
+        out.append(z.reshape(shape, order="F"))
+    return out

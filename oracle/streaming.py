@@ -13,6 +13,13 @@ Readings of the paper taken here (each is also listed in the design notes):
   * One call of ``update`` is one time step of Alg. 4: the temporal mode, then
     n = 1..N-1 in order, each mode using the cores already updated in the
     same step.
+  * ``sweeps`` > 1 (an extension, not in the paper) repeats that pass on the
+    same batch.  Every repetition starts again from the P_n^old, Q_n^old held
+    before the batch (Sec. 3.1 splits P_n, Q_n into an old part and the new
+    batch's part, eq. partial), recomputes the new temporal rows from the
+    current non-temporal cores (replacing the previous pass's rows instead
+    of appending more) and re-forms the new batch's increments with the
+    refreshed cores, so the old slices are never counted twice.
 """
 
 import numpy as np
@@ -93,12 +100,22 @@ class STR:
         self.cores[n] = tr.core_fold2(Gn2, G.shape[0], G.shape[2])
         self.Z[n] = tr.gram_tensor(self.cores[n])
 
-    def update(self, X_new):
-        """One time step of Alg. 4 for the batch X_new (I_1 x .. x t_new)."""
-        ZN_new = self._temporal(X_new)
-        for n in range(self.N - 1):
-            self._mode(n, X_new, ZN_new)
-        self.Z[self.N - 1] = tr.gram_tensor(self.cores[self.N - 1])
+    def update(self, X_new, sweeps=1):
+        """One time step of Alg. 4 for the batch X_new (I_1 x .. x t_new);
+        ``sweeps`` passes over the batch (see the module notes)."""
+        N = self.N
+        P_old = [P.copy() for P in self.P]
+        Q_old = [Q.copy() for Q in self.Q]
+        t_new = X_new.shape[N - 1]
+        for k in range(int(sweeps)):
+            if k > 0:
+                self.cores[N - 1] = self.cores[N - 1][:, :-t_new, :]
+                self.P = [P.copy() for P in P_old]
+                self.Q = [Q.copy() for Q in Q_old]
+            ZN_new = self._temporal(X_new)
+            for n in range(N - 1):
+                self._mode(n, X_new, ZN_new)
+        self.Z[N - 1] = tr.gram_tensor(self.cores[N - 1])
         self.steps += 1
         return self
 
