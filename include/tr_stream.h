@@ -24,9 +24,13 @@
  *
  * Errors: every function returns a tr_status; nothing is thrown across the
  * ABI.  Arguments and shapes are validated before any state changes.  A
- * device-side failure (a non-positive pivot in a normal-equation solve, a
- * HIP error) marks the handle TR_ERR_STATE and every later call on it
- * returns that status; tr_last_error() gives the message.
+ * singular or rank-deficient normal-equation matrix is not an error: the
+ * solve takes the pseudo-inverse (the dagger of Alg. 4 and Algs. 7-9, with
+ * singular values at or below d * eps * sigma_max taken as zero) and the
+ * handle counts the fallback (tr_stream_get_stats).  A device-side failure
+ * (a HIP error, a normal-equation matrix holding NaN or Inf) marks the
+ * handle TR_ERR_STATE and every later call on it returns that status;
+ * tr_last_error() gives the message.
  */
 #ifndef TR_STREAM_H
 #define TR_STREAM_H
@@ -48,7 +52,7 @@ typedef enum {
   TR_ERR_DEVICE = 4,      /* a HIP call failed                             */
   TR_ERR_NONFINITE = 5,   /* NaN or Inf in an input batch                  */
   TR_ERR_STATE = 6,       /* the handle was poisoned by an earlier failure */
-  TR_ERR_SINGULAR = 7,    /* a normal-equation matrix was not positive definite */
+  TR_ERR_SINGULAR = 7,    /* an elimination failed with no fallback available */
   TR_ERR_UNSUPPORTED = 8  /* a size or option outside what is built         */
 } tr_status;
 
@@ -71,8 +75,11 @@ typedef struct {
   int64_t sketch_size;    /* m (sample rows) for the randomized variants    */
   int32_t rescale;        /* 1: apply the rescaling D of the sketch (default
                              reading); 0: ignore it (Sec. 3.3 remark)        */
-  int32_t temporal_literal; /* KSRFT only: 1 = Re(Xhat_S) (Re(Ghat_S^T))^+,
-                             0 = real-constrained normal equations          */
+  int32_t temporal_normal_eq; /* KSRFT temporal rows.  0 (default): the
+                             printed form of the KSRFT paragraph of Sec. 3.3
+                             and Alg. 9, G_N^new = Re(Xhat_S) (Re(Ghat_S^T))^+;
+                             1: the real-constrained normal equations
+                             Re(Xhat_S conj Ghat_S) Re(Ghat_S^T conj Ghat_S)^+ */
   uint64_t seed;          /* key of the counter-based sample generator      */
   int64_t max_slices;     /* capacity of the temporal core in slices; 0 lets
                              the library grow it (a growth synchronises)     */
@@ -80,13 +87,41 @@ typedef struct {
                              batch then costs one extra pass and a sync)     */
   int32_t device;         /* HIP device ordinal                             */
   void *hip_stream;       /* hipStream_t to run on; NULL = library-owned    */
+  int32_t sweeps;         /* STR only: passes of the update stage over each
+                             batch (0 or 1: one pass, Alg. 4).  Pass k > 1
+                             starts again from the P_n, Q_n held before the
+                             batch (Sec. 3.1 splits them into the old part
+                             and the new batch's part) and recomputes the new
+                             temporal rows and increments with the refreshed
+                             cores.  An extension, not in the paper.        */
+  int32_t init_max_sweeps;/* initialiser without cores (tr_stream_init with
+                             cores_init NULL): batch TR-ALS sweeps at most
+                             (0: 100)                                        */
+  double init_tol;        /* ... and its stopping threshold on the change of
+                             the relative error between sweeps (<= 0: 1e-8) */
 } tr_config;
+
+/* Counters of a handle (tr_stream_get_stats). */
+typedef struct {
+  int64_t pinv_fallbacks; /* normal-equation solves that took the
+                             pseudo-inverse (rank-deficient or numerically
+                             singular matrix) since the handle was created  */
+  int32_t init_sweeps;    /* batch TR-ALS sweeps run by the initialiser
+                             (0 when the cores were given)                  */
+  double init_rel_err;    /* relative error on X_init after them            */
+} tr_stats;
 
 /* Initialisation stage of Alg. 4 / Algs. 7-9: store the initial cores, form
  * the Gram tensors and the complementary matrices P_n, Q_n (n < N-1) from
  * X_init (I_1 x .. x I_{N-1} x t_init, FP64).  cores_init[n] points to core n
  * in the column-major core layout; core N-1 has t_init slices.  Pointers are
- * host pointers unless x_is_device (X_init) / cores_on_device are set.    */
+ * host pointers unless x_is_device (X_init) / cores_on_device are set.
+ * cores_init == NULL: the cores are computed on the device by batch TR-ALS
+ * with normal equations (Alg. 2) on X_init, started from random cores of
+ * the counter-based generator (stream kind 2 of cfg->seed: Irwin-Hall
+ * normals) and stopped by cfg->init_tol / cfg->init_max_sweeps, as the
+ * protocol of Sec. 4 initialises every tracker (remark after Alg. 4: any
+ * method may give the initial cores).                                     */
 tr_status tr_stream_init(const tr_config *cfg, const double *X_init, int64_t t_init,
                          int32_t x_is_device, const double *const *cores_init,
                          int32_t cores_on_device, tr_stream **out);
@@ -118,16 +153,27 @@ tr_status tr_stream_get_PQ(tr_stream *s, int32_t n, double *P, double *Q);
  * row indexing the newest batch), as drawn by the counter-based generator. */
 tr_status tr_stream_get_samples(tr_stream *s, int32_t *idxs);
 
-/* Test hook (randomized variants, Alg. 3's Randsample bypassed): replaces
- * the current sample indices with a host N x m int32 row-major array laid
- * out as tr_stream_get_samples returns it.  Row q < N-1 indexes core q
+/* Test hook (randomized variants, the generator bypassed).
+ * idxs (may be NULL): replaces the current sample indices of Alg. 3's
+ * Randsample with a host N x m int32 row-major array laid out as
+ * tr_stream_get_samples returns it.  Row q < N-1 indexes core q
  * (0 <= idx < I_q); row N-1 indexes the newest temporal block
  * (0 <= idx < t of the last update, or t_init).  The next update uses the
  * injected rows until each is redrawn right after its core is updated,
- * exactly where drawn indices would be used.  Out-of-range entries give
- * TR_ERR_ARG and change nothing; no sketch configured gives TR_ERR_ARG.
- * Synchronous: the caller may reuse idxs on return.                       */
-tr_status tr_stream_set_samples(tr_stream *s, const int32_t *idxs);
+ * exactly where drawn indices would be used.
+ * signs (may be NULL; KSRFT only): the diagonals of D_1..D_N (Def. KSRFT)
+ * for the next time step instead of the generator's, int8 entries +1 / -1
+ * laid out as I_1 entries for D_1, then I_2 for D_2, .., then t_signs for
+ * the temporal D_N; the next update must bring t_signs slices
+ * (TR_ERR_SHAPE otherwise, before any state changes).
+ * Out-of-range indices, signs other than +-1, signs without the KSRFT
+ * sketch, both pointers NULL or no sketch configured give TR_ERR_ARG and
+ * change nothing.  Synchronous: the caller may reuse the arrays on return. */
+tr_status tr_stream_set_samples(tr_stream *s, const int32_t *idxs, const int8_t *signs,
+                                int64_t t_signs);
+
+/* Counters of the handle (see tr_stats).  Synchronises the handle's stream. */
+tr_status tr_stream_get_stats(tr_stream *s, tr_stats *out);
 
 /* Checkpoint of the streaming state between time steps (the quantities
  * Alg. 4 / Algs. 7-9 carry from one step to the next: the cores, the Gram
@@ -184,11 +230,35 @@ tr_status tr_mttkrp(int32_t N, const int64_t *dims, const int32_t *ranks, int32_
                     double *P_dev, int32_t accumulate, void *ws, size_t ws_bytes,
                     void *hip_stream);
 
-/* Q_n = (G^{!=n}_[2])^T G^{!=n}_[2] through the Gram-tensor chain
- * (Prop. subchain Gram), R_nR_{n+1} square row-major FP64 on the device.  */
-tr_status tr_gram_chain(int32_t N, const int64_t *dims, const int32_t *ranks, int32_t dt,
-                        int32_t n, const void *const *cores, double *Q_dev,
+/* Q_n = (G^{!=n}_[2])^T G^{!=n}_[2] = H^{!=n}_<2> through the chain of the
+ * Gram tensors (Prop. subchain Gram; Alg. 2's H^{!=n}).  Z_dev[k] (k != n,
+ * FP64 on the device) is the Gram tensor of core k, Z_k[b, a, b2, a2] =
+ * sum_i G_k[a, i, b] G_k[a2, i, b2], of size R_{k+1} x R_k x R_{k+1} x R_k
+ * stored column-major (Z_dev[n] is not read).  Q_dev: R_nR_{n+1} square,
+ * row-major, row/column index r + R_n s; accumulate = 1 adds to it (Q_n +=
+ * H_new of Alg. 4).  ws: the caller-owned workspace of tr_workspace_bytes
+ * (the chain's intermediate products; FP64 sizing), so the call allocates
+ * nothing.  dims are those of the stateless calls (all N sizes).          */
+tr_status tr_gram_chain(int32_t N, const int64_t *dims, const int32_t *ranks, int32_t n,
+                        const double *const *Z_dev, double *Q_dev, int32_t accumulate,
                         void *ws, size_t ws_bytes, void *hip_stream);
+
+/* Batch TR-ALS with normal equations (Alg. 2) on the device over a whole
+ * tensor X (I_1 x .. x I_{N-1} x T, FP64, host or device): the "Hot" batch
+ * baseline of the experiments (Sec. 4) when started from the previous
+ * cores, or a cold start from the counter-based random cores (cores_in
+ * NULL, stream kind 2 of cfg->seed).  cfg gives order, dims, ranks,
+ * compute_dtype, seed and device/stream (its sketch fields are ignored).
+ * Sweeps: modes 1..N in order, each solving G_{n(2)} H^{!=n}_<2> = M_n with
+ * the pseudo-inverse rule; it stops when the relative error changes by less
+ * than tol between sweeps or after max_sweeps.  cores_out: N host buffers
+ * in the column-major core layout (core N-1 with T slices).  rel_errs (host,
+ * may be NULL) receives the error of the start and after each sweep
+ * (*sweeps_done + 1 values, at most max_sweeps + 1); synchronous.          */
+tr_status tr_batch_als(const tr_config *cfg, const double *X, int64_t T, int32_t x_is_device,
+                       const double *const *cores_in, int32_t cores_on_device,
+                       int32_t max_sweeps, double tol, double *const *cores_out,
+                       double *rel_errs, int32_t *sweeps_done);
 
 /* Fit loss 1/2 ||TR(G) - X||_F^2 by direct residual; *loss_dev (FP64,
  * device) is written on the stream.                                       */

@@ -40,12 +40,23 @@ class tr_config(ctypes.Structure):
         ("sketch", c_int32),
         ("sketch_size", c_int64),
         ("rescale", c_int32),
-        ("temporal_literal", c_int32),
+        ("temporal_normal_eq", c_int32),
         ("seed", c_uint64),
         ("max_slices", c_int64),
         ("check_finite", c_int32),
         ("device", c_int32),
         ("hip_stream", c_void_p),
+        ("sweeps", c_int32),
+        ("init_max_sweeps", c_int32),
+        ("init_tol", c_double),
+    ]
+
+
+class tr_stats(ctypes.Structure):
+    _fields_ = [
+        ("pinv_fallbacks", c_int64),
+        ("init_sweeps", c_int32),
+        ("init_rel_err", c_double),
     ]
 
 
@@ -70,7 +81,10 @@ def load():
         "tr_stream_get_PQ": ([P, c_int32, P, P], c_int32),
         "tr_stream_sync": ([P], c_int32),
         "tr_stream_get_samples": ([P, P], c_int32),
-        "tr_stream_set_samples": ([P, P], c_int32),
+        "tr_stream_set_samples": ([P, P, P, c_int64], c_int32),
+        "tr_stream_get_stats": ([P, POINTER(tr_stats)], c_int32),
+        "tr_batch_als": ([POINTER(tr_config), P, c_int64, c_int32, P, c_int32, c_int32, c_double,
+                          POINTER(c_void_p), P, P], c_int32),
         "tr_stream_save": ([P, c_char_p], c_int32),
         "tr_stream_load": ([c_char_p, POINTER(tr_config), POINTER(c_void_p)], c_int32),
         "tr_stream_num_slices": ([P], c_int64),
@@ -81,7 +95,7 @@ def load():
         "tr_workspace_bytes": ([c_int32, P, P, c_int32], c_size_t),
         "tr_mttkrp": ([c_int32, P, P, c_int32, c_int32, P, POINTER(c_void_p), P, c_int32, P,
                        c_size_t, P], c_int32),
-        "tr_gram_chain": ([c_int32, P, P, c_int32, c_int32, POINTER(c_void_p), P, P, c_size_t,
+        "tr_gram_chain": ([c_int32, P, P, c_int32, POINTER(c_void_p), P, c_int32, P, c_size_t,
                            P], c_int32),
         "tr_fit_loss_fwd": ([c_int32, P, P, c_int32, P, POINTER(c_void_p), P, P, c_size_t, P],
                             c_int32),
@@ -160,27 +174,45 @@ def _ptr_array(ptrs):
 # functions with the C ABI's names
 # ---------------------------------------------------------------------------
 
-def tr_stream_init(X_init, cores_init, ranks, compute_dtype="f64", sketch=None, sketch_size=0,
-                   rescale=True, temporal_literal=False, seed=0, max_slices=0,
-                   check_finite=False, device=0, hip_stream=None):
-    """Returns an opaque handle (c_void_p).  X_init: (I_1..I_{N-1}, t_init)."""
-    lib = load()
-    shape = tuple(X_init.shape)
+def make_config(shape, ranks, compute_dtype="f64", sketch=None, sketch_size=0, rescale=True,
+                temporal_literal=True, seed=0, max_slices=0, check_finite=False, device=0,
+                hip_stream=None, sweeps=1, init_max_sweeps=0, init_tol=0.0):
+    """(tr_config, keepalive) for a tensor of `shape` (I_1..I_{N-1}, t)."""
     N = len(shape)
     dims = (c_int64 * (N - 1))(*shape[:-1])
     rk = (c_int32 * N)(*[int(r) for r in ranks])
     cfg = tr_config(order=N, dims=dims, ranks=rk, compute_dtype=DTYPES[compute_dtype],
                     sketch=SKETCHES[sketch], sketch_size=int(sketch_size),
-                    rescale=int(bool(rescale)), temporal_literal=int(bool(temporal_literal)),
+                    rescale=int(bool(rescale)), temporal_normal_eq=int(not temporal_literal),
                     seed=int(seed), max_slices=int(max_slices),
                     check_finite=int(bool(check_finite)), device=int(device),
-                    hip_stream=hip_stream)
+                    hip_stream=hip_stream, sweeps=int(sweeps),
+                    init_max_sweeps=int(init_max_sweeps), init_tol=float(init_tol))
+    return cfg, (dims, rk)
+
+
+def tr_stream_init(X_init, cores_init, ranks, compute_dtype="f64", sketch=None, sketch_size=0,
+                   rescale=True, temporal_literal=True, seed=0, max_slices=0,
+                   check_finite=False, device=0, hip_stream=None, sweeps=1, init_max_sweeps=0,
+                   init_tol=0.0):
+    """Returns an opaque handle (c_void_p).  X_init: (I_1..I_{N-1}, t_init).
+    cores_init None: the library initialises the cores by batch TR-ALS on
+    X_init from its counter-based random start (seed)."""
+    lib = load()
+    shape = tuple(X_init.shape)
+    cfg, ckeep = make_config(shape, ranks, compute_dtype, sketch, sketch_size, rescale,
+                             temporal_literal, seed, max_slices, check_finite, device, hip_stream,
+                             sweeps, init_max_sweeps, init_tol)
     xp, xkeep, xdev, _ = as_buffer(X_init, np.float64)
-    cbufs = [as_buffer(G, np.float64) for G in cores_init]
-    cdev = cbufs[0][2]
+    if cores_init is None:
+        cptr, cdev, cbufs = None, 0, []
+    else:
+        cbufs = [as_buffer(G, np.float64) for G in cores_init]
+        cdev = cbufs[0][2]
+        cptr = _ptr_array([b[0] for b in cbufs])
     handle = c_void_p()
-    code = lib.tr_stream_init(ctypes.byref(cfg), xp, shape[-1], xdev,
-                              _ptr_array([b[0] for b in cbufs]), cdev, ctypes.byref(handle))
+    code = lib.tr_stream_init(ctypes.byref(cfg), xp, shape[-1], xdev, cptr, cdev,
+                              ctypes.byref(handle))
     if code != 0:
         msg = ""
         if handle:
@@ -231,10 +263,52 @@ def tr_stream_get_samples(handle, N, m):
     return out
 
 
-def tr_stream_set_samples(handle, idxs):
-    """idxs: N x m integer array (row q = indices into core q)."""
-    a = np.ascontiguousarray(idxs, dtype=np.int32)
-    _check(load().tr_stream_set_samples(handle, a.ctypes.data), handle)
+def tr_stream_set_samples(handle, idxs=None, signs=None):
+    """idxs: N x m integer array (row q = indices into core q) or None;
+    signs: N vectors of +-1 (the D_k of the next KSRFT step, the last as long
+    as the next batch) or None."""
+    a = None if idxs is None else np.ascontiguousarray(idxs, dtype=np.int32)
+    sg, t = None, 0
+    if signs is not None:
+        sg = np.ascontiguousarray(np.concatenate([np.asarray(v).ravel() for v in signs]),
+                                  dtype=np.int8)
+        t = int(np.asarray(signs[-1]).size)
+    _check(load().tr_stream_set_samples(handle, None if a is None else a.ctypes.data,
+                                        None if sg is None else sg.ctypes.data, t), handle)
+
+
+def tr_stream_get_stats(handle):
+    """dict of the handle's counters (tr_stats)."""
+    st = tr_stats()
+    _check(load().tr_stream_get_stats(handle, ctypes.byref(st)), handle)
+    return {"pinv_fallbacks": st.pinv_fallbacks, "init_sweeps": st.init_sweeps,
+            "init_rel_err": st.init_rel_err}
+
+
+def tr_batch_als(X, ranks, cores_in=None, max_sweeps=100, tol=1e-8, compute_dtype="f64", seed=0,
+                 device=0, hip_stream=None):
+    """Batch TR-ALS-NE (Alg. 2) on the device over the whole tensor X
+    (I_1..I_{N-1}, T).  Returns (cores, rel_errs) with host cores
+    (R_n, I_n, R_{n+1}) and the error of the start and after every sweep."""
+    lib = load()
+    shape = tuple(X.shape)
+    N = len(shape)
+    cfg, ckeep = make_config(shape, ranks, compute_dtype, seed=seed, device=device,
+                             hip_stream=hip_stream)
+    xp, xkeep, xdev, _ = as_buffer(X, np.float64)
+    if cores_in is None:
+        cptr, cdev, cbufs = None, 0, []
+    else:
+        cbufs = [as_buffer(G, np.float64) for G in cores_in]
+        cdev = cbufs[0][2]
+        cptr = _ptr_array([b[0] for b in cbufs])
+    outs = [np.zeros((ranks[k], shape[k], ranks[(k + 1) % N]), order="F") for k in range(N)]
+    errs = np.zeros(int(max_sweeps) + 1)
+    done = c_int32()
+    _check(lib.tr_batch_als(ctypes.byref(cfg), xp, shape[-1], xdev, cptr, cdev, int(max_sweeps),
+                            float(tol), _ptr_array([o.ctypes.data for o in outs]),
+                            errs.ctypes.data, ctypes.byref(done)))
+    return outs, errs[:done.value + 1].copy()
 
 
 def tr_stream_save(handle, path):
@@ -317,10 +391,10 @@ def tr_mttkrp(dims, ranks, dt, n, X_ptr, core_ptrs, P_ptr, accumulate, ws_ptr, w
                             ws_ptr, ws_bytes, stream))
 
 
-def tr_gram_chain(dims, ranks, dt, n, core_ptrs, Q_ptr, ws_ptr, ws_bytes, stream):
+def tr_gram_chain(dims, ranks, n, Z_ptrs, Q_ptr, accumulate, ws_ptr, ws_bytes, stream):
     N, d, r = _shape_args(dims, ranks)
-    _check(load().tr_gram_chain(N, d, r, dt, n, _ptr_array(core_ptrs), Q_ptr, ws_ptr, ws_bytes,
-                                stream))
+    _check(load().tr_gram_chain(N, d, r, n, _ptr_array(Z_ptrs), Q_ptr, int(accumulate), ws_ptr,
+                                ws_bytes, stream))
 
 
 def tr_fit_loss_fwd(dims, ranks, dt, X_ptr, core_ptrs, loss_ptr, ws_ptr, ws_bytes, stream):

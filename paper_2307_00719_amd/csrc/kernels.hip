@@ -658,11 +658,164 @@ __global__ __launch_bounds__(256) void k_matmul(const double* __restrict__ A,
   if (row < d1 && col < d3) C[(size_t)row * d3 + col] = s;
 }
 
+// Transfer layout of a Gram tensor given in the paper's layout: Z of size
+// R' x R x R' x R (R = R_k, R' = R_{k+1}, column-major, the Gram tensor
+// Z[b, a, b2, a2] = sum_i G(i)[a, b] G(i)[a2, b2] of Alg. 2) to
+// E[(a + R a2), (b + R' b2)] (row-major), one thread per element.
+__global__ void k_z_to_E(const double* __restrict__ Z, int R, int R1, double* __restrict__ E) {
+  const int e = blockIdx.x * 256 + threadIdx.x;
+  const int n = R * R * R1 * R1;
+  if (e >= n) return;
+  const int row = e / (R1 * R1), col = e - row * (R1 * R1);
+  const int a = row % R, a2 = row / R, b = col % R1, b2 = col / R1;
+  E[e] = Z[b + R1 * (a + R * (b2 + R1 * a2))];
+}
+
+hipError_t launch_z_to_E(const double* Z, int R, int R1, double* E, hipStream_t st) {
+  const int n = R * R * R1 * R1;
+  hipLaunchKernelGGL(k_z_to_E, dim3((n + 255) / 256), dim3(256), 0, st, Z, R, R1, E);
+  return hipGetLastError();
+}
+
 hipError_t launch_matmul(const double* A, const double* B, double* C, int d1, int d2, int d3,
                          hipStream_t st) {
   dim3 grid((d3 + 15) / 16, (d1 + 15) / 16);
   hipLaunchKernelGGL(k_matmul, grid, dim3(256), 0, st, A, B, C, d1, d2, d3);
   return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Pseudo-inverse fallback of the normal-equation solves (the dagger in
+// G_{n(2)} = P_n Q_n^dagger of Alg. 4, and in Algs. 7-9).  The eliminations
+// below invert Q assuming it is positive definite; when one of their pivots
+// fails the positivity test the whole workgroup comes here instead and
+// replaces the result by the pseudo-inverse of the symmetric d x d matrix H.
+//
+// One-sided Jacobi (Hestenes): rotate pairs of columns of W (= H at the
+// start), accumulating the rotations in V, until every pair is orthogonal
+// to working precision.  Then H V = W, the column norms sigma_j = ||w_j||
+// are the singular values of H, and
+//   H^dagger = sum over sigma_j > tol of v_j w_j^T / sigma_j^2,
+//   tol = d * eps * max_j sigma_j
+// (singular values at or below tol are taken as zero, the cut-off of an
+// SVD pseudo-inverse).  The pairs of one round of a round-robin schedule
+// are disjoint, so groups of 16 lanes rotate them in parallel between
+// workgroup barriers.  W, V and the norms live in `work` (2 d^2 + d
+// doubles of global scratch).  status[2] counts the fallbacks, status[3] is
+// set for the solve that took one (the leverage scores read it), status[0]
+// is set to 2 if H holds NaN or Inf.  Every thread of the workgroup calls
+// it.
+// ---------------------------------------------------------------------------
+__device__ __noinline__ void pinv_fallback(const double* H, int d, double* Hinv, double* work,
+                                           int* status, int tid, int nthr) {
+  double* W = work;                       // column j at W + j d
+  double* V = work + (size_t)d * d;
+  double* sg = V + (size_t)d * d;
+  for (int e = tid; e < d * d; e += nthr) {
+    const int j = e / d, i = e - j * d;
+    W[e] = H[e];                          // H is symmetric: column j = row j
+    V[e] = i == j ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  const int grp = tid >> 4, ngrp = nthr >> 4, l = tid & 15;
+  const int D = d + (d & 1);              // an even count of columns: index d sits out
+  for (int sweep = 0; sweep < 48; ++sweep) {
+    int rot = 0;
+    for (int r = 0; r < D - 1; ++r) {
+      for (int k = grp; k < D / 2; k += ngrp) {
+        const int p = k == 0 ? r : (r + k) % (D - 1);
+        const int q = k == 0 ? D - 1 : (r + D - 1 - k) % (D - 1);
+        if (p >= d || q >= d) continue;   // the same for the 16 lanes of a group
+        double* wp = W + (size_t)p * d;
+        double* wq = W + (size_t)q * d;
+        double a = 0.0, b = 0.0, c = 0.0;
+        for (int i = l; i < d; i += 16) {
+          const double x = wp[i], y = wq[i];
+          a = fma(x, x, a);
+          b = fma(y, y, b);
+          c = fma(x, y, c);
+        }
+        for (int off = 8; off > 0; off >>= 1) {
+          a += __shfl_xor(a, off, 16);
+          b += __shfl_xor(b, off, 16);
+          c += __shfl_xor(c, off, 16);
+        }
+        if (c != 0.0 && fabs(c) > 1e-15 * sqrt(a * b)) {
+          // tan of the angle that makes the pair orthogonal (the smaller root
+          // of t^2 + 2 z t - 1 = 0, z = (b - a) / 2c)
+          const double z = (b - a) / (2.0 * c);
+          const double t = fabs(z) > 1e150 ? 0.5 / z
+                                           : (z >= 0.0 ? 1.0 : -1.0) / (fabs(z) + sqrt(1.0 + z * z));
+          const double cs = 1.0 / sqrt(1.0 + t * t), sn = cs * t;
+          double* vp = V + (size_t)p * d;
+          double* vq = V + (size_t)q * d;
+          for (int i = l; i < d; i += 16) {
+            const double x = wp[i], y = wq[i];
+            wp[i] = cs * x - sn * y;
+            wq[i] = sn * x + cs * y;
+            const double u = vp[i], v = vq[i];
+            vp[i] = cs * u - sn * v;
+            vq[i] = sn * u + cs * v;
+          }
+          rot = 1;
+        }
+      }
+      __syncthreads();
+    }
+    if (!__syncthreads_or(rot)) break;
+  }
+  for (int j = grp; j < d; j += ngrp) {
+    double a = 0.0;
+    for (int i = l; i < d; i += 16) a = fma(W[(size_t)j * d + i], W[(size_t)j * d + i], a);
+    for (int off = 8; off > 0; off >>= 1) a += __shfl_xor(a, off, 16);
+    if (l == 0) sg[j] = sqrt(a);
+  }
+  __syncthreads();
+  double smax = 0.0;
+  bool finite = true;
+  for (int j = 0; j < d; ++j) {
+    const double x = sg[j];
+    finite = finite && isfinite(x);
+    smax = fmax(smax, x);
+  }
+  const double tol = (double)d * 2.220446049250313e-16 * smax;
+  __syncthreads();
+  for (int j = tid; j < d; j += nthr) {
+    const double x = sg[j];
+    sg[j] = x > tol ? 1.0 / (x * x) : 0.0;
+  }
+  __syncthreads();
+  // upper triangle, mirrored: the result is exactly symmetric
+  for (int e = tid; e < d * d; e += nthr) {
+    const int i = e / d, k = e - i * d;
+    if (k < i) continue;
+    double acc = 0.0;
+    for (int j = 0; j < d; ++j) acc = fma(V[(size_t)j * d + i] * sg[j], W[(size_t)j * d + k], acc);
+    Hinv[(size_t)i * d + k] = acc;
+    Hinv[(size_t)k * d + i] = acc;
+  }
+  if (tid == 0 && status) {
+    if (!finite) status[0] = 2;
+    atomicAdd(status + 2, 1);
+    status[3] = 1;
+  }
+}
+
+// End of an elimination, by the whole workgroup, once `any` (some pivot of
+// the workgroup failed its test, from __syncthreads_or) is known and the
+// elimination's result has been stored only if `any` is false: the
+// pseudo-inverse fallback from the saved matrix H, or, without a saved
+// matrix or scratch, the failure flagged in status[0] (value 1).
+__device__ inline void finish_inverse(bool any, const double* H, int d, double* Hinv,
+                                      double* work, int* status, int tid, int nthr) {
+  if (any && H && work) {
+    pinv_fallback(H, d, Hinv, work, status, tid, nthr);
+    return;
+  }
+  if (tid == 0 && status) {
+    if (any) status[0] = 1;
+    status[3] = 0;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -681,7 +834,8 @@ template <int TG, int B>
 __global__ __launch_bounds__(TG* TG) void k_invert_spd(const double* __restrict__ M, int Ra,
                                                        int Rb, double* Q, int accumulate,
                                                        int store_Q, double* __restrict__ Qinv,
-                                                       int* status, int m_plain) {
+                                                       int* status, int m_plain, double* Hs,
+                                                       double* work) {
   __shared__ double rowk[2][TG * B], colk[2][TG * B];
   __shared__ double sh_tol;
   const int tid = threadIdx.x;
@@ -703,7 +857,10 @@ __global__ __launch_bounds__(TG* TG) void k_invert_spd(const double* __restrict_
           v = M[(size_t)(s1 + Rb * s2) * (Ra * Ra) + (r + Ra * r2)];
         }
         if (Q && accumulate) v += Q[e];
-        if (Q && store_Q) Q[e] = v;
+        if (Q && store_Q)
+          Q[e] = v;
+        else if (Hs)
+          Hs[e] = v;
       }
       a[i][j] = v;
     }
@@ -786,15 +943,18 @@ __global__ __launch_bounds__(TG* TG) void k_invert_spd(const double* __restrict_
         }
     }
   }
+  const bool any = __syncthreads_or(bad) != 0;
+  if (!any) {
 #pragma unroll
-  for (int i = 0; i < B; ++i) {
+    for (int i = 0; i < B; ++i) {
 #pragma unroll
-    for (int j = 0; j < B; ++j) {
-      const int gi = ty * B + i, gj = tx * B + j;
-      if (gi < d && gj < d) Qinv[gi * d + gj] = a[i][j];
+      for (int j = 0; j < B; ++j) {
+        const int gi = ty * B + i, gj = tx * B + j;
+        if (gi < d && gj < d) Qinv[gi * d + gj] = a[i][j];
+      }
     }
   }
-  if (bad && tid == 0 && status) status[0] = 1;
+  finish_inverse(any, Q && store_Q ? Q : Hs, d, Qinv, work, status, tid, TG * TG);
 }
 
 // Q-layout assembly alone (no inverse), one thread per element:
@@ -823,12 +983,12 @@ hipError_t launch_assemble_q(const double* M, int Ra, int Rb, double* Q, int acc
 
 hipError_t launch_invert_spd(const double* M, int Ra, int Rb, double* Q, int accumulate,
                              int store_Q, double* Qinv, int* status, hipStream_t st,
-                             int m_plain) {
+                             int m_plain, double* Hs, double* work) {
   const int d = Ra * Rb;
   if (d > 256) return hipErrorInvalidValue;
 #define TRK_INV(TG, B)                                                                    \
   hipLaunchKernelGGL((k_invert_spd<TG, B>), dim3(1), dim3(TG * TG), 0, st, M, Ra, Rb, Q, \
-                     accumulate, store_Q, Qinv, status, m_plain)
+                     accumulate, store_Q, Qinv, status, m_plain, Hs, work)
   const int B16 = (d + 15) / 16;
   switch (B16) {
     case 1: TRK_INV(16, 1); break;
@@ -934,7 +1094,10 @@ __global__ __launch_bounds__(1024) void k_side(SideArgs sa) {
         const int r = gi % Ra, s1 = gi / Ra, r2 = gj % Ra, s2 = gj / Ra;
         v = M[(size_t)(s1 + Rb * s2) * (Ra * Ra) + (r + Ra * r2)];
         if (sa.Q && sa.accumulate) v += sa.Q[e];
-        if (sa.Q && sa.store_Q) sa.Q[e] = v;
+        if (sa.Q && sa.store_Q)
+          sa.Q[e] = v;
+        else if (sa.Hs)
+          sa.Hs[e] = v;
       }
       a[i][j] = v;
     }
@@ -1015,15 +1178,19 @@ __global__ __launch_bounds__(1024) void k_side(SideArgs sa) {
         }
     }
   }
+  const bool any = __syncthreads_or(bad) != 0;
+  if (!any) {
 #pragma unroll
-  for (int i = 0; i < B; ++i) {
+    for (int i = 0; i < B; ++i) {
 #pragma unroll
-    for (int j = 0; j < B; ++j) {
-      const int gi = ty * B + i, gj = tx * B + j;
-      if (gi < d && gj < d) sa.Qinv[gi * d + gj] = a[i][j];
+      for (int j = 0; j < B; ++j) {
+        const int gi = ty * B + i, gj = tx * B + j;
+        if (gi < d && gj < d) sa.Qinv[gi * d + gj] = a[i][j];
+      }
     }
   }
-  if (bad && tid == 0 && sa.status) sa.status[0] = 1;
+  finish_inverse(any, sa.Q && sa.store_Q ? sa.Q : sa.Hs, d, sa.Qinv, sa.pw, sa.status, tid,
+                 1024);
 }
 
 // ---------------------------------------------------------------------------
@@ -1487,6 +1654,10 @@ __device__ inline void side_serial(const SideArgs& sa, double* lds, double* dmax
         // the mirror of an upper off-diagonal tile (the upper-triangle
         // elimination keeps only those; Q stays exactly symmetric)
         if (!COLS && ti != tj) sa.Q[gj * d + gi] = val;
+      } else if (ok && sa.Hs) {
+        // the matrix kept for the pseudo-inverse fallback
+        sa.Hs[gi * d + gj] = val;
+        if (!COLS && ti != tj) sa.Hs[gj * d + gi] = val;
       }
       if (ok && gi == gj) mx = fmax(mx, val);
       A[s][v] = ok ? val : (gi == gj ? 1.0 : 0.0);
@@ -1600,23 +1771,26 @@ __device__ inline void side_serial(const SideArgs& sa, double* lds, double* dmax
     if (!dbuf) __syncthreads();
   }
   }
+  const bool any = __syncthreads_or(bad) != 0;
   const int cl = lane & 15;
+  if (!any) {
 #pragma unroll
-  for (int s = 0; s < MAXT; ++s) {
-    if (TV[s]) {
-      const int ti = TI[s], tj = TJ[s];
+    for (int s = 0; s < MAXT; ++s) {
+      if (TV[s]) {
+        const int ti = TI[s], tj = TJ[s];
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int gi = ti * 16 + Acc<double>::row(lane, v), gj = tj * 16 + cl;
-        if (gi < d && gj < d) {
-          sa.Qinv[gi * d + gj] = A[s][v];
-          // all blocks pivoted: the inverse is symmetric
-          if (!COLS && ti != tj) sa.Qinv[gj * d + gi] = A[s][v];
+        for (int v = 0; v < 4; ++v) {
+          const int gi = ti * 16 + Acc<double>::row(lane, v), gj = tj * 16 + cl;
+          if (gi < d && gj < d) {
+            sa.Qinv[gi * d + gj] = A[s][v];
+            // all blocks pivoted: the inverse is symmetric
+            if (!COLS && ti != tj) sa.Qinv[gj * d + gi] = A[s][v];
+          }
         }
       }
     }
   }
-  if (bad && lane == 0 && sa.status) sa.status[0] = 1;
+  finish_inverse(any, storeQ ? sa.Q : sa.Hs, d, sa.Qinv, sa.pw, sa.status, tid, NW * 64);
 }
 
 // One upper-triangle 16x16 tile (index `tile`, row-major over the upper

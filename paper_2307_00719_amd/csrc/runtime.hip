@@ -34,7 +34,8 @@ struct tr_stream {
   int dt = F64;
   int sketch = 0;
   int64_t m = 0;
-  int rescale = 1, temporal_literal = 0, check_finite = 0;
+  int rescale = 1, temporal_literal = 1, check_finite = 0;
+  int sweeps = 1;               // passes of the update stage over each batch
   uint64_t seed = 0;
   int device = 0;
   int ncu = 0;                  // compute units of the device
@@ -48,6 +49,14 @@ struct tr_stream {
   double* Q[MAXN] = {};
   double* Minv = nullptr;
   double* MinvM[MAXN] = {};    // per-mode inverses (two-stream STR update)
+  double* Pold[MAXN] = {};     // P_n, Q_n before the batch (multi-pass updates)
+  double* Qold[MAXN] = {};
+  double* pinvH = nullptr;     // matrix copy and scratch of the pseudo-inverse fallback
+  double* pinvW = nullptr;
+  int32_t init_sweeps = 0;     // batch TR-ALS sweeps run by the initialiser
+  double init_err = 0.0;       // its final relative error
+  std::vector<double> next_signs;  // injected D_k of the next step (KSRFT)
+  int64_t next_signs_t = 0;
   double* chain[2] = {};
   unsigned* sidecnt = nullptr;  // arrival counter of the side kernel's Gram workgroups
   hipStream_t side = nullptr;  // second stream: Gram refresh, chain, inverse
@@ -307,10 +316,15 @@ void prof_end(tr_stream* s, long rec, hipStream_t on = nullptr) {
   (void)hipEventRecord(s->ev_pool[s->rec_ev[rec] + 1], on ? on : s->st);
 }
 
+// Device status words: [0] 1 = an elimination failed with no fallback
+// scratch, 2 = a normal-equation matrix held NaN or Inf; [1] finite check
+// of a device batch; [2] count of pseudo-inverse fallbacks; [3] whether the
+// last solve fell back.
 tr_status read_status(tr_stream* s) {
   int st[2] = {0, 0};
   TR_HIP(hipMemcpyAsync(st, s->dstatus, sizeof(int), hipMemcpyDeviceToHost, s->st));
   TR_HIP(hipStreamSynchronize(s->st));
+  if (st[0] == 2) return poison(s, TR_ERR_NONFINITE, "a normal-equation matrix holds NaN or Inf");
   if (st[0]) return poison(s, TR_ERR_SINGULAR, "a normal-equation matrix was not positive definite");
   return TR_OK;
 }
@@ -334,15 +348,16 @@ tr_status leverage_probs(tr_stream* s, int k, const double* rows, int64_t I, dou
     // G^T G of the rows and its inverse (one side kernel for d <= 192)
     tr_status c = gram_update_invert(s, s->st, s->Zb, Ra, Rb, nullptr, 0, s->Zi, rows, nullptr, I);
     if (c != TR_OK) return c;
-    TR_HIP(launch_leverage(rows, I, d, s->Zi, p, s->st));
+    TR_HIP(launch_leverage(rows, I, d, s->Zi, nullptr, nullptr, p, s->st));
   } else {
     if (I > 256) return poison(s, TR_ERR_UNSUPPORTED, "leverage rank check needs I <= 256");
     // full row rank: the row Gram G G^T passes the positivity test of the
-    // elimination (its inverse is not used)
+    // elimination (its inverse is not used); otherwise the elimination's
+    // pseudo-inverse K^+ gives the scores diag(K K^+)
     TR_HIP(launch_row_gram(rows, I, d, s->Zb, s->st));
     tr_status c = gram_update_invert(s, s->st, s->Zb, (int)I, 1, nullptr, 0, s->Zi);
     if (c != TR_OK) return c;
-    TR_HIP(launch_leverage(rows, I, d, nullptr, p, s->st));
+    TR_HIP(launch_leverage(rows, I, d, s->Zi, s->Zb, s->dstatus + 3, p, s->st));
   }
   return TR_OK;
 }
@@ -415,11 +430,14 @@ tr_status gram_update_invert(tr_stream* s, hipStream_t on, double* M, int Ra, in
     a.Qinv = Qinv;
     a.status = s->dstatus;
     a.counter = s->sidecnt;
+    a.Hs = s->pinvH;
+    a.pw = s->pinvW;
     TR_HIP(launch_side(a, on));
     return TR_OK;
   }
   if (A) TR_HIP(launch_wgram(A, w, rows, d, M, on));
-  TR_HIP(launch_invert_spd(M, Ra, Rb, Q, accumulate, 1, Qinv, s->dstatus, on, 1));
+  TR_HIP(launch_invert_spd(M, Ra, Rb, Q, accumulate, 1, Qinv, s->dstatus, on, 1, s->pinvH,
+                           s->pinvW));
   return TR_OK;
 }
 
@@ -553,6 +571,20 @@ tr_status ksrft_signs(tr_stream* s, int64_t t) {
     TR_HIP(dev_alloc(&s->dsign[N - 1], (size_t)t));
     s->ksign_cap = t;
   }
+  if (!s->next_signs.empty()) {
+    // injected D_k (tr_stream_set_samples): checked against t by the update
+    int64_t off = 0;
+    for (int k = 0; k < N; ++k) {
+      const int64_t n = k == N - 1 ? t : s->I[k];
+      TR_HIP(hipMemcpyAsync(s->dsign[k], s->next_signs.data() + off, n * sizeof(double),
+                            hipMemcpyHostToDevice, s->st));
+      off += n;
+    }
+    TR_HIP(hipStreamSynchronize(s->st));
+    s->next_signs.clear();
+    s->next_signs_t = 0;
+    return TR_OK;
+  }
   for (int k = 0; k < N; ++k) {
     const int64_t n = k == N - 1 ? t : s->I[k];
     TR_HIP(launch_signs(rng_key(s->seed, (uint64_t)s->step, (uint64_t)k, 1), n, s->dsign[k],
@@ -607,8 +639,9 @@ tr_status ksrft_slices(tr_stream* s, int k, const double* rows, int64_t I) {
 // One mode of Alg. 9: Re(Q_n) += Re(Ghat_S^T W conj(Ghat_S)) and
 // Re(P_n) += Re(D_n F_n^* Xhat_S W conj(Ghat_S)), then G_n = Re(P_n) Re(Q_n)^-1
 // when `solve`; for the temporal mode (n = N-1) the rows G_N^new are written
-// to Gout from the increments alone (or the literal reading
-// Re(D F^* Xhat_S) (Re(Ghat_S)^T)^+ when temporal_literal is set).
+// to Gout: by default in the printed form Re(D F^* Xhat_S) (Re(Ghat_S)^T)^+
+// (the KSRFT paragraph of Sec. 3.3, Alg. 9), or, with temporal_literal
+// cleared, from the increments alone (real-constrained normal equations).
 tr_status ksrft_increment(tr_stream* s, int n, const void* xhat, int64_t t, int accumulate,
                           bool solve, double* Gout) {
   const int N = s->N;
@@ -742,6 +775,8 @@ tr_status check_config(const tr_config* cfg, int64_t t_first) {
   }
   for (int k = 0; k < N; ++k)
     if (cfg->ranks[k] * cfg->ranks[(k + 1) % N] > 256) return TR_ERR_UNSUPPORTED;
+  if (cfg->sweeps < 0 || cfg->init_max_sweeps < 0) return TR_ERR_ARG;
+  if (cfg->sweeps > 1 && cfg->sketch != TR_SKETCH_NONE) return TR_ERR_UNSUPPORTED;
   return TR_OK;
 }
 
@@ -758,7 +793,8 @@ tr_status create_handle(const tr_config* cfg, int64_t t_slices, tr_stream** out)
   s->sketch = cfg->sketch;
   s->m = cfg->sketch_size;
   s->rescale = cfg->rescale;
-  s->temporal_literal = cfg->temporal_literal;
+  s->temporal_literal = cfg->temporal_normal_eq ? 0 : 1;
+  s->sweeps = cfg->sweeps > 1 ? cfg->sweeps : 1;
   s->seed = cfg->seed;
   s->check_finite = cfg->check_finite;
   s->device = cfg->device;
@@ -789,6 +825,16 @@ tr_status create_handle(const tr_config* cfg, int64_t t_slices, tr_stream** out)
   }
   TR_HIP(dev_alloc(&s->Minv, (size_t)dmax * dmax));
   for (int k = 0; k < N; ++k) TR_HIP(dev_alloc(&s->MinvM[k], (size_t)dmax * dmax));
+  // pseudo-inverse fallback: the largest matrix an elimination inverts is
+  // d x d, or the row Gram of a leverage rank check (at most 256 x 256)
+  const int dfb = s->sketch == TR_SKETCH_NONE ? dmax : 256;
+  TR_HIP(dev_alloc(&s->pinvH, (size_t)dfb * dfb));
+  TR_HIP(dev_alloc(&s->pinvW, (size_t)2 * dfb * dfb + dfb));
+  if (s->sweeps > 1)
+    for (int k = 0; k < N - 1; ++k) {
+      TR_HIP(dev_alloc(&s->Pold[k], (size_t)s->I[k] * s->d(k)));
+      TR_HIP(dev_alloc(&s->Qold[k], (size_t)s->d(k) * s->d(k)));
+    }
   TR_HIP(hipStreamCreateWithFlags(&s->side, hipStreamNonBlocking));
   // ordering events between the two streams of one device: a device-scope
   // release suffices (each kernel's dispatch already releases its writes to
@@ -835,11 +881,11 @@ tr_status create_handle(const tr_config* cfg, int64_t t_slices, tr_stream** out)
 
 // ---- saved state (tr_stream_save / tr_stream_load) --------------------------
 
-const char kSaveMagic[8] = {'T', 'R', 'S', 'T', 'A', 'T', 'E', '1'};
+const char kSaveMagic[8] = {'T', 'R', 'S', 'T', 'A', 'T', 'E', '2'};
 
 struct SaveHeader {
   char magic[8];
-  int32_t N, dt, sketch, rescale, temporal_literal, check_finite;
+  int32_t N, dt, sketch, rescale, temporal_literal, check_finite, sweeps, pad;
   int64_t m, t_total, step, last_t;
   uint64_t seed;
   int64_t dims[MAXN];
@@ -888,129 +934,165 @@ uint64_t fnv1a(const char* p, size_t n) {
   return h;
 }
 
-}  // namespace
-
-extern "C" {
-
-tr_status tr_stream_init(const tr_config* cfg, const double* X_init, int64_t t_init,
-                         int32_t x_is_device, const double* const* cores_init,
-                         int32_t cores_on_device, tr_stream** out) {
-  if (!cfg || !out || !X_init || !cores_init) return TR_ERR_ARG;
-  *out = nullptr;
-  tr_status c = check_config(cfg, t_init);
-  if (c != TR_OK) return c;
-  c = create_handle(cfg, t_init, out);
-  tr_stream* s = *out;
-  if (c != TR_OK) return c;
+// Cores in the column-major core layout (FP64, host or device; core N-1
+// with T slices) to the slice-major state rows.
+tr_status load_cores(tr_stream* s, const double* const* cores, int on_device, int64_t T) {
   const int N = s->N;
-
-  // cores: column-major FP64 (host or device) -> slice-major state
   std::vector<int64_t> dims(N);
   for (int k = 0; k < N - 1; ++k) dims[k] = s->I[k];
-  dims[N - 1] = t_init;
+  dims[N - 1] = T;
   size_t maxcore = 0;
   for (int k = 0; k < N; ++k) maxcore = std::max(maxcore, (size_t)dims[k] * s->d(k));
   double* tmp = nullptr;
-  if (!cores_on_device) TR_HIP(dev_alloc(&tmp, maxcore));
-  for (int k = 0; k < N; ++k) {
+  if (!on_device) TR_HIP(dev_alloc(&tmp, maxcore));
+  tr_status c = TR_OK;
+  for (int k = 0; k < N && c == TR_OK; ++k) {
     const size_t cnt = (size_t)dims[k] * s->d(k);
-    const double* src = cores_init[k];
-    if (!src) return poison(s, TR_ERR_ARG, "null core pointer");
-    if (!cores_on_device) {
+    const double* src = cores[k];
+    if (!src) {
+      c = poison(s, TR_ERR_ARG, "null core pointer");
+      break;
+    }
+    if (!on_device) {
       TR_HIP(hipMemcpyAsync(tmp, src, cnt * sizeof(double), hipMemcpyHostToDevice, s->st));
       src = tmp;
     }
     TR_HIP(launch_core_to_slices(src, F64, 1, s->R[k], (int64_t)s->R[k] * dims[k], dims[k],
                                  s->R[k], s->R[(k + 1) % N], s->G[k], s->st));
-    if (!cores_on_device) TR_HIP(hipStreamSynchronize(s->st));
+    if (!on_device) TR_HIP(hipStreamSynchronize(s->st));
   }
   if (tmp) TR_HIP(hipFree(tmp));
-  s->t_total = t_init;
-  s->last_t = t_init;
+  return c;
+}
 
-  // Gram matrices (Alg. 4 initialisation; Z_N over the initial temporal rows)
-  for (int k = 0; k < N; ++k) {
-    const int64_t rows = k == N - 1 ? t_init : s->I[k];
-    TR_HIP(launch_gram_E(s->G[k], rows, s->R[k], s->R[(k + 1) % N], s->E[k], s->st));
-  }
-  // X_init on the device in the compute dtype
-  int64_t J = 1;
-  for (int k = 0; k < N - 1; ++k) J *= s->I[k];
-  const void* Xd = nullptr;
-  c = stage_batch(s, X_init, F64, J * t_init, x_is_device, &Xd);
-  if (c != TR_OK) return c;
+// ---- batch TR-ALS with normal equations (Alg. 2) ----------------------------
 
-  std::vector<int64_t> gd(dims);
-  const CoreView cv = state_view(s, s->G[N - 1]);
-  if (s->sketch != TR_SKETCH_NONE) {
-    c = s->sketch == TR_SKETCH_KSRFT ? ksrft_init(s, Xd, t_init) : sketch_init(s, Xd, t_init);
-    if (c != TR_OK) return c;
-    TR_HIP(hipStreamSynchronize(s->st));
-    s->copy_pending = false;
-    return read_status(s);
+// ||X - TR(G)|| / ||X|| of the state cores over the T slices of Xd (compute
+// dtype), synchronous.
+tr_status state_error(tr_stream* s, const void* Xd, int64_t T, double* out) {
+  const int N = s->N;
+  std::vector<int64_t> gd(N);
+  for (int k = 0; k < N - 1; ++k) gd[k] = s->I[k];
+  gd[N - 1] = T;
+  Geom g = make_geom(N, gd.data(), s->R, N - 1);
+  const int nwg = recon_err_blocks(g);
+  if ((size_t)nwg * 2 > s->wg_n) {
+    if (s->wg) {
+      TR_HIP(hipStreamSynchronize(s->st));
+      TR_HIP(hipFree(s->wg));
+    }
+    TR_HIP(dev_alloc(&s->wg, (size_t)nwg * 2));
+    s->wg_n = (size_t)nwg * 2;
   }
-  for (int n = 0; n < N - 1; ++n) {
-    Geom g = make_geom(N, gd.data(), s->R, n);
-    MttkrpPlan p = plan_mttkrp(g, s->dt);
-    c = ensure_partials(s, g, p);
-    if (c != TR_OK) return c;
-    TR_HIP(launch_mttkrp(g, p, Xd, s->dt, cv, F64, s->part, s->st));
-    TR_HIP(launch_reduce_solve(s->part, p.psize, p.nsplit, g.In, g.d, s->P[n], 0, nullptr,
-                               nullptr, s->st));
-    hipError_t he;
-    const double* M = chain_product(s, n, s->E[N - 1], &he);
-    TR_HIP(he);
-    TR_HIP(launch_assemble_q(M, s->R[n], s->R[(n + 1) % N], s->Q[n], 0, s->st));
-  }
+  int got = 0;
+  TR_HIP(launch_recon_err(g, Xd, s->dt, state_view(s, s->G[N - 1]), F64, s->G[N - 1], s->wg, &got,
+                          s->st));
+  TR_HIP(launch_sum_pairs(s->wg, got, s->pair, s->st));
+  double h[2];
+  TR_HIP(hipMemcpyAsync(h, s->pair, sizeof(h), hipMemcpyDeviceToHost, s->st));
   TR_HIP(hipStreamSynchronize(s->st));
-  s->copy_pending = false;
+  *out = h[1] > 0 ? std::sqrt(h[0] / h[1]) : std::sqrt(h[0]);
   return TR_OK;
 }
 
-tr_status tr_stream_update(tr_stream* s, const void* X_new, int32_t x_dtype, int64_t t_new,
-                           int32_t x_is_device) {
-  if (!s) return TR_ERR_ARG;
-  if (s->poisoned != TR_OK) return s->poisoned;
-  if (!X_new) return fail(s, TR_ERR_ARG, "null batch");
-  if (t_new < 1) return fail(s, TR_ERR_SHAPE, "t_new must be positive");
-  if (x_dtype != TR_F64 && x_dtype != TR_F32) return fail(s, TR_ERR_UNSUPPORTED, "batch dtype");
+// Batch TR-ALS with normal equations (Alg. 2) on the state cores, over the
+// T slices of Xd: per sweep the modes n = 0..N-1 in order, each with
+//   H^{!=n} from the Gram tensors of the other cores (Gram refresh of the
+//   core updated just before, Gram chain, (pseudo-)inverse: side kernel),
+//   M_n = X_[n] G^{!=n}_[2] (MTTKRP over all T slices),
+//   G_{n(2)} = M_n (H^{!=n}_<2>)^dagger (reduction + solve),
+// and the relative error after the sweep; it stops when the error changes
+// by less than `tol` or after max_sweeps (the stopping rule of the Sec. 4
+// protocol).  errs receives the error of the starting cores and of every
+// sweep.  The Gram tensors of the final cores are left in E.
+tr_status als_run(tr_stream* s, const void* Xd, int64_t T, int max_sweeps, double tol,
+                  std::vector<double>* errs) {
   const int N = s->N;
-  TR_HIP(hipSetDevice(s->device));
-  int64_t J = 1;
-  for (int k = 0; k < N - 1; ++k) J *= s->I[k];
-  tr_status c = grow_temporal(s, s->t_total + t_new);
-  if (c != TR_OK) return c;
-  const void* Xd = nullptr;
-  c = stage_batch(s, X_new, x_dtype, J * t_new, x_is_device, &Xd);
-  if (c != TR_OK) return c;
-
   std::vector<int64_t> gd(N);
   for (int k = 0; k < N - 1; ++k) gd[k] = s->I[k];
-  gd[N - 1] = t_new;
-  const int dN = s->d(N - 1);
-  double* Gnew = s->G[N - 1] + (size_t)s->t_total * dN;
-  hipError_t he;
-
-  if (s->sketch != TR_SKETCH_NONE) {
-    const long pst = prof_begin(s, PK_STEP);
-    if (s->sketch == TR_SKETCH_KSRFT && t_new > 256)
-      return fail(s, TR_ERR_UNSUPPORTED, "KSRFT batches hold at most 256 slices");
-    c = s->sketch == TR_SKETCH_KSRFT ? ksrft_update(s, Xd, t_new, Gnew)
-                                     : sketch_update(s, Xd, t_new, Gnew);
+  gd[N - 1] = T;
+  for (int k = 0; k < N; ++k)
+    TR_HIP(launch_gram_E(s->G[k], gd[k], s->R[k], s->R[(k + 1) % N], s->E[k], s->st));
+  double e = 0.0;
+  tr_status c = state_error(s, Xd, T, &e);
+  if (c != TR_OK) return c;
+  errs->push_back(e);
+  const CoreView cv = state_view(s, s->G[N - 1]);
+  int sw = 0;
+  while (sw < max_sweeps) {
+    for (int n = 0; n < N; ++n) {
+      const int p = (n + N - 1) % N;
+      SideArgs a;
+      std::memset(&a, 0, sizeof(a));
+      a.Gp = s->G[p];
+      a.rows_p = gd[p];
+      a.Rpa = s->R[p];
+      a.Rpb = s->R[(p + 1) % N];
+      a.Ep = s->E[p];
+      a.nfac = N - 1;
+      for (int j = 0; j < N - 1; ++j) {
+        const int q = (n + 1 + j) % N;
+        a.fac[j] = s->E[q];
+        a.fr[j] = s->R[q] * s->R[q];
+        a.fc[j] = s->R[(q + 1) % N] * s->R[(q + 1) % N];
+      }
+      a.cbuf[0] = s->chain[0];
+      a.cbuf[1] = s->chain[1];
+      a.Ra = s->R[n];
+      a.Rb = s->R[(n + 1) % N];
+      a.Qinv = s->MinvM[n];
+      a.status = s->dstatus;
+      a.counter = s->sidecnt;
+      a.Hs = s->pinvH;
+      a.pw = s->pinvW;
+      TR_HIP(launch_side(a, s->st));
+      Geom g = make_geom(N, gd.data(), s->R, n);
+      MttkrpPlan pl = plan_mttkrp(g, s->dt);
+      c = ensure_partials(s, g, pl);
+      if (c != TR_OK) return c;
+      TR_HIP(launch_mttkrp(g, pl, Xd, s->dt, cv, F64, s->part, s->st));
+      TR_HIP(launch_reduce_solve(s->part, pl.psize, pl.nsplit, g.In, g.d, nullptr, 0, s->MinvM[n],
+                                 s->G[n], s->st));
+    }
+    ++sw;
+    c = state_error(s, Xd, T, &e);
     if (c != TR_OK) return c;
-    prof_end(s, pst);
-    s->t_total += t_new;
-    s->last_t = t_new;
-    return TR_OK;
+    errs->push_back(e);
+    if (std::fabs((*errs)[errs->size() - 2] - e) < tol) break;
   }
+  TR_HIP(launch_gram_E(s->G[N - 1], T, s->R[N - 1], s->R[0], s->E[N - 1], s->st));
+  s->init_sweeps = sw;
+  s->init_err = e;
+  return read_status(s);
+}
+
+// Random start of the batch TR-ALS: core k (slice-major state rows) from
+// the initial-core stream of the counter-based generator (kind 2).
+tr_status random_cores(tr_stream* s, int64_t T) {
+  const int N = s->N;
+  for (int k = 0; k < N; ++k) {
+    const int64_t I = k == N - 1 ? T : s->I[k];
+    TR_HIP(launch_init_normal(rng_key(s->seed, 0, (uint64_t)k, 2), s->R[k], I, s->R[(k + 1) % N],
+                              s->G[k], s->st));
+  }
+  return TR_OK;
+}
+
+// One pass of the STR update stage (Alg. 4) over the batch Xd of t_new
+// slices (compute dtype), writing the new temporal rows at Gnew.
+tr_status str_pass(tr_stream* s, const void* Xd, int64_t t_new, double* Gnew) {
   // Per mode: the side step (Gram refresh of the core updated just before,
   // Gram chain, Q update, inverse), the MTTKRP, then the split reduction +
   // solve, which needs both.  When every mode fits the fused launch the side
   // step and the MTTKRP share one kernel on the caller's stream.  Otherwise
   // the side stream carries the serial chain (side kernel, then solve) and
   // the caller's stream the MTTKRPs, each after the solve before it.
+  const int N = s->N;
+  std::vector<int64_t> gd(N);
+  for (int k = 0; k < N - 1; ++k) gd[k] = s->I[k];
+  gd[N - 1] = t_new;
+  tr_status c;
   hipStream_t side = s->side;
-  const long pstep = prof_begin(s, PK_STEP);
   long pr;
   auto side_args = [&](int n, int p, const double* Gp, int64_t rows_p) {
     // every field not set below (the Gram's row weights Gw among them) is
@@ -1039,6 +1121,8 @@ tr_status tr_stream_update(tr_stream* s, const void* X_new, int32_t x_dtype, int
     a.Qinv = s->MinvM[n];
     a.status = s->dstatus;
     a.counter = s->sidecnt;
+    a.Hs = s->pinvH;
+    a.pw = s->pinvW;
     return a;
   };
   auto side_of = [&](int n) {
@@ -1072,9 +1156,6 @@ tr_status tr_stream_update(tr_stream* s, const void* X_new, int32_t x_dtype, int
                                    s->MinvM[n], s->G[n], s->st));
       prof_end(s, pr);
     }
-    prof_end(s, pstep);
-    s->t_total += t_new;
-    s->last_t = t_new;
     return TR_OK;
   }
   // otherwise two streams.  Modes in order: temporal (its side kernel also
@@ -1112,6 +1193,136 @@ tr_status tr_stream_update(tr_stream* s, const void* X_new, int32_t x_dtype, int
   }
   TR_HIP(hipEventRecord(s->ev_join, side));
   TR_HIP(hipStreamWaitEvent(s->st, s->ev_join, 0));
+  return TR_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+tr_status tr_stream_init(const tr_config* cfg, const double* X_init, int64_t t_init,
+                         int32_t x_is_device, const double* const* cores_init,
+                         int32_t cores_on_device, tr_stream** out) {
+  if (!cfg || !out || !X_init) return TR_ERR_ARG;
+  *out = nullptr;
+  tr_status c = check_config(cfg, t_init);
+  if (c != TR_OK) return c;
+  c = create_handle(cfg, t_init, out);
+  tr_stream* s = *out;
+  if (c != TR_OK) return c;
+  const int N = s->N;
+
+  if (cores_init) {
+    c = load_cores(s, cores_init, cores_on_device, t_init);
+    if (c != TR_OK) return c;
+  }
+  s->t_total = t_init;
+  s->last_t = t_init;
+
+  // X_init on the device in the compute dtype
+  int64_t J = 1;
+  for (int k = 0; k < N - 1; ++k) J *= s->I[k];
+  const void* Xd = nullptr;
+  c = stage_batch(s, X_init, F64, J * t_init, x_is_device, &Xd);
+  if (c != TR_OK) return c;
+  if (!cores_init) {
+    // no initial cores: batch TR-ALS (Alg. 2) on X_init from the random
+    // start, as the protocol of Sec. 4 initialises the trackers
+    c = random_cores(s, t_init);
+    if (c != TR_OK) return c;
+    std::vector<double> errs;
+    c = als_run(s, Xd, t_init, cfg->init_max_sweeps > 0 ? cfg->init_max_sweeps : 100,
+                cfg->init_tol > 0 ? cfg->init_tol : 1e-8, &errs);
+    if (c != TR_OK) return c;
+  }
+  // Gram matrices (Alg. 4 initialisation; Z_N over the initial temporal rows)
+  for (int k = 0; k < N; ++k) {
+    const int64_t rows = k == N - 1 ? t_init : s->I[k];
+    TR_HIP(launch_gram_E(s->G[k], rows, s->R[k], s->R[(k + 1) % N], s->E[k], s->st));
+  }
+
+  std::vector<int64_t> gd(N);
+  for (int k = 0; k < N - 1; ++k) gd[k] = s->I[k];
+  gd[N - 1] = t_init;
+  const CoreView cv = state_view(s, s->G[N - 1]);
+  if (s->sketch != TR_SKETCH_NONE) {
+    c = s->sketch == TR_SKETCH_KSRFT ? ksrft_init(s, Xd, t_init) : sketch_init(s, Xd, t_init);
+    if (c != TR_OK) return c;
+    TR_HIP(hipStreamSynchronize(s->st));
+    s->copy_pending = false;
+    return read_status(s);
+  }
+  for (int n = 0; n < N - 1; ++n) {
+    Geom g = make_geom(N, gd.data(), s->R, n);
+    MttkrpPlan p = plan_mttkrp(g, s->dt);
+    c = ensure_partials(s, g, p);
+    if (c != TR_OK) return c;
+    TR_HIP(launch_mttkrp(g, p, Xd, s->dt, cv, F64, s->part, s->st));
+    TR_HIP(launch_reduce_solve(s->part, p.psize, p.nsplit, g.In, g.d, s->P[n], 0, nullptr,
+                               nullptr, s->st));
+    hipError_t he;
+    const double* M = chain_product(s, n, s->E[N - 1], &he);
+    TR_HIP(he);
+    TR_HIP(launch_assemble_q(M, s->R[n], s->R[(n + 1) % N], s->Q[n], 0, s->st));
+  }
+  TR_HIP(hipStreamSynchronize(s->st));
+  s->copy_pending = false;
+  return TR_OK;
+}
+
+tr_status tr_stream_update(tr_stream* s, const void* X_new, int32_t x_dtype, int64_t t_new,
+                           int32_t x_is_device) {
+  if (!s) return TR_ERR_ARG;
+  if (s->poisoned != TR_OK) return s->poisoned;
+  if (!X_new) return fail(s, TR_ERR_ARG, "null batch");
+  if (t_new < 1) return fail(s, TR_ERR_SHAPE, "t_new must be positive");
+  if (x_dtype != TR_F64 && x_dtype != TR_F32) return fail(s, TR_ERR_UNSUPPORTED, "batch dtype");
+  if (!s->next_signs.empty() && s->next_signs_t != t_new)
+    return fail(s, TR_ERR_SHAPE, "injected temporal signs do not match the batch size");
+  const int N = s->N;
+  TR_HIP(hipSetDevice(s->device));
+  int64_t J = 1;
+  for (int k = 0; k < N - 1; ++k) J *= s->I[k];
+  tr_status c = grow_temporal(s, s->t_total + t_new);
+  if (c != TR_OK) return c;
+  const void* Xd = nullptr;
+  c = stage_batch(s, X_new, x_dtype, J * t_new, x_is_device, &Xd);
+  if (c != TR_OK) return c;
+
+  const int dN = s->d(N - 1);
+  double* Gnew = s->G[N - 1] + (size_t)s->t_total * dN;
+
+  if (s->sketch != TR_SKETCH_NONE) {
+    const long pst = prof_begin(s, PK_STEP);
+    if (s->sketch == TR_SKETCH_KSRFT && t_new > 256)
+      return fail(s, TR_ERR_UNSUPPORTED, "KSRFT batches hold at most 256 slices");
+    c = s->sketch == TR_SKETCH_KSRFT ? ksrft_update(s, Xd, t_new, Gnew)
+                                     : sketch_update(s, Xd, t_new, Gnew);
+    if (c != TR_OK) return c;
+    prof_end(s, pst);
+    s->t_total += t_new;
+    s->last_t = t_new;
+    return TR_OK;
+  }
+  // STR: one pass of the update stage (Alg. 4), or `sweeps` passes that
+  // each start again from the P_n, Q_n held before the batch and rewrite the
+  // new temporal rows (the multi-pass extension)
+  const long pstep = prof_begin(s, PK_STEP);
+  for (int k = 0; k < s->sweeps; ++k) {
+    for (int n = 0; n < N - 1 && s->sweeps > 1; ++n) {
+      const size_t pb = (size_t)s->I[n] * s->d(n) * sizeof(double);
+      const size_t qb = (size_t)s->d(n) * s->d(n) * sizeof(double);
+      if (k == 0) {
+        TR_HIP(hipMemcpyAsync(s->Pold[n], s->P[n], pb, hipMemcpyDeviceToDevice, s->st));
+        TR_HIP(hipMemcpyAsync(s->Qold[n], s->Q[n], qb, hipMemcpyDeviceToDevice, s->st));
+      } else {
+        TR_HIP(hipMemcpyAsync(s->P[n], s->Pold[n], pb, hipMemcpyDeviceToDevice, s->st));
+        TR_HIP(hipMemcpyAsync(s->Q[n], s->Qold[n], qb, hipMemcpyDeviceToDevice, s->st));
+      }
+    }
+    c = str_pass(s, Xd, t_new, Gnew);
+    if (c != TR_OK) return c;
+  }
   prof_end(s, pstep);
   s->t_total += t_new;
   s->last_t = t_new;
@@ -1245,22 +1456,59 @@ tr_status tr_stream_get_samples(tr_stream* s, int32_t* idxs) {
   return TR_OK;
 }
 
-tr_status tr_stream_set_samples(tr_stream* s, const int32_t* idxs) {
-  if (!s || !idxs) return TR_ERR_ARG;
+tr_status tr_stream_set_samples(tr_stream* s, const int32_t* idxs, const int8_t* signs,
+                                int64_t t_signs) {
+  if (!s || (!idxs && !signs)) return TR_ERR_ARG;
   if (s->poisoned != TR_OK) return s->poisoned;
   if (s->sketch == TR_SKETCH_NONE) return fail(s, TR_ERR_ARG, "no sketch configured");
+  if (signs && s->sketch != TR_SKETCH_KSRFT)
+    return fail(s, TR_ERR_ARG, "signs are injected only into the KSRFT sketch");
   const int N = s->N;
-  for (int k = 0; k < N; ++k) {
-    const int64_t size = k == N - 1 ? s->last_t : s->I[k];
-    for (int64_t j = 0; j < s->m; ++j) {
-      const int32_t v = idxs[(size_t)k * s->m + j];
-      if (v < 0 || v >= size) return fail(s, TR_ERR_ARG, "sample index out of range");
+  if (idxs)
+    for (int k = 0; k < N; ++k) {
+      const int64_t size = k == N - 1 ? s->last_t : s->I[k];
+      for (int64_t j = 0; j < s->m; ++j) {
+        const int32_t v = idxs[(size_t)k * s->m + j];
+        if (v < 0 || v >= size) return fail(s, TR_ERR_ARG, "sample index out of range");
+      }
+    }
+  std::vector<double> sg;
+  if (signs) {
+    if (t_signs < 1 || t_signs > 256) return fail(s, TR_ERR_ARG, "t_signs out of range");
+    int64_t total = t_signs;
+    for (int k = 0; k < N - 1; ++k) total += s->I[k];
+    sg.resize(total);
+    for (int64_t j = 0; j < total; ++j) {
+      if (signs[j] != 1 && signs[j] != -1) return fail(s, TR_ERR_ARG, "a sign is not +1 or -1");
+      sg[j] = (double)signs[j];
     }
   }
   TR_HIP(hipSetDevice(s->device));
-  TR_HIP(hipMemcpyAsync(s->idxs, idxs, (size_t)N * s->m * sizeof(int32_t),
-                        hipMemcpyHostToDevice, s->st));
+  if (idxs) {
+    // (the sampled slices are gathered again with these indices where the
+    // next step uses them: the KSRFT step re-gathers its mixed slices after
+    // drawing the new signs)
+    TR_HIP(hipMemcpyAsync(s->idxs, idxs, (size_t)N * s->m * sizeof(int32_t),
+                          hipMemcpyHostToDevice, s->st));
+    TR_HIP(hipStreamSynchronize(s->st));
+  }
+  if (signs) {
+    s->next_signs.swap(sg);
+    s->next_signs_t = t_signs;
+  }
+  return TR_OK;
+}
+
+tr_status tr_stream_get_stats(tr_stream* s, tr_stats* out) {
+  if (!s || !out) return TR_ERR_ARG;
+  if (s->poisoned != TR_OK) return s->poisoned;
+  TR_HIP(hipSetDevice(s->device));
+  int st[4] = {0, 0, 0, 0};
+  TR_HIP(hipMemcpyAsync(st, s->dstatus, sizeof(st), hipMemcpyDeviceToHost, s->st));
   TR_HIP(hipStreamSynchronize(s->st));
+  out->pinv_fallbacks = st[2];
+  out->init_sweeps = s->init_sweeps;
+  out->init_rel_err = s->init_err;
   return TR_OK;
 }
 
@@ -1280,6 +1528,7 @@ tr_status tr_stream_save(tr_stream* s, const char* path) {
   h.rescale = s->rescale;
   h.temporal_literal = s->temporal_literal;
   h.check_finite = s->check_finite;
+  h.sweeps = s->sweeps;
   h.m = s->m;
   h.t_total = s->t_total;
   h.step = s->step;
@@ -1335,7 +1584,8 @@ tr_status tr_stream_load(const char* path, const tr_config* cfg, tr_stream** out
   fc.sketch = h.sketch;
   fc.sketch_size = h.m;
   fc.rescale = h.rescale;
-  fc.temporal_literal = h.temporal_literal;
+  fc.temporal_normal_eq = h.temporal_literal ? 0 : 1;
+  fc.sweeps = h.sweeps;
   fc.seed = h.seed;
   fc.check_finite = h.check_finite;
   if (cfg) {
@@ -1399,13 +1649,15 @@ void tr_stream_destroy(tr_stream* s) {
     if (b) (void)hipFree(b);
   void* bufs[] = {s->sidecnt, s->Minv, s->chain[0], s->chain[1], s->xcast, s->xf64, s->part,
                   s->wg,   s->pair,     s->dstatus,  s->idxs,  s->SA,   s->Sw,
-                  s->Zb,   s->Zi,       s->dprobs,   s->cdf};
+                  s->Zb,   s->Zi,       s->dprobs,   s->cdf,   s->pinvH, s->pinvW};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
   for (hipEvent_t e : s->ev_pool) (void)hipEventDestroy(e);
   if (s->side) (void)hipStreamSynchronize(s->side);
   for (int k = 0; k < MAXN; ++k) {
     if (s->MinvM[k]) (void)hipFree(s->MinvM[k]);
+    if (s->Pold[k]) (void)hipFree(s->Pold[k]);
+    if (s->Qold[k]) (void)hipFree(s->Qold[k]);
     if (s->ev_inv[k]) (void)hipEventDestroy(s->ev_inv[k]);
     if (s->ev_rs[k]) (void)hipEventDestroy(s->ev_rs[k]);
   }
@@ -1505,7 +1757,8 @@ tr_status tr_mttkrp(int32_t N, const int64_t* dims, const int32_t* ranks, int32_
 
 static tr_status gram_chain_into(int32_t N, const int64_t* dims, const int32_t* ranks, int32_t dt,
                                  int32_t n, const void* const* cores, double* Q_dev, char* base,
-                                 const WsLayout& w, hipStream_t st, bool grams_ready) {
+                                 const WsLayout& w, hipStream_t st, bool grams_ready,
+                                 int accumulate = 0) {
   if (!grams_ready) {
     for (int k = 0; k < N; ++k) {
       const int Ra = ranks[k], Rb = ranks[(k + 1) % N];
@@ -1533,20 +1786,69 @@ static tr_status gram_chain_into(int32_t N, const int64_t* dims, const int32_t* 
     pp ^= 1;
     cols = c2;
   }
-  if (launch_assemble_q(cur, ranks[n], ranks[(n + 1) % N], Q_dev, 0, st) != hipSuccess)
+  if (launch_assemble_q(cur, ranks[n], ranks[(n + 1) % N], Q_dev, accumulate, st) != hipSuccess)
     return TR_ERR_DEVICE;
   return TR_OK;
 }
 
-tr_status tr_gram_chain(int32_t N, const int64_t* dims, const int32_t* ranks, int32_t dt,
-                        int32_t n, const void* const* cores, double* Q_dev, void* ws,
+tr_status tr_gram_chain(int32_t N, const int64_t* dims, const int32_t* ranks, int32_t n,
+                        const double* const* Z_dev, double* Q_dev, int32_t accumulate, void* ws,
                         size_t ws_bytes, void* hip_stream) {
-  if (!valid_shape(N, dims, ranks, dt) || !cores || !Q_dev || !ws) return TR_ERR_ARG;
+  if (!valid_shape(N, dims, ranks, TR_F64) || !Z_dev || !Q_dev || !ws) return TR_ERR_ARG;
   if (n < 0 || n >= N) return TR_ERR_ARG;
-  WsLayout w = ws_layout(N, dims, ranks, dt);
-  if (ws_bytes < w.total) return TR_ERR_SHAPE;
-  return gram_chain_into(N, dims, ranks, dt, n, cores, Q_dev, (char*)ws, w,
-                         (hipStream_t)hip_stream, false);
+  for (int k = 0; k < N; ++k)
+    if (k != n && !Z_dev[k]) return TR_ERR_ARG;
+  // only the Gram matrices and the chain buffers of the workspace are used;
+  // their offsets do not depend on the operand dtype of the sizing call
+  WsLayout w = ws_layout(N, dims, ranks, TR_F64);
+  int emax = 0;
+  for (int k = 0; k < N; ++k) emax = std::max(emax, ranks[k] * ranks[k]);
+  if (ws_bytes < w.chain1 + (size_t)emax * emax * 8) return TR_ERR_SHAPE;
+  hipStream_t st = (hipStream_t)hip_stream;
+  char* base = (char*)ws;
+  for (int k = 0; k < N; ++k)
+    if (k != n && launch_z_to_E(Z_dev[k], ranks[k], ranks[(k + 1) % N], (double*)(base + w.E[k]),
+                                st) != hipSuccess)
+      return TR_ERR_DEVICE;
+  return gram_chain_into(N, dims, ranks, TR_F64, n, nullptr, Q_dev, base, w, st, true,
+                         accumulate);
+}
+
+tr_status tr_batch_als(const tr_config* cfg, const double* X, int64_t T, int32_t x_is_device,
+                       const double* const* cores_in, int32_t cores_on_device,
+                       int32_t max_sweeps, double tol, double* const* cores_out,
+                       double* rel_errs, int32_t* sweeps_done) {
+  if (!cfg || !X || !cores_out || max_sweeps < 0) return TR_ERR_ARG;
+  tr_config c2 = *cfg;
+  c2.sketch = TR_SKETCH_NONE;
+  c2.sketch_size = 0;
+  c2.sweeps = 0;
+  c2.max_slices = T;
+  tr_status c = check_config(&c2, T);
+  if (c != TR_OK) return c;
+  tr_stream* s = nullptr;
+  c = create_handle(&c2, T, &s);
+  if (c == TR_OK) {
+    s->t_total = T;
+    s->last_t = T;
+    c = cores_in ? load_cores(s, cores_in, cores_on_device, T) : random_cores(s, T);
+  }
+  const void* Xd = nullptr;
+  if (c == TR_OK) {
+    int64_t J = 1;
+    for (int k = 0; k < s->N - 1; ++k) J *= s->I[k];
+    c = stage_batch(s, X, F64, J * T, x_is_device, &Xd);
+  }
+  std::vector<double> errs;
+  if (c == TR_OK) c = als_run(s, Xd, T, max_sweeps, tol, &errs);
+  if (c == TR_OK) c = tr_stream_get_cores(s, cores_out);
+  if (c == TR_OK) {
+    if (rel_errs)
+      for (size_t j = 0; j < errs.size(); ++j) rel_errs[j] = errs[j];
+    if (sweeps_done) *sweeps_done = s->init_sweeps;
+  }
+  tr_stream_destroy(s);
+  return c;
 }
 
 tr_status tr_fit_loss_fwd(int32_t N, const int64_t* dims, const int32_t* ranks, int32_t dt,

@@ -25,6 +25,34 @@ __device__ inline double rng_uniform(uint64_t key, uint64_t s) {
   return (double)(mix64(key + s) >> 11) * 0x1.0p-53;
 }
 
+// Random start of the batch TR-ALS: entry e = r + Ra (i + I s) of a core
+// (column-major numbering) is the Irwin-Hall sum of twelve uniforms of the
+// stream `key` minus six, z_e = u_{12e} + ... + u_{12e+11} - 6, summed left
+// to right (mean 0, variance 1; no transcendental function, so the bits do
+// not depend on a math library), written to the slice-major state row i.
+__global__ void k_init_normal(uint64_t key, int Ra, int64_t I, int Rb, double* __restrict__ G) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t n = (int64_t)Ra * I * Rb;
+  if (e >= n) return;
+  double z = 0.0;
+  for (int j = 0; j < 12; ++j) z += rng_uniform(key, (uint64_t)(12 * e + j));
+  z -= 6.0;
+  const int r = (int)(e % Ra);
+  const int64_t rest = e / Ra;
+  const int64_t i = rest % I;
+  const int sidx = (int)(rest / I);
+  G[i * (int64_t)(Ra * Rb) + r + (int64_t)Ra * sidx] = z;
+}
+
+hipError_t launch_init_normal(uint64_t key, int Ra, int64_t I, int Rb, double* G,
+                              hipStream_t st) {
+  const int64_t n = (int64_t)Ra * I * Rb;
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_init_normal, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, key, Ra,
+                     I, Rb, G);
+  return hipGetLastError();
+}
+
 // Randsample(I, m) with replacement, uniform (Alg. 7).
 __global__ void k_draw_uniform(uint64_t key, int m, int64_t I, int* __restrict__ idx) {
   const int s = blockIdx.x * blockDim.x + threadIdx.x;
@@ -107,19 +135,29 @@ hipError_t launch_draw_dist(uint64_t key, int m, int64_t I, const double* p, dou
 }
 
 // Leverage-based distribution of a core (Lemma on leverage estimation,
-// Def. leverage scores): p_i = l_i / sum_j l_j with
-//   l_i = g_i Zinv g_i^T   (I > d: Zinv = (G_(2)^T G_(2))^{-1}),
-//   l_i = 1                (I <= d: G_(2) has full row rank, checked by the
-//                            caller through the row-Gram inverse).
+// Def. leverage scores): p_i = l_i / sum_j l_j (sum_j l_j = rank G_(2)) with
+//   l_i = g_i Zinv g_i^T   (I > d: Zinv = (G_(2)^T G_(2))^dagger, the
+//                            inverse or, for a rank-deficient core, the
+//                            pseudo-inverse of the elimination's fallback),
+//   l_i = 1                (I <= d and G_(2) of full row rank: the row Gram
+//                            K = G_(2) G_(2)^T passed the elimination),
+//   l_i = (K K^dagger)_ii  (I <= d and K rank-deficient: the elimination
+//                            fell back to the pseudo-inverse, *fell_back).
+// The scores are the diagonal of the projector onto the column space of
+// G_(2) in every case.  A zero core (every score 0) gives the uniform
+// distribution.
 __global__ __launch_bounds__(256) void k_leverage(const double* __restrict__ G, int64_t I, int d,
                                                   const double* __restrict__ Zinv,
+                                                  const double* __restrict__ K,
+                                                  const int* __restrict__ fell_back,
                                                   double* __restrict__ p) {
   __shared__ double red[256];
   const int tid = threadIdx.x;
+  const bool rowk = K && fell_back && *fell_back;
   double part = 0.0;
   for (int64_t i = tid; i < I; i += 256) {
     double l = 1.0;
-    if (Zinv) {
+    if (!K) {
       const double* g = G + i * d;
       l = 0.0;
       for (int c = 0; c < d; ++c) {
@@ -127,6 +165,10 @@ __global__ __launch_bounds__(256) void k_leverage(const double* __restrict__ G, 
         for (int c2 = 0; c2 < d; ++c2) t += Zinv[(size_t)c * d + c2] * g[c2];
         l += g[c] * t;
       }
+    } else if (rowk) {
+      // diagonal of the projector K K^+ onto the row space of G G^T
+      l = 0.0;
+      for (int64_t j = 0; j < I; ++j) l += K[i * I + j] * Zinv[j * I + i];
     }
     p[i] = l;
     part += l;
@@ -138,12 +180,12 @@ __global__ __launch_bounds__(256) void k_leverage(const double* __restrict__ G, 
     __syncthreads();
   }
   const double tot = red[0];
-  for (int64_t i = tid; i < I; i += 256) p[i] = p[i] / tot;
+  for (int64_t i = tid; i < I; i += 256) p[i] = tot > 0.0 ? p[i] / tot : 1.0 / (double)I;
 }
 
-hipError_t launch_leverage(const double* G, int64_t I, int d, const double* Zinv, double* p,
-                           hipStream_t st) {
-  hipLaunchKernelGGL(k_leverage, dim3(1), dim3(256), 0, st, G, I, d, Zinv, p);
+hipError_t launch_leverage(const double* G, int64_t I, int d, const double* Zinv,
+                           const double* K, const int* fell_back, double* p, hipStream_t st) {
+  hipLaunchKernelGGL(k_leverage, dim3(1), dim3(256), 0, st, G, I, d, Zinv, K, fell_back, p);
   return hipGetLastError();
 }
 

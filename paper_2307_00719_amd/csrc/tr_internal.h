@@ -75,29 +75,37 @@ hipError_t launch_reduce_solve(const void* part, int psize, int nsplit, int64_t 
 hipError_t launch_gram_E(const double* G, int64_t rows, int Ra, int Rb, double* E,
                          hipStream_t st);
 
+// E (transfer layout) of a Gram tensor Z in the paper's R_{k+1} x R_k x
+// R_{k+1} x R_k column-major layout (R = R_k, R1 = R_{k+1}).
+hipError_t launch_z_to_E(const double* Z, int R, int R1, double* E, hipStream_t st);
+
 // C (d1 x d3) = A (d1 x d2) * B (d2 x d3), row-major FP64.
 hipError_t launch_matmul(const double* A, const double* B, double* C, int d1, int d2, int d3,
                          hipStream_t st);
 
 // Q-layout matrix from an E-layout chain product M (rows (s + Rb*s'),
 // columns (r + Ra*r')), optionally added to / stored in Q, then optionally
-// inverted in place by Gauss-Jordan into Qinv.  status[0] is set to 1 on a
-// non-positive or tiny pivot.
+// inverted in place by Gauss-Jordan into Qinv.  A non-positive or tiny
+// pivot sends the workgroup to the pseudo-inverse fallback.
 // With m_plain = 1, M is already a d x d matrix in the Q layout.
 // Q (+)= the Q-layout image of the Gram-chain product M (Rb^2 x Ra^2),
 // no inverse.
 hipError_t launch_assemble_q(const double* M, int Ra, int Rb, double* Q, int accumulate,
                              hipStream_t st);
+// When a pivot fails, Qinv receives the pseudo-inverse instead (one-sided
+// Jacobi from the stored Q, or from Hs when Q is not stored; scratch
+// `work` of 2 d^2 + d doubles); without Hs/work, status[0] is set to 1.
 hipError_t launch_invert_spd(const double* M, int Ra, int Rb, double* Q, int accumulate,
                              int store_Q, double* Qinv, int* status, hipStream_t st,
-                             int m_plain = 0);
+                             int m_plain = 0, double* Hs = nullptr, double* work = nullptr);
 
 // Fused per-mode side step (workgroups of 1024 threads): optionally the
 // transfer-layout Gram E_p of `rows_p` slice-major rows Gp (written to Ep,
 // one workgroup per upper-triangle 16x16 tile; the last to finish goes on),
 // then the ring product of the nfac transfer-layout factors fac[0..nfac)
 // (fac[j] is fr[j] x fc[j]; a null entry stands for Ep), then the Q-layout
-// assembly / accumulation into Q and the Gauss-Jordan inverse into Qinv.
+// assembly / accumulation into Q and the Gauss-Jordan inverse into Qinv
+// (the pseudo-inverse when a pivot fails its test and Hs / pw are given).
 // With row weights Gw (rows_p of them) the Gram is sum_s Gw[s] Gp_s^T Gp_s
 // (the weighted sketched Gram, with Rpa = d and Rpb = 1).
 struct SideArgs {
@@ -114,8 +122,10 @@ struct SideArgs {
   double* Q;
   int accumulate, store_Q;
   double* Qinv;
-  int* status;
+  int* status;         // [0] failure flag, [2] fallback count, [3] this solve fell back
   unsigned* counter;   // arrival counter of the Gram workgroups (zero between launches)
+  double* Hs;          // d x d copy of the matrix when Q is not stored (fallback input)
+  double* pw;          // 2 d^2 + d doubles of scratch for the pseudo-inverse fallback
 };
 hipError_t launch_side(const SideArgs& a, hipStream_t st);
 
@@ -166,16 +176,25 @@ hipError_t launch_core_to_slices(const void* src, int cdt, int64_t sr, int64_t s
 
 uint64_t rng_key(uint64_t seed, uint64_t step, uint64_t core, uint64_t kind);
 
+// Initial core (Ra x I x Rb) from the stream `key` (Irwin-Hall normals),
+// as slice-major FP64 rows.
+hipError_t launch_init_normal(uint64_t key, int Ra, int64_t I, int Rb, double* G,
+                              hipStream_t st);
+
 // m uniform draws over [I] / from the distribution p (cdf: I doubles of
 // scratch) into idx.
 hipError_t launch_draw_uniform(uint64_t key, int m, int64_t I, int* idx, hipStream_t st);
 hipError_t launch_draw_dist(uint64_t key, int m, int64_t I, const double* p, double* cdf,
                             int* idx, hipStream_t st);
 
-// Leverage distribution of I slice-major rows of width d; Zinv = inverse
-// column Gram (I > d) or nullptr (every score 1, I <= d).
-hipError_t launch_leverage(const double* G, int64_t I, int d, const double* Zinv, double* p,
-                           hipStream_t st);
+// Leverage distribution of I slice-major rows of width d.  With K null,
+// Zinv is the (pseudo-)inverse of the column Gram G^T G (I > d) and
+// l_i = g_i Zinv g_i^T.  With K given (the row Gram G G^T, I <= d) and its
+// (pseudo-)inverse in Zinv, every score is 1 unless *fell_back (the
+// inverse was the pseudo-inverse: rank below I), when l_i = (K Zinv)_ii.
+// p = l / sum(l), or uniform when every score is zero.
+hipError_t launch_leverage(const double* G, int64_t I, int d, const double* Zinv,
+                           const double* K, const int* fell_back, double* p, hipStream_t st);
 
 // Sampled subchain rows A (m x d) of mode g.n and their weights w; idxs is
 // N x m (row q = samples of core q); probs (device array of N device

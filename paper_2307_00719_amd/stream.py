@@ -10,20 +10,26 @@ class TRStream:
 
     X_init and batches are (I_1, .., I_{N-1}, t) arrays (NumPy on the host, or
     torch tensors on the device); cores are (R_n, I_n, R_{n+1}) arrays with the
-    temporal core holding t_init slices.
+    temporal core holding t_init slices.  With cores_init None the library
+    initialises the cores by batch TR-ALS on X_init (``ranks`` required).
     """
 
-    def __init__(self, X_init, cores_init, compute_dtype="f64", sketch=None, sketch_size=0,
-                 rescale=True, temporal_literal=False, seed=0, max_slices=0,
-                 check_finite=False, device=0, hip_stream=None):
+    def __init__(self, X_init, cores_init=None, compute_dtype="f64", sketch=None,
+                 sketch_size=0, rescale=True, temporal_literal=True, seed=0, max_slices=0,
+                 check_finite=False, device=0, hip_stream=None, ranks=None, sweeps=1,
+                 init_max_sweeps=0, init_tol=0.0):
         self.dims = list(X_init.shape[:-1])
-        self.ranks = [int(G.shape[0]) for G in cores_init]
+        if cores_init is not None:
+            self.ranks = [int(G.shape[0]) for G in cores_init]
+        else:
+            self.ranks = [int(r) for r in ranks]
         self.N = len(self.ranks)
         self.handle = _lib.tr_stream_init(
             X_init, cores_init, self.ranks, compute_dtype=compute_dtype, sketch=sketch,
             sketch_size=sketch_size, rescale=rescale, temporal_literal=temporal_literal,
             seed=seed, max_slices=max_slices, check_finite=check_finite, device=device,
-            hip_stream=hip_stream)
+            hip_stream=hip_stream, sweeps=sweeps, init_max_sweeps=init_max_sweeps,
+            init_tol=init_tol)
         self.sketch_size = int(sketch_size)
         self._keep = None
 
@@ -48,8 +54,11 @@ class TRStream:
     def save(self, path):
         _lib.tr_stream_save(self.handle, path)
 
-    def set_samples(self, idxs):
-        _lib.tr_stream_set_samples(self.handle, idxs)
+    def set_samples(self, idxs=None, signs=None):
+        _lib.tr_stream_set_samples(self.handle, idxs, signs)
+
+    def stats(self):
+        return _lib.tr_stream_get_stats(self.handle)
 
     def d(self, n):
         return self.ranks[n] * self.ranks[(n + 1) % self.N]

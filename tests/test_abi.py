@@ -99,4 +99,6 @@ def test_checkpoint_entry_points_validate_without_device(tmp_path):
     assert lib.tr_stream_load(os.fsencode(str(empty)), None, ctypes.byref(h)) == 1
     assert not h
     assert lib.tr_stream_save(None, b"x") == 1
-    assert lib.tr_stream_set_samples(None, None) == 1
+    assert lib.tr_stream_set_samples(None, None, None, 0) == 1
+    assert lib.tr_stream_get_stats(None, None) == 1
+    assert lib.tr_batch_als(None, None, 0, 0, None, 0, 0, 0.0, None, None, None) == 1

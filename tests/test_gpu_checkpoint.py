@@ -13,13 +13,12 @@ import numpy as np
 import pytest
 
 import workloads as W
+from parity import dev
 from oracle import randomized as rs
 
 pytestmark = pytest.mark.gpu
 
 
-def rel(a, b):
-    return float(np.linalg.norm(np.ravel(a - b)) / max(np.linalg.norm(np.ravel(b)), 1e-300))
 
 
 def _problem(dims, ranks, t_init, nb, t_new, seed):
@@ -136,8 +135,8 @@ def test_injected_samples_match_oracle(trlib, sketch, dims, ranks):
         assert all(np.array_equal(sg[k], o.idxs[k]) for k in range(N))
     T = t_init + nb * t_new
     eo, eg = o.rel_error(X[..., :T]), g.reconstruct_error(X[..., :T])
-    cores = max(rel(a, c) for a, c in zip(g.cores(), o.cores))
-    pq = max(max(rel(g.PQ(n)[0], o.P[n].real), rel(g.PQ(n)[1], o.Q[n].real))
+    cores = max(dev(a, c) for a, c in zip(g.cores(), o.cores))
+    pq = max(max(dev(g.PQ(n)[0], o.P[n].real), dev(g.PQ(n)[1], o.Q[n].real))
              for n in range(N - 1))
     print(f"[inject {sketch}] err dev {abs(eg - eo) / eo:.2e} cores {cores:.2e} PQ {pq:.2e}",
           flush=True)
@@ -169,20 +168,53 @@ def test_set_samples_rejects_out_of_range(trlib):
     h.close()
 
 
-@pytest.mark.parametrize("sketch", [None, "uniform", "ksrft"])
-def test_singular_normal_equations_are_reported(trlib, sketch):
-    """A zero core makes every Gram chain through it zero, so the first
-    update's normal-equation matrix has a zero pivot: the update reports
-    TR_ERR_SINGULAR when the stream is synchronised, and the handle then
-    answers TR_ERR_STATE."""
-    init, X = _problem((14, 12), (2, 3, 2), 8, 1, 4, 6)
-    init[1] = np.zeros_like(init[1])
-    g = trlib.TRStream(X[..., :8], init, sketch=sketch, sketch_size=40 if sketch else 0, seed=2)
-    g.update(X[..., 8:12])
+def test_injected_signs_match_oracle(trlib):
+    """KSRFT with the D_k of each step injected on both sides (the sign
+    diagonals of Def. KSRFT taken from outside instead of the generator):
+    the results agree with the oracle to the FP64 parity tolerances, and
+    differ from the run with the generator's signs."""
+    dims, ranks, t_init, t_new, nb, m = (12, 10, 6), (2, 2, 3, 2), 8, 5, 3, 50
+    init, X = _problem(dims, ranks, t_init, nb, t_new, 23)
+    N = len(ranks)
+    o = rs.RSTR(X[..., :t_init], [G.copy() for G in init], m=m, sketch="ksrft", seed=3)
+    g = trlib.TRStream(X[..., :t_init], init, sketch="ksrft", sketch_size=m, seed=3)
+    h = trlib.TRStream(X[..., :t_init], init, sketch="ksrft", sketch_size=m, seed=3)
+    rng = np.random.default_rng(99)
+    sizes = list(dims) + [t_new]
+    for b in range(nb):
+        D = [np.where(rng.random(sizes[k]) < 0.5, 1, -1).astype(np.int8) for k in range(N)]
+        g.set_samples(signs=D)
+        o.set_samples(signs=D)
+        xb = X[..., t_init + b * t_new:t_init + (b + 1) * t_new]
+        o.update(xb)
+        g.update(xb)
+        h.update(xb)
+        sg = g.samples()
+        assert all(np.array_equal(sg[k], o.idxs[k]) for k in range(N))
+    T = t_init + nb * t_new
+    eo, eg, eh = (o.rel_error(X[..., :T]), g.reconstruct_error(X[..., :T]),
+                  h.reconstruct_error(X[..., :T]))
+    cores = max(dev(a, c) for a, c in zip(g.cores(), o.cores))
+    pq = max(max(dev(g.PQ(n)[0], o.P[n].real), dev(g.PQ(n)[1], o.Q[n].real))
+             for n in range(N - 1))
+    print(f"[inject signs] err gpu {eg:.10e} oracle {eo:.10e} generator {eh:.10e} "
+          f"cores {cores:.2e} PQ {pq:.2e}", flush=True)
+    assert abs(eg - eo) <= 1e-10 * eo and cores < 1e-9 and pq < 1e-10
+    assert eg != eh
+    # a temporal sign vector that does not match the next batch is refused
+    D = [np.ones(sizes[k], dtype=np.int8) for k in range(N - 1)] + [np.ones(3, dtype=np.int8)]
+    g.set_samples(signs=D)
     with pytest.raises(trlib.TRError) as e:
-        g.sync()
-    assert e.value.code == 7
+        g.update(X[..., :t_new])
+    assert e.value.code == 2
+    bad = [d.copy() for d in D]
+    bad[0][0] = 0
     with pytest.raises(trlib.TRError) as e:
-        g.update(X[..., 8:12])
-    assert e.value.code == 6
+        g.set_samples(signs=bad)
+    assert e.value.code == 1
     g.close()
+    h.close()
+    u = trlib.TRStream(X[..., :t_init], init, sketch="uniform", sketch_size=m, seed=3)
+    with pytest.raises(trlib.TRError):
+        u.set_samples(signs=D)
+    u.close()

@@ -6,6 +6,7 @@ import pytest
 
 import workloads as W
 from oracle import fitloss
+from parity import dev
 
 pytestmark = pytest.mark.gpu
 
@@ -38,7 +39,7 @@ def test_fitloss_f64_parity(trlib, dims, ranks):
     print(f"[fitloss {dims}] loss rel {abs(loss - ref_loss) / ref_loss:.2e}", flush=True)
     assert abs(loss - ref_loss) <= 1e-11 * ref_loss
     for g, r in zip(grads, ref):
-        assert np.linalg.norm(g - r) <= 1e-10 * np.linalg.norm(r)
+        assert dev(g, r) < 1e-10
 
 
 def test_fitloss_finite_differences_gpu(trlib):
@@ -63,20 +64,21 @@ def test_fitloss_finite_differences_gpu(trlib):
             assert abs(fd - grads[k][idx]) <= 1e-6 * max(1.0, abs(grads[k][idx]))
 
 
-def test_fitloss_f32_c5_shape(trlib):
-    """FP32 forward/backward at the c5 slice shape (64^3, fewer slices so the
-    FP64 oracle stays quick): loss within 1e-5, gradients within 1e-4."""
+def test_fitloss_f32_c5_full(trlib):
+    """FP32 forward/backward on the whole 64 x 64 x 64 x 50 evaluation (TR-ranks
+    16) against the FP64 oracle's loss and G_{n(2)} Q_n - P_n: loss within
+    1e-5 relative, every gradient entry within 1e-4 (parity.dev)."""
     import torch
-    w = W.make("c5", T=6)
+    w = W.make("c5")
     point = W.c5_point(w)
     loss, grads = _run(trlib, w.X, point, torch.float32)
     ref_loss = fitloss.fit_loss(w.X, point)
     ref = fitloss.grad_normal_eq(w.X, point)
-    dev = [np.linalg.norm(g - r) / np.linalg.norm(r) for g, r in zip(grads, ref)]
-    print(f"[fitloss c5 f32] loss rel {abs(loss - ref_loss) / ref_loss:.2e} grads {dev}",
+    devs = [dev(g, r) for g, r in zip(grads, ref)]
+    print(f"[fitloss c5 f32] loss rel {abs(loss - ref_loss) / ref_loss:.2e} grads {devs}",
           flush=True)
     assert abs(loss - ref_loss) <= 1e-5 * ref_loss
-    assert max(dev) < 1e-4
+    assert max(devs) < 1e-4
 
 
 @pytest.mark.parametrize("dt", ["f64", "f32"])
@@ -92,6 +94,10 @@ def test_mttkrp_and_gram_chain_entry_points(trlib, dt, dims, ranks):
     code = 0 if dt == "f64" else 1
     Xt = torch.from_numpy(np.asfortranarray(X)).to(tdt).cuda()
     ct = [torch.from_numpy(np.asfortranarray(G)).to(tdt).cuda() for G in cores]
+    # Gram tensors in the paper's layout (R_{k+1} x R_k x R_{k+1} x R_k,
+    # column-major), the input of tr_gram_chain
+    Zt = [torch.from_numpy(np.asfortranarray(tr.gram_tensor(G)).ravel(order="F")).cuda()
+          for G in cores]
     wsb = trlib.tr_workspace_bytes(list(dims), list(ranks), dt)
     ws = torch.empty(wsb, dtype=torch.uint8, device="cuda")
     st_ = torch.cuda.current_stream().cuda_stream
@@ -102,12 +108,15 @@ def test_mttkrp_and_gram_chain_entry_points(trlib, dt, dims, ranks):
         Q = torch.zeros((d, d), dtype=torch.float64, device="cuda")
         trlib.tr_mttkrp(list(dims), list(ranks), code, n, Xt.data_ptr(),
                         [c.data_ptr() for c in ct], P.data_ptr(), 0, ws.data_ptr(), wsb, st_)
-        trlib.tr_gram_chain(list(dims), list(ranks), code, n, [c.data_ptr() for c in ct],
-                            Q.data_ptr(), ws.data_ptr(), wsb, st_)
+        trlib.tr_gram_chain(list(dims), list(ranks), n, [z.data_ptr() for z in Zt],
+                            Q.data_ptr(), 0, ws.data_ptr(), wsb, st_)
+        Q2 = Q.clone()
+        trlib.tr_gram_chain(list(dims), list(ranks), n, [z.data_ptr() for z in Zt],
+                            Q2.data_ptr(), 1, ws.data_ptr(), wsb, st_)
         torch.cuda.synchronize()
         S = tr.subchain_unfold2(tr.subchain(cores, n))
         Pr, Qr = tr.unfold_mode(X, n) @ S, S.T @ S
-        ep = np.linalg.norm(P.cpu().numpy() - Pr) / np.linalg.norm(Pr)
-        eq = np.linalg.norm(Q.cpu().numpy() - Qr) / np.linalg.norm(Qr)
+        ep = dev(P.cpu().numpy(), Pr)
+        eq = max(dev(Q.cpu().numpy(), Qr), dev(Q2.cpu().numpy(), 2 * Qr))
         print(f"[mttkrp {dims} n={n} {dt}] P {ep:.2e} Q {eq:.2e}", flush=True)
-        assert ep < tol and eq < (1e-12 if dt == "f64" else 2e-6)
+        assert ep < tol and eq < 1e-12

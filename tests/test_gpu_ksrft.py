@@ -15,16 +15,13 @@ import numpy as np
 import pytest
 
 import workloads as W
+from parity import dev
 from oracle import randomized as rs
 
 pytestmark = pytest.mark.gpu
 
 
-def rel(a, b):
-    return float(np.linalg.norm(np.ravel(a - b)) / max(np.linalg.norm(np.ravel(b)), 1e-300))
-
-
-def run_pair(P, X, init, t_init, t_new, nb, m, seed=11, dt="f64", literal=False, log=""):
+def run_pair(P, X, init, t_init, t_new, nb, m, seed=11, dt="f64", literal=True, log=""):
     o = rs.RSTR(X[..., :t_init], [G.copy() for G in init], m=m, sketch="ksrft", seed=seed,
                 temporal_literal=literal)
     g = P.TRStream(X[..., :t_init], init, compute_dtype=dt, sketch="ksrft", sketch_size=m,
@@ -35,7 +32,7 @@ def run_pair(P, X, init, t_init, t_new, nb, m, seed=11, dt="f64", literal=False,
     pq0 = 0.0
     for n in range(N - 1):
         Pg, Qg = g.PQ(n)
-        pq0 = max(pq0, rel(Pg, o.P[n].real), rel(Qg, o.Q[n].real))
+        pq0 = max(pq0, dev(Pg, o.P[n].real), dev(Qg, o.Q[n].real))
     worst = 0.0
     for b in range(nb):
         xb = X[..., t_init + b * t_new:t_init + (b + 1) * t_new]
@@ -48,14 +45,14 @@ def run_pair(P, X, init, t_init, t_new, nb, m, seed=11, dt="f64", literal=False,
         assert all(np.array_equal(sg[k], o.idxs[k]) for k in range(N)), \
             f"samples differ after batch {b}"
     out = dict(err_dev=worst, err=eg, err_oracle=eo, PQ_init=pq0)
-    out["cores"] = max(rel(a, b) for a, b in zip(g.cores(), o.cores))
+    out["cores"] = max(dev(a, b) for a, b in zip(g.cores(), o.cores))
     pq = 0.0
     for n in range(N - 1):
         Pg, Qg = g.PQ(n)
-        pq = max(pq, rel(Pg, o.P[n].real), rel(Qg, o.Q[n].real))
+        pq = max(pq, dev(Pg, o.P[n].real), dev(Qg, o.Q[n].real))
     out["PQ"] = pq
     g.close()
-    print(f"[ksrft {log} {dt}{' literal' if literal else ''}] {out}", flush=True)
+    print(f"[ksrft {log} {dt}{'' if literal else ' normal-eq'}] {out}", flush=True)
     return out
 
 
@@ -83,12 +80,15 @@ def test_ksrft_parity_f64(trlib, dims, ranks, t_init, t_new, nb, m):
     assert r["err_dev"] < 1e-10 and r["PQ"] < 1e-10 and r["cores"] < 1e-9
 
 
-def test_ksrft_literal_temporal_f64(trlib):
-    dims, ranks, t_init, t_new, nb, m = CASES[0]
+@pytest.mark.parametrize("case", [0, 1])
+def test_ksrft_normal_eq_temporal_f64(trlib, case):
+    """The other reading of the temporal rows (real-constrained normal
+    equations of the complex sketch), behind the option."""
+    dims, ranks, t_init, t_new, nb, m = CASES[case]
     _, X, init = problem(dims, ranks, t_init, t_new, nb)
     init = W.perturb(init, 0.05, np.random.default_rng(2))
-    r = run_pair(trlib, X, init, t_init, t_new, nb, m, literal=True, log="literal")
-    assert r["err_dev"] < 1e-9 and r["PQ"] < 1e-9 and r["cores"] < 1e-8
+    r = run_pair(trlib, X, init, t_init, t_new, nb, m, literal=False, log="normal-eq")
+    assert r["err_dev"] < 1e-10 and r["PQ"] < 1e-10 and r["cores"] < 1e-9
 
 
 # deviation from the FP64 oracle: FP32 1.5e-7 fit error and 1.1e-7 P/Q
@@ -124,19 +124,20 @@ def test_ksrft_exact_recovery(trlib, dt, tol):
     assert e < tol
 
 
-@pytest.mark.parametrize("dt", ["f64", "bf16"])
-def test_ksrft_video_workload(trlib, dt):
+@pytest.mark.parametrize("dt,nb", [("f64", 5), ("bf16", 2)])
+def test_ksrft_video_workload(trlib, dt, nb):
     """The 120 x 160 x 3 video-like stream (TR-ranks 12, batches of 20, m =
-    1440): two batches against the oracle.  Each spatial factor of the field
+    1440): five batches (FP64) or two (BF16) against the oracle.  Each spatial factor of the field
     spans cosines of four frequencies (rank 8 < 12), so the initial Re(Q_n)
     have cond about 2e9..5e9: two correct FP64 solvers then agree on the
     cores and P/Q only to about cond * eps ~ 1e-6 (bound 1e-5), while the fit
     error, the stated measure, agrees to 2e-10 (bound 1e-9).  In BF16 the
     same conditioning lets the cores drift by a few percent along the near
     null directions after the first solve, so the comparison is the fit error
-    (1.8e-4 measured, bound 5e-3) and P/Q at initialisation, before any solve
-    (1.6e-3 measured, bound 1e-2)."""
-    nb = 2
+    (2.2e-4 measured, bound 5e-3) and P/Q at initialisation, before any solve:
+    1.2e-2 measured entry by entry (1.6e-3 as a relative Frobenius norm),
+    bound 3e-2, a few units of the BF16 rounding 2^-9 of the mixed data in
+    the entries of P/Q far smaller than the terms summed into them."""
     w = W.make("c4", T=60 + nb * 20)
     T = w.t_init + nb * w.t_new
     X = np.asfortranarray(w.X[..., :T])
@@ -145,4 +146,4 @@ def test_ksrft_video_workload(trlib, dt):
     if dt == "f64":
         assert r["err_dev"] < 1e-9 and r["PQ"] < 1e-5 and r["cores"] < 1e-5
     else:
-        assert np.isfinite(r["err"]) and r["err_dev"] < 5e-3 and r["PQ_init"] < 1e-2
+        assert np.isfinite(r["err"]) and r["err_dev"] < 5e-3 and r["PQ_init"] < 3e-2

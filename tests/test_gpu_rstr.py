@@ -12,13 +12,12 @@ import numpy as np
 import pytest
 
 import workloads as W
+from parity import dev
 from oracle import randomized as rs
 
 pytestmark = pytest.mark.gpu
 
 
-def rel(a, b):
-    return float(np.linalg.norm(np.ravel(a - b)) / max(np.linalg.norm(np.ravel(b)), 1e-300))
 
 
 def run_pair(P, X, init, t_init, t_new, nb, m, sketch, seed=7, dt="f64", log=""):
@@ -40,11 +39,11 @@ def run_pair(P, X, init, t_init, t_new, nb, m, sketch, seed=7, dt="f64", log="")
         same = all(np.array_equal(sg[k], o.idxs[k]) for k in range(N))
         assert same, f"samples differ after batch {b}"
     out = dict(err_dev=worst, err=eg)
-    out["cores"] = max(rel(a, b) for a, b in zip(g.cores(), o.cores))
+    out["cores"] = max(dev(a, b) for a, b in zip(g.cores(), o.cores))
     pq = 0.0
     for n in range(N - 1):
         Pg, Qg = g.PQ(n)
-        pq = max(pq, rel(Pg, o.P[n]), rel(Qg, o.Q[n]))
+        pq = max(pq, dev(Pg, o.P[n]), dev(Qg, o.Q[n]))
     out["PQ"] = pq
     g.close()
     print(f"[rstr {sketch} {log} {dt}] {out}", flush=True)
