@@ -703,10 +703,27 @@ hipError_t launch_matmul(const double* A, const double* B, double* C, int d1, in
 // workgroup barriers.  W, V and the norms live in `work` (2 d^2 + d
 // doubles of global scratch).  status[2] counts the fallbacks, status[3] is
 // set for the solve that took one (the leverage scores read it), status[0]
-// is set to 2 if H holds NaN or Inf.  Every thread of the workgroup calls
-// it.
+// is set to 2 if H holds NaN or Inf.  Called by every thread of the
+// workgroup (nthr threads), or by one whole wave (nthr = 64).
 // ---------------------------------------------------------------------------
-__device__ __noinline__ void pinv_fallback(const double* H, int d, double* Hinv, double* work,
+__device__ inline void fb_sync(int nthr) {
+  if (nthr > 64) {
+    __syncthreads();
+  } else {
+    // one wave: its own global stores complete before its next loads
+    __builtin_amdgcn_s_waitcnt(0);
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+  }
+}
+
+__device__ inline bool fb_any(int x, int nthr) {
+  if (nthr > 64) return __syncthreads_or(x) != 0;
+  fb_sync(nthr);
+  return __ballot(x) != 0;
+}
+
+__device__ __forceinline__ void pinv_fallback(const double* H, int d, double* Hinv, double* work,
                                            int* status, int tid, int nthr) {
   double* W = work;                       // column j at W + j d
   double* V = work + (size_t)d * d;
@@ -716,7 +733,7 @@ __device__ __noinline__ void pinv_fallback(const double* H, int d, double* Hinv,
     W[e] = H[e];                          // H is symmetric: column j = row j
     V[e] = i == j ? 1.0 : 0.0;
   }
-  __syncthreads();
+  fb_sync(nthr);
   const int grp = tid >> 4, ngrp = nthr >> 4, l = tid & 15;
   const int D = d + (d & 1);              // an even count of columns: index d sits out
   for (int sweep = 0; sweep < 48; ++sweep) {
@@ -760,9 +777,9 @@ __device__ __noinline__ void pinv_fallback(const double* H, int d, double* Hinv,
           rot = 1;
         }
       }
-      __syncthreads();
+      fb_sync(nthr);
     }
-    if (!__syncthreads_or(rot)) break;
+    if (!fb_any(rot, nthr)) break;
   }
   for (int j = grp; j < d; j += ngrp) {
     double a = 0.0;
@@ -770,7 +787,7 @@ __device__ __noinline__ void pinv_fallback(const double* H, int d, double* Hinv,
     for (int off = 8; off > 0; off >>= 1) a += __shfl_xor(a, off, 16);
     if (l == 0) sg[j] = sqrt(a);
   }
-  __syncthreads();
+  fb_sync(nthr);
   double smax = 0.0;
   bool finite = true;
   for (int j = 0; j < d; ++j) {
@@ -779,12 +796,12 @@ __device__ __noinline__ void pinv_fallback(const double* H, int d, double* Hinv,
     smax = fmax(smax, x);
   }
   const double tol = (double)d * 2.220446049250313e-16 * smax;
-  __syncthreads();
+  fb_sync(nthr);
   for (int j = tid; j < d; j += nthr) {
     const double x = sg[j];
     sg[j] = x > tol ? 1.0 / (x * x) : 0.0;
   }
-  __syncthreads();
+  fb_sync(nthr);
   // upper triangle, mirrored: the result is exactly symmetric
   for (int e = tid; e < d * d; e += nthr) {
     const int i = e / d, k = e - i * d;
@@ -801,11 +818,11 @@ __device__ __noinline__ void pinv_fallback(const double* H, int d, double* Hinv,
   }
 }
 
-// End of an elimination, by the whole workgroup, once `any` (some pivot of
-// the workgroup failed its test, from __syncthreads_or) is known and the
-// elimination's result has been stored only if `any` is false: the
-// pseudo-inverse fallback from the saved matrix H, or, without a saved
-// matrix or scratch, the failure flagged in status[0] (value 1).
+// End of an elimination, once `any` (some pivot test of the workgroup
+// failed) is known: the pseudo-inverse fallback from the stored matrix H
+// (the Q the elimination started from), or, without a stored matrix or
+// scratch, the failure flagged in status[0] (value 1).  Called by the
+// nthr threads the fallback is to use (the workgroup, or one wave).
 __device__ inline void finish_inverse(bool any, const double* H, int d, double* Hinv,
                                       double* work, int* status, int tid, int nthr) {
   if (any && H && work) {
@@ -834,8 +851,7 @@ template <int TG, int B>
 __global__ __launch_bounds__(TG* TG) void k_invert_spd(const double* __restrict__ M, int Ra,
                                                        int Rb, double* Q, int accumulate,
                                                        int store_Q, double* __restrict__ Qinv,
-                                                       int* status, int m_plain, double* Hs,
-                                                       double* work) {
+                                                       int* status, int m_plain, double* work) {
   __shared__ double rowk[2][TG * B], colk[2][TG * B];
   __shared__ double sh_tol;
   const int tid = threadIdx.x;
@@ -857,10 +873,7 @@ __global__ __launch_bounds__(TG* TG) void k_invert_spd(const double* __restrict_
           v = M[(size_t)(s1 + Rb * s2) * (Ra * Ra) + (r + Ra * r2)];
         }
         if (Q && accumulate) v += Q[e];
-        if (Q && store_Q)
-          Q[e] = v;
-        else if (Hs)
-          Hs[e] = v;
+        if (Q && store_Q) Q[e] = v;
       }
       a[i][j] = v;
     }
@@ -954,7 +967,7 @@ __global__ __launch_bounds__(TG* TG) void k_invert_spd(const double* __restrict_
       }
     }
   }
-  finish_inverse(any, Q && store_Q ? Q : Hs, d, Qinv, work, status, tid, TG * TG);
+  finish_inverse(any, Q && store_Q ? Q : nullptr, d, Qinv, work, status, tid, TG * TG);
 }
 
 // Q-layout assembly alone (no inverse), one thread per element:
@@ -983,12 +996,12 @@ hipError_t launch_assemble_q(const double* M, int Ra, int Rb, double* Q, int acc
 
 hipError_t launch_invert_spd(const double* M, int Ra, int Rb, double* Q, int accumulate,
                              int store_Q, double* Qinv, int* status, hipStream_t st,
-                             int m_plain, double* Hs, double* work) {
+                             int m_plain, double* work) {
   const int d = Ra * Rb;
   if (d > 256) return hipErrorInvalidValue;
 #define TRK_INV(TG, B)                                                                    \
   hipLaunchKernelGGL((k_invert_spd<TG, B>), dim3(1), dim3(TG * TG), 0, st, M, Ra, Rb, Q, \
-                     accumulate, store_Q, Qinv, status, m_plain, Hs, work)
+                     accumulate, store_Q, Qinv, status, m_plain, work)
   const int B16 = (d + 15) / 16;
   switch (B16) {
     case 1: TRK_INV(16, 1); break;
@@ -1094,10 +1107,7 @@ __global__ __launch_bounds__(1024) void k_side(SideArgs sa) {
         const int r = gi % Ra, s1 = gi / Ra, r2 = gj % Ra, s2 = gj / Ra;
         v = M[(size_t)(s1 + Rb * s2) * (Ra * Ra) + (r + Ra * r2)];
         if (sa.Q && sa.accumulate) v += sa.Q[e];
-        if (sa.Q && sa.store_Q)
-          sa.Q[e] = v;
-        else if (sa.Hs)
-          sa.Hs[e] = v;
+        if (sa.Q && sa.store_Q) sa.Q[e] = v;
       }
       a[i][j] = v;
     }
@@ -1189,7 +1199,7 @@ __global__ __launch_bounds__(1024) void k_side(SideArgs sa) {
       }
     }
   }
-  finish_inverse(any, sa.Q && sa.store_Q ? sa.Q : sa.Hs, d, sa.Qinv, sa.pw, sa.status, tid,
+  finish_inverse(any, sa.Q && sa.store_Q ? sa.Q : nullptr, d, sa.Qinv, sa.pw, sa.status, tid,
                  1024);
 }
 
@@ -1421,6 +1431,13 @@ constexpr int SIDE_LDS_ALLOC = SIDE_LDS + 2;
 template <int NW, int MAXT>
 __device__ inline void side_serial(const SideArgs& sa, double* lds, double* dmax, int tid,
                                    bool pre = false) {
+  // [0] some pivot test failed, [1] waves done (zeroed here; the barriers of
+  // the chain product order this before any use)
+  __shared__ int fb_rec[2];
+  if (tid == 0) {
+    fb_rec[0] = 0;
+    fb_rec[1] = 0;
+  }
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
   const int ar = lane & 15, ak = lane >> 4;
   const int Ra = sa.Ra, Rb = sa.Rb, d = Ra * Rb;
@@ -1654,10 +1671,6 @@ __device__ inline void side_serial(const SideArgs& sa, double* lds, double* dmax
         // the mirror of an upper off-diagonal tile (the upper-triangle
         // elimination keeps only those; Q stays exactly symmetric)
         if (!COLS && ti != tj) sa.Q[gj * d + gi] = val;
-      } else if (ok && sa.Hs) {
-        // the matrix kept for the pseudo-inverse fallback
-        sa.Hs[gi * d + gj] = val;
-        if (!COLS && ti != tj) sa.Hs[gj * d + gi] = val;
       }
       if (ok && gi == gj) mx = fmax(mx, val);
       A[s][v] = ok ? val : (gi == gj ? 1.0 : 0.0);
@@ -1771,26 +1784,37 @@ __device__ inline void side_serial(const SideArgs& sa, double* lds, double* dmax
     if (!dbuf) __syncthreads();
   }
   }
-  const bool any = __syncthreads_or(bad) != 0;
   const int cl = lane & 15;
-  if (!any) {
 #pragma unroll
-    for (int s = 0; s < MAXT; ++s) {
-      if (TV[s]) {
-        const int ti = TI[s], tj = TJ[s];
+  for (int s = 0; s < MAXT; ++s) {
+    if (TV[s]) {
+      const int ti = TI[s], tj = TJ[s];
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int gi = ti * 16 + Acc<double>::row(lane, v), gj = tj * 16 + cl;
-          if (gi < d && gj < d) {
-            sa.Qinv[gi * d + gj] = A[s][v];
-            // all blocks pivoted: the inverse is symmetric
-            if (!COLS && ti != tj) sa.Qinv[gj * d + gi] = A[s][v];
-          }
+      for (int v = 0; v < 4; ++v) {
+        const int gi = ti * 16 + Acc<double>::row(lane, v), gj = tj * 16 + cl;
+        if (gi < d && gj < d) {
+          sa.Qinv[gi * d + gj] = A[s][v];
+          // all blocks pivoted: the inverse is symmetric
+          if (!COLS && ti != tj) sa.Qinv[gj * d + gi] = A[s][v];
         }
       }
     }
   }
-  finish_inverse(any, storeQ ? sa.Q : sa.Hs, d, sa.Qinv, sa.pw, sa.status, tid, NW * 64);
+  if (!sa.status) return;
+  // The waves do not wait for each other here (a workgroup barrier at this
+  // point measured about 2.5 us per launch): each wave records a failed
+  // pivot test in LDS, waits for its own stores, and counts itself out;
+  // the last wave out reads the record and, if a test failed, replaces the
+  // stored inverse by the pseudo-inverse on its own (its stores follow the
+  // other waves', which completed before they counted out).
+  if (bad) atomicOr(fb_rec, 1);
+  __builtin_amdgcn_s_waitcnt(0);
+  int prev = 0;
+  if (lane == 0) prev = atomicAdd(fb_rec + 1, 1);
+  prev = __shfl(prev, 0);
+  if (prev != NW - 1) return;
+  const bool any = atomicOr(fb_rec, 0) != 0;
+  finish_inverse(any, storeQ ? sa.Q : nullptr, d, sa.Qinv, sa.pw, sa.status, lane, 64);
 }
 
 // One upper-triangle 16x16 tile (index `tile`, row-major over the upper

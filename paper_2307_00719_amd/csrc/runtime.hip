@@ -424,20 +424,19 @@ tr_status gram_update_invert(tr_stream* s, hipStream_t on, double* M, int Ra, in
     a.cbuf[1] = s->chain[1];
     a.Ra = d;
     a.Rb = 1;
-    a.Q = Q;
-    a.accumulate = accumulate;
+    a.Q = Q ? Q : s->pinvH;          // the fallback's input is the stored matrix
+    a.accumulate = Q ? accumulate : 0;
     a.store_Q = 1;
     a.Qinv = Qinv;
     a.status = s->dstatus;
     a.counter = s->sidecnt;
-    a.Hs = s->pinvH;
     a.pw = s->pinvW;
     TR_HIP(launch_side(a, on));
     return TR_OK;
   }
   if (A) TR_HIP(launch_wgram(A, w, rows, d, M, on));
-  TR_HIP(launch_invert_spd(M, Ra, Rb, Q, accumulate, 1, Qinv, s->dstatus, on, 1, s->pinvH,
-                           s->pinvW));
+  TR_HIP(launch_invert_spd(M, Ra, Rb, Q ? Q : s->pinvH, Q ? accumulate : 0, 1, Qinv, s->dstatus,
+                           on, 1, s->pinvW));
   return TR_OK;
 }
 
@@ -1040,10 +1039,11 @@ tr_status als_run(tr_stream* s, const void* Xd, int64_t T, int max_sweeps, doubl
       a.cbuf[1] = s->chain[1];
       a.Ra = s->R[n];
       a.Rb = s->R[(n + 1) % N];
+      a.Q = s->pinvH;                // H^{!=n} kept for the fallback
+      a.store_Q = 1;
       a.Qinv = s->MinvM[n];
       a.status = s->dstatus;
       a.counter = s->sidecnt;
-      a.Hs = s->pinvH;
       a.pw = s->pinvW;
       TR_HIP(launch_side(a, s->st));
       Geom g = make_geom(N, gd.data(), s->R, n);
@@ -1115,13 +1115,14 @@ tr_status str_pass(tr_stream* s, const void* Xd, int64_t t_new, double* Gnew) {
     a.cbuf[1] = s->chain[1];
     a.Ra = s->R[n];
     a.Rb = s->R[(n + 1) % N];
-    a.Q = n == N - 1 ? nullptr : s->Q[n];
-    a.accumulate = 1;
+    // the temporal mode's H^{!=N} is not kept, but stored to scratch for the
+    // pseudo-inverse fallback
+    a.Q = n == N - 1 ? s->pinvH : s->Q[n];
+    a.accumulate = n == N - 1 ? 0 : 1;
     a.store_Q = 1;
     a.Qinv = s->MinvM[n];
     a.status = s->dstatus;
     a.counter = s->sidecnt;
-    a.Hs = s->pinvH;
     a.pw = s->pinvW;
     return a;
   };

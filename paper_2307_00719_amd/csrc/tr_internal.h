@@ -93,11 +93,11 @@ hipError_t launch_matmul(const double* A, const double* B, double* C, int d1, in
 hipError_t launch_assemble_q(const double* M, int Ra, int Rb, double* Q, int accumulate,
                              hipStream_t st);
 // When a pivot fails, Qinv receives the pseudo-inverse instead (one-sided
-// Jacobi from the stored Q, or from Hs when Q is not stored; scratch
-// `work` of 2 d^2 + d doubles); without Hs/work, status[0] is set to 1.
+// Jacobi from the stored Q; scratch `work` of 2 d^2 + d doubles); without a
+// stored Q or work, status[0] is set to 1.
 hipError_t launch_invert_spd(const double* M, int Ra, int Rb, double* Q, int accumulate,
                              int store_Q, double* Qinv, int* status, hipStream_t st,
-                             int m_plain = 0, double* Hs = nullptr, double* work = nullptr);
+                             int m_plain = 0, double* work = nullptr);
 
 // Fused per-mode side step (workgroups of 1024 threads): optionally the
 // transfer-layout Gram E_p of `rows_p` slice-major rows Gp (written to Ep,
@@ -105,7 +105,8 @@ hipError_t launch_invert_spd(const double* M, int Ra, int Rb, double* Q, int acc
 // then the ring product of the nfac transfer-layout factors fac[0..nfac)
 // (fac[j] is fr[j] x fc[j]; a null entry stands for Ep), then the Q-layout
 // assembly / accumulation into Q and the Gauss-Jordan inverse into Qinv
-// (the pseudo-inverse when a pivot fails its test and Hs / pw are given).
+// (the pseudo-inverse of the stored Q when a pivot fails its test and pw is
+// given: callers that do not keep Q pass a scratch Q with accumulate = 0).
 // With row weights Gw (rows_p of them) the Gram is sum_s Gw[s] Gp_s^T Gp_s
 // (the weighted sketched Gram, with Rpa = d and Rpb = 1).
 struct SideArgs {
@@ -124,7 +125,6 @@ struct SideArgs {
   double* Qinv;
   int* status;         // [0] failure flag, [2] fallback count, [3] this solve fell back
   unsigned* counter;   // arrival counter of the Gram workgroups (zero between launches)
-  double* Hs;          // d x d copy of the matrix when Q is not stored (fallback input)
   double* pw;          // 2 d^2 + d doubles of scratch for the pseudo-inverse fallback
 };
 hipError_t launch_side(const SideArgs& a, hipStream_t st);
