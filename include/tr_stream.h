@@ -230,6 +230,21 @@ tr_status tr_mttkrp(int32_t N, const int64_t *dims, const int32_t *ranks, int32_
                     double *P_dev, int32_t accumulate, void *ws, size_t ws_bytes,
                     void *hip_stream);
 
+/* tr_mttkrp without a workspace, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc): the same kernels and the same work split as tr_mttkrp,
+ * so the same bits, with the split-K partials in a file-scope device array
+ * of tr_mttkrp_noalloc_max_bytes() (16 MiB) held by each device the library
+ * runs on until the process ends.  The call allocates nothing and runs on
+ * the current device and the caller's stream.  A problem whose partials
+ * need more than that gives TR_ERR_UNSUPPORTED before any device work (use
+ * tr_mttkrp).  Every call on a device shares that device's array: calls that
+ * overlap on one device (other streams, other threads) race.             */
+tr_status tr_mttkrp_noalloc(int32_t N, const int64_t *dims, const int32_t *ranks, int32_t dt,
+                            int32_t n, const void *X, const void *const *cores,
+                            double *P_dev, int32_t accumulate, void *hip_stream);
+size_t tr_mttkrp_noalloc_max_bytes(void);
+
 /* Q_n = (G^{!=n}_[2])^T G^{!=n}_[2] = H^{!=n}_<2> through the chain of the
  * Gram tensors (Prop. subchain Gram; Alg. 2's H^{!=n}).  Z_dev[k] (k != n,
  * FP64 on the device) is the Gram tensor of core k, Z_k[b, a, b2, a2] =

@@ -9,6 +9,7 @@ every compute call does, and a missing library raises ImportError.
 
 from ._lib import (LIB_PATH, TRError, declared_functions, load, tr_batch_als,  # noqa: F401
                    tr_fit_loss_bwd, tr_fit_loss_fwd, tr_gram_chain, tr_last_error, tr_mttkrp,
+                   tr_mttkrp_noalloc, tr_mttkrp_noalloc_max_bytes,
                    tr_stream_get_stats,
                    tr_reconstruct_error, tr_stream_destroy, tr_stream_get_cores,
                    tr_stream_get_PQ, tr_stream_get_samples, tr_stream_init, tr_stream_load,

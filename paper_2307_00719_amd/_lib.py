@@ -95,6 +95,9 @@ def load():
         "tr_workspace_bytes": ([c_int32, P, P, c_int32], c_size_t),
         "tr_mttkrp": ([c_int32, P, P, c_int32, c_int32, P, POINTER(c_void_p), P, c_int32, P,
                        c_size_t, P], c_int32),
+        "tr_mttkrp_noalloc": ([c_int32, P, P, c_int32, c_int32, P, POINTER(c_void_p), P, c_int32,
+                               P], c_int32),
+        "tr_mttkrp_noalloc_max_bytes": ([], c_size_t),
         "tr_gram_chain": ([c_int32, P, P, c_int32, POINTER(c_void_p), P, c_int32, P, c_size_t,
                            P], c_int32),
         "tr_fit_loss_fwd": ([c_int32, P, P, c_int32, P, POINTER(c_void_p), P, P, c_size_t, P],
@@ -389,6 +392,16 @@ def tr_mttkrp(dims, ranks, dt, n, X_ptr, core_ptrs, P_ptr, accumulate, ws_ptr, w
     N, d, r = _shape_args(dims, ranks)
     _check(load().tr_mttkrp(N, d, r, dt, n, X_ptr, _ptr_array(core_ptrs), P_ptr, int(accumulate),
                             ws_ptr, ws_bytes, stream))
+
+
+def tr_mttkrp_noalloc(dims, ranks, dt, n, X_ptr, core_ptrs, P_ptr, accumulate, stream):
+    N, d, r = _shape_args(dims, ranks)
+    _check(load().tr_mttkrp_noalloc(N, d, r, dt, n, X_ptr, _ptr_array(core_ptrs), P_ptr,
+                                    int(accumulate), stream))
+
+
+def tr_mttkrp_noalloc_max_bytes():
+    return load().tr_mttkrp_noalloc_max_bytes()
 
 
 def tr_gram_chain(dims, ranks, n, Z_ptrs, Q_ptr, accumulate, ws_ptr, ws_bytes, stream):

@@ -16,6 +16,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -1752,6 +1753,70 @@ tr_status tr_mttkrp(int32_t N, const int64_t* dims, const int32_t* ranks, int32_
   if (launch_mttkrp(g, p, X, dt, cv, dt, base + w.part, st) != hipSuccess) return TR_ERR_DEVICE;
   if (launch_reduce_solve(base + w.part, p.psize, p.nsplit, g.In, g.d, P_dev, accumulate, nullptr,
                           nullptr, st) != hipSuccess)
+    return TR_ERR_DEVICE;
+  return TR_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Allocation-free MTTKRP (tr_mttkrp_noalloc): the split-K partials live in a
+// file-scope device array instead of a caller workspace.  Each device holds
+// its own copy of the array; its address is looked up once per device
+// (hipGetSymbolAddress, with that device current) and kept.  Every call on
+// a device shares that device's array, so calls that overlap on one device
+// race; the partials are fully written by the MTTKRP before the reduction
+// reads them, so nothing has to be cleared between calls.
+// ---------------------------------------------------------------------------
+namespace {
+
+constexpr size_t kScratchBytes = (size_t)16 << 20;   // 16 MiB per device
+constexpr int kScratchDevices = 64;
+
+static __device__ __align__(256) char scratch[kScratchBytes];
+
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kScratchDevices] = {};
+
+// Device address of this device's `scratch` (resolved on first use).
+hipError_t scratch_address(int device, void** out) {
+  *out = nullptr;
+  if (device < 0 || device >= kScratchDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[device]) {
+    void* p = nullptr;
+    hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[device] = p;
+  }
+  *out = g_scratch_ptr[device];
+  return hipSuccess;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t tr_mttkrp_noalloc_max_bytes(void) { return kScratchBytes; }
+
+tr_status tr_mttkrp_noalloc(int32_t N, const int64_t* dims, const int32_t* ranks, int32_t dt,
+                            int32_t n, const void* X, const void* const* cores, double* P_dev,
+                            int32_t accumulate, void* hip_stream) {
+  if (!valid_shape(N, dims, ranks, dt) || !X || !cores || !P_dev) return TR_ERR_ARG;
+  if (n < 0 || n >= N) return TR_ERR_ARG;
+  Geom g = make_geom(N, dims, ranks, n);
+  MttkrpPlan p = plan_mttkrp(g, dt);
+  // the partials of the same plan as tr_mttkrp, so both give the same bits
+  if (mttkrp_partial_bytes(g, p) > kScratchBytes) return TR_ERR_UNSUPPORTED;
+  int device = 0;
+  if (hipGetDevice(&device) != hipSuccess) return TR_ERR_DEVICE;
+  void* part = nullptr;
+  if (scratch_address(device, &part) != hipSuccess) return TR_ERR_DEVICE;
+  hipStream_t st = (hipStream_t)hip_stream;
+  CoreView cv = colmajor_view(N, dims, ranks, cores);
+  if (launch_mttkrp(g, p, X, dt, cv, dt, part, st) != hipSuccess) return TR_ERR_DEVICE;
+  if (launch_reduce_solve(part, p.psize, p.nsplit, g.In, g.d, P_dev, accumulate, nullptr, nullptr,
+                          st) != hipSuccess)
     return TR_ERR_DEVICE;
   return TR_OK;
 }
