@@ -4,8 +4,11 @@ MI355X.
 A step is one ``tr_stream_update`` of the 256 x 256 x 1000 Gaussian-core
 stream (TR-ranks 8, batches of 20 slices after a 100-slice start): the
 temporal rows, then modes 1 and 2 (Gram chain + inverse, MTTKRP, split
-reduction + solve, Gram refresh each).  The stream sits in HBM before the
-timed region starts.  ``value`` is new temporal slices per second of the
+reduction + solve, Gram refresh each).  Every stream starts from cores
+computed on the GPU by batch TR-ALS with normal equations on its first
+slices, from the counter-based random start (the initialisation of the
+experimental protocol); the CPU baseline's oracle computes its own start
+the same way.  The stream sits in HBM before the timed region starts.  ``value`` is new temporal slices per second of the
 FP64 path; the FP32-operand path (MTTKRP in FP32 MFMA, FP64 Gram/solves) is
 reported beside it.  The headline loop runs without per-kernel events
 (recording an event after every kernel serialises the queue and adds about
@@ -40,6 +43,33 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
+INIT_SWEEPS, INIT_TOL = 100, 1e-8
+
+
+def gpu_init(X_dev, t_init, ranks, seed):
+    """Initial cores of a stream: batch TR-ALS-NE (Alg. 2) on the GPU over the
+    first t_init slices from the counter-based random start of `seed` (what
+    tr_stream_init does when it is given no cores).  Returns (cores, info)."""
+    import paper_2307_00719_amd as P
+    cores, errs = P.tr_batch_als(X_dev[..., :t_init], list(ranks), None, max_sweeps=INIT_SWEEPS,
+                                 tol=INIT_TOL, seed=seed)
+    return cores, {"method": "batch TR-ALS-NE on the GPU from counter-based random cores",
+                   "sweeps": len(errs) - 1, "rel_err": float(errs[-1]), "seed": seed}
+
+
+def kernel_stats_from_profile():
+    """Average rocprofv3 durations of the fused per-mode kernel (FP64, FP32
+    operands) from the committed kernel-trace summary, if it was taken on the
+    current kernel sources."""
+    p = os.path.join(ROOT, "profiles", "mode_c2_kernel_stats.json")
+    if not os.path.exists(p):
+        return None
+    d = json.load(open(p))
+    if d.get("source_hash") != kernel_source_hash():
+        return None
+    return d
+
+
 def traffic_from_profile(dtype):
     """Per-launch HBM bytes of the fused per-mode kernel from the committed
     rocprofv3 PMC summary, if it was taken on the current kernel sources."""
@@ -52,7 +82,7 @@ def traffic_from_profile(dtype):
     return d.get("hbm_bytes_per_launch")
 
 
-def run_gpu(w, X_dev, dtype, steps, warmup):
+def run_gpu(w, X_dev, dtype, steps, warmup, cores_init):
     import torch
     import paper_2307_00719_amd as P
 
@@ -68,7 +98,7 @@ def run_gpu(w, X_dev, dtype, steps, warmup):
         return Xd[..., t0:t0 + w.t_new]
 
     # warm-up handle (compiles nothing at run time, but touches every path)
-    g = P.TRStream(X_dev[..., :w.t_init], w.cores_init, compute_dtype=dtype,
+    g = P.TRStream(X_dev[..., :w.t_init], cores_init, compute_dtype=dtype,
                    max_slices=cap, hip_stream=stream.cuda_stream)
     for b in range(warmup):
         g.update(batch(b))
@@ -76,7 +106,7 @@ def run_gpu(w, X_dev, dtype, steps, warmup):
     g.close()
 
     # timed pass: no per-kernel events (they serialise the queue)
-    g = P.TRStream(X_dev[..., :w.t_init], w.cores_init, compute_dtype=dtype,
+    g = P.TRStream(X_dev[..., :w.t_init], cores_init, compute_dtype=dtype,
                    max_slices=cap, hip_stream=stream.cuda_stream)
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -96,7 +126,7 @@ def run_gpu(w, X_dev, dtype, steps, warmup):
     g.close()
     # kernel pass: the same batches with HIP events around every kernel on
     # the streams the kernels run on (durations for the roofline)
-    g = P.TRStream(X_dev[..., :w.t_init], w.cores_init, compute_dtype=dtype,
+    g = P.TRStream(X_dev[..., :w.t_init], cores_init, compute_dtype=dtype,
                    max_slices=cap, hip_stream=stream.cuda_stream)
     g.profile(True)
     for b in range(steps):
@@ -115,22 +145,24 @@ def run_gpu(w, X_dev, dtype, steps, warmup):
     return dict(wall_s=wall, event_ms=ev_ms, kinds=kinds, rel_err=err)
 
 
-def run_stream(name, dt, steps, warmup, sketch=None):
+def run_stream(name, dt, steps, warmup, sketch=None, R=None):
     """Slices/s of the update on another configuration's stream (the sketched
-    variants use that configuration's m and seed)."""
+    variants use that configuration's seed and m = 10 R^2)."""
     import torch
     import workloads as W
     import paper_2307_00719_amd as P
 
     c = W.CONFIGS[name]
     T = c["t_init"] + (warmup + steps) * c["t_new"]
-    w = W.make(name, T=T)
+    w = W.make(name, T=T, R=R)
+    m = 10 * w.ranks[0] ** 2
     sk = sketch if sketch is not None else w.sketch
     sk = None if sk == "none" else sk
     X_dev = torch.from_numpy(w.X).cuda()
+    cores, info = gpu_init(X_dev, w.t_init, w.ranks, w.sketch_seed)
     stream = torch.cuda.Stream()
-    g = P.TRStream(X_dev[..., :w.t_init], w.cores_init, compute_dtype=dt, sketch=sk,
-                   sketch_size=w.m, seed=w.sketch_seed, max_slices=T,
+    g = P.TRStream(X_dev[..., :w.t_init], cores, compute_dtype=dt, sketch=sk,
+                   sketch_size=m, seed=w.sketch_seed, max_slices=T,
                    hip_stream=stream.cuda_stream)
     for b in range(warmup):
         g.update(X_dev[..., w.t_init + b * w.t_new:w.t_init + (b + 1) * w.t_new])
@@ -144,10 +176,29 @@ def run_stream(name, dt, steps, warmup, sketch=None):
     ms = e0.elapsed_time(e1)
     err = g.reconstruct_error(X_dev[..., :T])
     g.close()
-    return {"workload": f"{'x'.join(map(str, w.dims[:-1]))} stream, TR-ranks {w.ranks[0]}, "
-                        f"batches of {w.t_new}" + (f", {sk} sketch m={w.m}" if sk else ""),
-            "dtype": dt, "slices_per_s": steps * w.t_new / (ms / 1e3),
-            "us_per_step": 1e3 * ms / steps, "steps": steps, "rel_fit_error": err}
+    us = 1e3 * ms / steps
+    out = {"workload": f"{'x'.join(map(str, w.dims[:-1]))} stream, TR-ranks {w.ranks[0]}, "
+                       f"batches of {w.t_new}" + (f", {sk} sketch m={m}" if sk else ""),
+           "dtype": dt, "slices_per_s": steps * w.t_new / (ms / 1e3),
+           "us_per_step": us, "steps": steps, "rel_fit_error": err, "init": info}
+    N = len(w.dims)
+    esize = {"f64": 8, "f32": 4, "bf16": 2}[dt]
+    if sk:
+        # sketched steps gather m fibres per mode: the useful bytes are the
+        # sampled data, far below one pass over the batch; latency-bound
+        useful = m * (w.t_new + sum(w.dims[:-1])) * esize
+        out["roofline"] = {"bound": "latency", "useful_bytes_per_step": useful,
+                           "useful_GBps": useful / (us * 1e-6) / 1e9}
+    else:
+        xnew = 1
+        for i in w.dims[:-1]:
+            xnew *= i
+        xnew *= w.t_new
+        fl = sum(2.0 * xnew * w.ranks[k] * w.ranks[(k + 1) % N] for k in range(N))
+        out["roofline"] = {"bound": "mfma", "mttkrp_flop_per_step": fl,
+                           "achieved_TFLOPs": fl / (us * 1e-6) / 1e12,
+                           "frac": fl / (us * 1e-6) / PEAK["f32" if dt == "f32" else "f64"]}
+    return out
 
 
 def run_fitloss(steps, warmup):
@@ -187,17 +238,21 @@ def run_fitloss(steps, warmup):
             "mttkrp_frac_lower_bound": flop / (ms * 1e-3) / PEAK["f32"], "steps": steps}
 
 
-def cpu_baseline(w, budget_s):
-    """The FP64 oracle on the host: STR over as many batches as fit the
-    budget (at least 2)."""
+def cpu_baseline(w, budget_s, seed):
+    """The FP64 oracle on the host: its own start (batch TR-ALS-NE on the
+    first slices from the same counter-based random cores; not timed), then
+    STR over as many batches as fit the budget (at least 2)."""
     import numpy as np
-    from oracle import streaming
+    from oracle import batch_als, rng, streaming
     try:
         from threadpoolctl import threadpool_info
         threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
     except Exception:
         threads = os.cpu_count() or 1
-    s = streaming.STR(w.X_init(), [G.copy() for G in w.cores_init])
+    X_init = w.X_init()
+    c0 = rng.init_cores(seed, list(X_init.shape), list(w.ranks))
+    cores, errs = batch_als.tr_als_ne(X_init, c0, max_sweeps=INIT_SWEEPS, tol=INIT_TOL)
+    s = streaming.STR(X_init, cores)
     done, t0 = 0, time.perf_counter()
     while done < w.n_batches:
         s.update(w.batch(done))
@@ -209,7 +264,8 @@ def cpu_baseline(w, budget_s):
     err = s.rel_error(np.asfortranarray(w.X[..., :T]))
     return {"value": done * w.t_new / el, "unit": "slices/s", "cores": threads,
             "kind": "oracle", "sample": f"first {done} batches of the same stream "
-            f"({done * w.t_new} slices, {el:.1f} s)", "rel_fit_error": err, "batches": done}
+            f"({done * w.t_new} slices, {el:.1f} s)", "rel_fit_error": err, "batches": done,
+            "init_sweeps": len(errs) - 1, "init_rel_err": float(errs[-1])}
 
 
 def pmc_summary(fetch_dir, write_dir):
@@ -277,9 +333,51 @@ def pmc_summary(fetch_dir, write_dir):
         print("  temporal", rec["temporal"], "\n  non_temporal", rec["non_temporal"])
 
 
+def kernel_stats_summary(stats_dir):
+    """Turns the rocprofv3 ``--kernel-trace --stats`` run of this script
+    (``--steps 40 --warmup 5 --no-cpu --no-extra``) into
+    profiles/mode_c2_kernel_stats.json: average durations of the fused
+    per-mode kernel for FP64 and FP32 operands, stamped with the hash of
+    the kernel sources, plus the whole kernel table."""
+    import csv
+    import glob
+    fs = glob.glob(os.path.join(stats_dir, "**", "*kernel_stats.csv"), recursive=True)
+    if not fs:
+        raise SystemExit(f"no kernel_stats.csv under {stats_dir}")
+    rows = list(csv.DictReader(open(fs[0])))
+    table = []
+    for r in rows:
+        table.append({"kernel": r["Name"], "calls": int(r["Calls"]),
+                      "avg_us": float(r["AverageNs"]) / 1e3, "min_us": float(r["MinNs"]) / 1e3,
+                      "max_us": float(r["MaxNs"]) / 1e3, "percent": float(r["Percentage"])})
+    table.sort(key=lambda t: -t["percent"])
+
+    def avg(tag):
+        c = [t for t in table if tag in t["kernel"]]
+        return c[0]["avg_us"] if c else None
+
+    rec = {"source_hash": kernel_source_hash(),
+           "workload": "256x256x1000 stream, TR-ranks 8, batches of 20 slices",
+           "f64_kernel": "trk::k_mode<double, double, 4, 4>",
+           "f64_avg_us": avg("trk::k_mode<double, double"),
+           "f32_kernel": "trk::k_mode<float, double, 4, 4>",
+           "f32_avg_us": avg("trk::k_mode<float, double"),
+           "command": "cd /tmp && export TMPDIR=/tmp && rocprofv3 --kernel-trace --stats -d "
+                      "<repo>/gpurun_out/prof_c2 -o c2 --output-format csv -- python3 <repo>/bench.py "
+                      "--steps 40 --warmup 5 --no-cpu --no-extra; then python3 bench.py "
+                      "--kernel-stats-summary gpurun_out/prof_c2",
+           "kernels": table[:20]}
+    path = os.path.join(ROOT, "profiles", "mode_c2_kernel_stats.json")
+    json.dump(rec, open(path, "w"), indent=1)
+    print(path, rec["f64_avg_us"], rec["f32_avg_us"])
+
+
 def main():
     if len(sys.argv) == 4 and sys.argv[1] == "--pmc-summary":
         pmc_summary(sys.argv[2], sys.argv[3])
+        return
+    if len(sys.argv) == 3 and sys.argv[1] == "--kernel-stats-summary":
+        kernel_stats_summary(sys.argv[2])
         return
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -304,10 +402,12 @@ def main():
     X_dev = torch.from_numpy(w.X).cuda()          # Fortran order is preserved
     torch.cuda.synchronize()
     print(f"[bench] data on device: {tuple(w.X.shape)}", file=sys.stderr, flush=True)
+    cores0, init_info = gpu_init(X_dev, w.t_init, w.ranks, w.sketch_seed)
+    print(f"[bench] initial cores: {json.dumps(init_info)}", file=sys.stderr, flush=True)
 
     res = {}
     for dt in ("f64", "f32"):
-        res[dt] = run_gpu(w, X_dev, dt, args.steps, args.warmup)
+        res[dt] = run_gpu(w, X_dev, dt, args.steps, args.warmup, cores0)
         print(f"[bench] {dt}: {1e3 * res[dt]['event_ms'] / args.steps:.1f} us/step "
               f"{json.dumps(res[dt]['kinds'])}", file=sys.stderr, flush=True)
 
@@ -326,6 +426,7 @@ def main():
     mt_us = r["kinds"]["launch_all_modes"]["avg_us"]
     achieved = flops_launch / (mt_us * 1e-6)
     traffic = traffic_from_profile(main_dt)
+    prof = kernel_stats_from_profile()
     out = {
         "metric": "temporal slices/sec at stated rel. fit error; MTTKRP fraction of HBM/MFMA peak",
         "value": value,
@@ -340,15 +441,23 @@ def main():
         "dtype": main_dt,
         "data": "synthetic",
         "config": {"workload": "STR stream 256x256x1000, TR-ranks 8, t_init 100, t_new 20, "
-                               "Gaussian cores + 1e-2 relative noise, 1 ALS sweep per batch",
+                               "Gaussian cores + 1e-2 relative noise, 1 ALS sweep per batch, "
+                               "start from batch TR-ALS-NE on the first 100 slices",
                    "global_batch": w.t_new, "seq_len": None, "parallelism": "single-gpu"},
         "rel_fit_error": r["rel_err"],
+        "init": init_info,
         "roofline": {"bound": "mfma", "achieved": achieved / 1e12, "peak": PEAK[main_dt] / 1e12,
                      "unit": "TFLOP/s", "frac": achieved / PEAK[main_dt],
                      "traffic": traffic,
                      "kernel": "k_mode (fused side step + MTTKRP), all modes",
                      "flop_per_launch": flops_launch, "mttkrp_flop_per_launch": flops_mttkrp,
-                     "avg_launch_us": mt_us},
+                     "avg_launch_us": mt_us,
+                     "avg_launch_us_source": "HIP events around each launch on its stream",
+                     "profile_avg_launch_us": prof["f64_avg_us"] if prof else None,
+                     "frac_profile_mttkrp_only": (flops_mttkrp / (prof["f64_avg_us"] * 1e-6)
+                                                  / PEAK[main_dt]) if prof else None,
+                     "profile": "profiles/mode_c2_kernel_stats.json (rocprofv3 kernel trace, "
+                                "same sources)" if prof else None},
         "kernel_breakdown_us": {k: v["avg_us"] for k, v in r["kinds"].items()},
         "mixed_precision": {
             "dtype": "f32", "value": args.steps * w.t_new / (res["f32"]["event_ms"] / 1e3),
@@ -363,12 +472,13 @@ def main():
     }
     if not args.no_extra:
         extra = {}
-        for key, name, dt, sk in [("rstr_uniform_f32", "c3", "f32", "uniform"),
-                                  ("rstr_leverage_f32", "c3", "f32", "leverage"),
-                                  ("rstr_ksrft_bf16", "c4", "bf16", "ksrft"),
-                                  ("rstr_ksrft_f64", "c4", "f64", "ksrft"),
-                                  ("str_f32_order4", "c3", "f32", "none")]:
-            extra[key] = run_stream(name, dt, args.extra_steps, 3, sketch=sk)
+        for key, name, dt, sk, R in [("rstr_uniform_f32", "c3", "f32", "uniform", None),
+                                     ("rstr_leverage_f32", "c3", "f32", "leverage", None),
+                                     ("rstr_leverage_f32_R5", "c3", "f32", "leverage", 5),
+                                     ("rstr_ksrft_bf16", "c4", "bf16", "ksrft", None),
+                                     ("rstr_ksrft_f64", "c4", "f64", "ksrft", None),
+                                     ("str_f32_order4", "c3", "f32", "none", None)]:
+            extra[key] = run_stream(name, dt, args.extra_steps, 3, sketch=sk, R=R)
             print(f"[bench] {key}: {extra[key]['us_per_step']:.1f} us/step", file=sys.stderr,
                   flush=True)
         extra["fit_loss_f32"] = run_fitloss(args.extra_steps, 2)
@@ -376,12 +486,14 @@ def main():
               file=sys.stderr, flush=True)
         out["other_workloads"] = extra
     if not args.no_cpu:
-        cb = cpu_baseline(w, args.cpu_budget)
+        cb = cpu_baseline(w, args.cpu_budget, w.sketch_seed)
         out["cpu_baseline"] = {k: cb[k] for k in ("value", "unit", "cores", "kind", "sample")}
         out["cpu_baseline"]["rel_fit_error"] = cb["rel_fit_error"]
+        out["cpu_baseline"]["oracle_init"] = {"sweeps": cb["init_sweeps"],
+                                              "rel_err": cb["init_rel_err"]}
         # GPU error after the same number of batches, for a like-for-like comparison
         import paper_2307_00719_amd as P
-        g = P.TRStream(X_dev[..., :w.t_init], w.cores_init)
+        g = P.TRStream(X_dev[..., :w.t_init], cores0)
         for b in range(cb["batches"]):
             g.update(X_dev[..., w.t_init + b * w.t_new:w.t_init + (b + 1) * w.t_new])
         T = w.t_init + cb["batches"] * w.t_new
