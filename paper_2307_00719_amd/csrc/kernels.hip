@@ -1309,110 +1309,80 @@ __device__ inline bool wave_gj16(d4& c, int lane, double tol, int nvalid) {
 }
 
 // ---------------------------------------------------------------------------
-// Column-owner Gauss-Jordan inverse of a symmetric positive definite matrix
-// of at most 64 x 64 (nb <= 4 tiles a side) on four waves: wave j holds tile
-// column j (A[i] = tile (i, j)).  The elimination runs over pivot blocks of
-// four: step k pivots on rows / columns 4k..4k+3, which are register k%4 of
-// tile row k/4.  Per step:
-//   Pinv = P^{-1} of the 4 x 4 pivot block (four scalar pivots, owner wave),
-//   pivot rows   R_j <- Pinv R_j                      (MFMA, B operand R_j),
-//   other rows   T_ij <- T_ij - C_i (Pinv R_j)        (one 16x16x4 MFMA),
-//   pivot columns C_i <- -C_i Pinv                    (MFMA, owner wave),
-//   pivot block  <- Pinv.
-// The pivot columns are never read: in-place elimination of a symmetric
-// matrix keeps T[a][b] = -T[b][a] when exactly one of a, b has been pivoted
-// and T[a][b] = T[b][a] otherwise, so C_i is the transposed pivot-row strip
-// of tile column i with the rows already pivoted negated.  The transposed
-// strip in the A-operand layout sits in the same lanes as the strip in the
-// accumulator layout, so the waves only exchange the four pivot rows (one
-// register per tile) and Pinv through LDS, with one barrier per step.  The
-// scalar pivots are the Schur-complement diagonals of the unblocked
-// elimination, so the positivity test is the same.
+// Column-owner Gauss-Jordan inverse over 16x16 pivot blocks of a symmetric
+// positive definite matrix of at most 64 x 64 (nb <= 4 tiles a side) on four
+// waves: wave w holds tile column w (A[i] = tile (i, w)) in the MFMA
+// accumulator layout.  Step K (pivot block K, P = A_KK^{-1}):
+//   A_Kj <- P A_Kj,  A_ij <- A_ij - A_iK (P A_Kj),  A_iK <- -A_iK P,  A_KK <- P.
+// The pivot-block inverse is the owner wave's 16 in-register scalar pivots
+// (wave_gj16).  Only the pivot row strip (K, i) and P are exchanged, through
+// LDS (two buffers, one barrier per step): in-place elimination of a
+// symmetric matrix keeps A_iK = (A_Ki)^T while neither block is pivoted and
+// A_iK = -(A_Ki)^T once block i is, so the pivot column comes from the
+// pivot row, and register q of an accumulator tile is the A operand of
+// k-step q of its transpose (P is symmetric, so it serves as its own A
+// operand).  Look-ahead: every wave updates its tile of the next pivot row
+// first and publishes it; the next owner inverts its updated diagonal tile
+// at once, before its other updates.  The scalar pivots are those of the
+// unblocked elimination, so the positivity test is the same.
 // ---------------------------------------------------------------------------
-
-// Pinv of the 4 x 4 pivot block held in register x at lanes 16g + 4*KK + r
-// (row g, column r): four in-wave scalar Gauss-Jordan steps.  Lanes outside
-// the block's columns end with Pinv times their row strip (unused).
-template <int KK, int p>
-__device__ inline void pinv4_step(double& x, int g, int r, double tol, int nvalid, bool& bad) {
-  const double rowp = group_bcast<p>(x);                      // P[p][r]
-  const double colp = row_bcast<4 * KK + p>(x);               // P[g][p]
-  const double piv = lane_value<16 * p + 4 * KK + p>(x);      // P[p][p]
-  if (4 * KK + p < nvalid && !(piv > tol)) bad = true;
-  // the hardware reciprocal is good to about 2^-26; one Newton step squares
-  // its error to the last bit or two of the double
-  double ip = __builtin_amdgcn_rcp(piv);
-  ip = fma(fma(-piv, ip, 1.0), ip, ip);
-  const bool cj = r == 4 * KK + p;
-  const double yo = cj ? -x * ip : fma(-colp, rowp * ip, x);
-  const double yr = cj ? ip : x * ip;
-  x = g == p ? yr : yo;
-  if constexpr (p < 3) pinv4_step<KK, p + 1>(x, g, r, tol, nvalid, bad);
-}
-
-// Input of elimination step k: every wave publishes its part of the pivot
-// rows (register k%4 of tile (k/4, j)), the owner wave inverts the pivot
-// block and publishes Pinv (kept in `pinv` for its own fix-ups).  LDS per
-// step parity: four 64-lane strips and the 16 entries of Pinv.
-template <int k>
-__device__ inline void gj64_publish(const d4 (&A)[4], double* lds, int lane, int wave, int nb,
-                                    int d, double tol, bool& bad, double& pinv) {
-  constexpr int K = k >> 2, KK = k & 3;
-  double* S = lds + (k & 1) * 320;
-  double* Pv = S + 256;
-  if (wave < nb) S[wave * 64 + lane] = A[K][KK];
-  if (wave == K) {
-    const int g = lane >> 4, r = lane & 15;
-    pinv = A[K][KK];
-    pinv4_step<KK, 0>(pinv, g, r, tol, d - 16 * K, bad);
-    if ((r >> 2) == KK) Pv[g * 4 + (r & 3)] = pinv;
-  }
-}
-
-// Elimination step k (pivot rows 4k..4k+3), then the next.  The tile row
-// of the next pivot block is updated first and the next step's input is
-// published right after it, before the other tiles of this step.
-template <int k>
-__device__ inline void gj64_step(d4 (&A)[4], double* lds, int lane, int wave, int nb, int d,
-                                 double tol, bool& bad, double& pinv) {
-  constexpr int K = k >> 2, KK = k & 3;
-  if (K >= nb) return;
-  const int g = lane >> 4, r = lane & 15;
-  const double* S = lds + (k & 1) * 320;
-  const double* Pv = S + 256;
-  __syncthreads();
-  const double pin = pinv;
+__device__ inline void gj_cols16(d4 (&A)[4], double* lds, int lane, int wave, int nb, int d,
+                                 double tol, bool& bad) {
+  // slot i of buffer b: lds + 1024 b + 256 i (tile (K, i), or P in slot K)
   if (wave < nb) {
-    const d4 zero = {0, 0, 0, 0};
-    const double pa = r < 4 ? Pv[r * 4 + g] : 0.0;            // Pinv[r][g], A operand
-    const d4 d1 = mfma16(pa, A[K][KK], zero);                 // rows 0..3: Pinv R_j
-    const bool own = wave == K;
-    const bool colP = own && (r >> 2) == KK;
-    const double pb = colP ? Pv[g * 4 + (r & 3)] : 0.0;       // Pinv in the pivot columns
-    constexpr int KN = (k + 1) >> 2;
+    if (wave == 0) bad |= wave_gj16(A[0], lane, tol, d);
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
-      const int i = (KN + t) & 3;
-      if (i < nb) {
-        const double sv = S[i * 64 + lane];
-        const double a2 = 16 * i + r < 4 * k ? sv : -sv;      // -C_i, A operand
-        const d4 d2 = mfma16(a2, d1[0], A[i]);
-        d4 d3 = zero;
-        if (own) d3 = mfma16(a2, pb, zero);                   // -C_i Pinv
+    for (int v = 0; v < 4; ++v) lds[wave * 256 + v * 64 + lane] = A[0][v];
+  }
+  __syncthreads();
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          if (i == K && v == KK)
-            A[i][v] = colP ? pin : d1[0];
-          else
-            A[i][v] = colP ? d3[v] : d2[v];
+  for (int K = 0; K < 4; ++K) {
+    if (K >= nb) break;
+    const double* Sc = lds + (K & 1) * 1024;
+    double* Sn = lds + ((K & 1) ^ 1) * 1024;
+    const bool nextp = K + 1 < nb;
+    if (wave < nb) {
+      if (wave != K) {
+        d4 U = {0, 0, 0, 0};
+#pragma unroll
+        for (int q = 0; q < 4; ++q) U = mfma16(Sc[K * 256 + q * 64 + lane], A[K][q], U);
+#pragma unroll
+        for (int t = 1; t < 4; ++t) {
+          const int i = (K + t) & 3;
+          if (i < nb) {
+            const double sg = i < K ? 1.0 : -1.0;
+            d4 acc = A[i];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) acc = mfma16(sg * Sc[i * 256 + q * 64 + lane], U[q], acc);
+            A[i] = acc;
+            if (t == 1 && nextp) {
+              if (wave == K + 1) bad |= wave_gj16(A[i], lane, tol, d - 16 * (K + 1));
+#pragma unroll
+              for (int v = 0; v < 4; ++v) Sn[wave * 256 + v * 64 + lane] = A[i][v];
+            }
+          }
+        }
+        A[K] = U;
+      } else {
+#pragma unroll
+        for (int t = 1; t < 4; ++t) {
+          const int i = (K + t) & 3;
+          if (i < nb) {
+            const double sg = i < K ? 1.0 : -1.0;
+            d4 acc = {0, 0, 0, 0};
+#pragma unroll
+            for (int q = 0; q < 4; ++q) acc = mfma16(sg * Sc[i * 256 + q * 64 + lane], A[K][q], acc);
+            A[i] = acc;
+            if (t == 1 && nextp) {
+#pragma unroll
+              for (int v = 0; v < 4; ++v) Sn[wave * 256 + v * 64 + lane] = A[i][v];
+            }
+          }
         }
       }
-      if constexpr (k < 15) {
-        if (t == 0 && KN < nb) gj64_publish<k + 1>(A, lds, lane, wave, nb, d, tol, bad, pinv);
-      }
     }
+    __syncthreads();
   }
-  if constexpr (k < 15) gj64_step<k + 1>(A, lds, lane, wave, nb, d, tol, bad, pinv);
 }
 
 // LDS budget of the side step, in doubles (66 KiB: two 64 x 64 chain operands,
@@ -1686,10 +1656,8 @@ __device__ inline void side_serial(const SideArgs& sa, double* lds, double* dmax
   const double tol = (double)d * 2.220446049250313e-16 * mx;
   bool bad = false;
   if constexpr (COLS) {
-    // 4. column-owner elimination in pivot blocks of four
-    double pinv = 0.0;
-    gj64_publish<0>(A, lds, lane, wave, nb, d, tol, bad, pinv);
-    gj64_step<0>(A, lds, lane, wave, nb, d, tol, bad, pinv);
+    // 4. column-owner elimination over 16x16 pivot blocks
+    gj_cols16(A, lds, lane, wave, nb, d, tol, bad);
   } else {
   // 4. blocked Gauss-Jordan over the upper-triangle tiles, LDS
   //    double-buffered per pivot block: Pb = P (row-major), PbT = P^T,
