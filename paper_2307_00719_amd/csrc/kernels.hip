@@ -11,6 +11,8 @@
 
 #include <hip/hip_runtime.h>
 #include <hip/hip_bf16.h>
+
+#include "bf16_round.h"
 #include <stdint.h>
 
 #include <algorithm>
@@ -118,9 +120,10 @@ __device__ inline int64_t decode_column(const Geom& g, int64_t k, int* idx) {
   return off;
 }
 
-MttkrpPlan plan_mttkrp(const Geom& g, int xdtype, int max_wg) {
+MttkrpPlan plan_mttkrp(const Geom& g, int xdtype, int max_wg, bool bulk) {
   MttkrpPlan p;
   const int N = g.N;
+  p.zform = 0;
   p.MT = 16;
   p.mtiles = (int)((g.In + 15) / 16);
   p.psize = (xdtype == F64) ? 8 : 4;
@@ -154,6 +157,20 @@ MttkrpPlan plan_mttkrp(const Geom& g, int xdtype, int max_wg) {
   }
   p.upw = (p.Kout + chunks - 1) / chunks;
   p.nsplit = (int)((p.Kout + p.upw - 1) / p.upw);
+  if (bulk && xdtype == F32 && If <= 64) {
+    bool small = N <= 4;
+    for (int k = 0; k < N; ++k) small = small && g.R[k] <= 16;
+    // one 8-wave workgroup per CU (its two Z buffers take 136 KiB of LDS):
+    // about 256 workgroups of 64 rows, at least two outer indices each
+    const int64_t mg = (g.In + 63) / 64;
+    int64_t zc = 256 / mg;
+    if (zc < 1) zc = 1;
+    if (small && p.Kout >= 2 * zc) {
+      p.zform = 1;
+      p.upw = (p.Kout + zc - 1) / zc;
+      p.nsplit = (int)((p.Kout + p.upw - 1) / p.upw);
+    }
+  }
   return p;
 }
 
@@ -498,6 +515,9 @@ static hipError_t launch_mttkrp_j(const Geom& g, const MttkrpPlan& p, const void
   }
 }
 
+static hipError_t launch_mttkrp_z(const Geom& g, const MttkrpPlan& p, const float* X,
+                                  const CoreView& cv, float* part, hipStream_t st);
+
 hipError_t launch_mttkrp(const Geom& g, const MttkrpPlan& p, const void* X, int xdt,
                          const CoreView& cv, int cdt, void* part, hipStream_t st) {
   if (g.d > 256 || p.nbf > 16) return hipErrorInvalidValue;
@@ -509,8 +529,519 @@ hipError_t launch_mttkrp(const Geom& g, const MttkrpPlan& p, const void* X, int 
   if (xspan >= ((int64_t)1 << 31) || gspan >= ((int64_t)1 << 31)) return hipErrorInvalidValue;
   if (xdt == F64 && cdt == F64) return launch_mttkrp_j<double, double>(g, p, X, cv, part, st);
   if (xdt == F32 && cdt == F64) return launch_mttkrp_j<float, double>(g, p, X, cv, part, st);
-  if (xdt == F32 && cdt == F32) return launch_mttkrp_j<float, float>(g, p, X, cv, part, st);
+  if (xdt == F32 && cdt == F32) {
+    if (p.zform) return launch_mttkrp_z(g, p, (const float*)X, cv, (float*)part, st);
+    return launch_mttkrp_j<float, float>(g, p, X, cv, part, st);
+  }
   return hipErrorInvalidValue;
+}
+
+// ---------------------------------------------------------------------------
+// MTTKRP over many outer indices with every TR-rank <= 16 and I_f <= 64, FP32
+// operands and FP32 accumulation over the chunk (the fit-loss gradients).
+// For each outer index o the subchain block of all i_f,
+//   Z_o[i_f][s][r] = (U(o) G_f(i_f) V(o))[s][r],
+// is formed once for the workgroup's 64 rows (per i_f two 16x16x16 MFMA
+// products; U^T and V are MFMA chains of the core slices) into LDS, and the
+// rows accumulate P[m, r + R_n s] += sum_{i_f} X[m, o, i_f] Z_o[i_f][s][r] in
+// MFMA accumulators across the chunk.  Z of the next outer index is formed
+// while the current one is used (two LDS buffers, one barrier per outer
+// index); the X operands and core slices are loaded one outer index ahead.
+// Workgroup: 8 waves over rows [64 y, 64 y + 64); wave w owns row tile w % 4
+// and the column tiles s in [8 (w / 4), 8 (w / 4) + 8), and forms Z for
+// i_f in [8 w, 8 w + 8).  K order of the main product: lane group g of
+// k-step q takes i_f = 16 g + q, so the 16 Z operands of a lane in one
+// column tile are one contiguous LDS row.
+// Layout facts used (16x16x4 FP32 MFMA): the accumulator register v of lane
+// (c, g) holds row 4 g + v, column c, which is also the B operand of k-step
+// v with k = 4 g + v; the A operand of that k-step at lane (m, g) is then
+// A[m][4 g + v], i.e. the accumulator layout of A^T.  So V = F_1 .. F_k is
+// built right to left (C <- F_j C) and U^T = F_k^T .. F_1^T likewise.
+// ---------------------------------------------------------------------------
+constexpr int ZKP = 68;            // LDS pitch (floats) of one Z row (s, r): 64 i_f + 4
+constexpr int ZMAXF = 2;          // most slices in U and V together (orders 2 to 4)
+
+// Everything the formed-subchain kernels read besides X, resolved on the
+// host: slot j < nU + nV is the j-th chain factor (U's modes n+1 .. f-1, then
+// V's modes f+1 .. n-1), slot ZMAXF is G_f, slot ZMAXF + 1 is G_n.  Factor j
+// of outer index o is the slice at index (o / div[j]) % mod[j] of its mode;
+// the X offset of (i_n = 0, i_f = 0, o) is mlo (o % Lh) + mhi (o / Lh).
+struct ZArgs {
+  const float* ptr[ZMAXF + 2];
+  int si[ZMAXF + 2], sr[ZMAXF + 2], ss[ZMAXF + 2], ra[ZMAXF + 2], rb[ZMAXF + 2];
+  unsigned div[ZMAXF], mod[ZMAXF];
+  int nU, nV;
+  int In, If, Rn, Rn1, d;
+  int sm, sf;        // X strides (elements) of the row index and of i_f
+  unsigned Lh;
+  long long mlo, mhi;
+  int upw, Kout;
+};
+
+// Slice F (R_a x R_b, zero padded to 16 x 16) of slot j at index i, in one of
+// two register patterns of lane (l16, g4):
+//   acc pattern: reg v = F[4 g4 + v][l16]   (accumulator layout of F)
+//   A pattern:   reg v = F[l16][4 g4 + v]   (A operand of F = acc layout of F^T)
+__device__ inline bool slice16_ok(const ZArgs& z, int j, bool acc_pattern, int l16, int g4,
+                                  int v) {
+  const int a = acc_pattern ? 4 * g4 + v : l16, b = acc_pattern ? l16 : 4 * g4 + v;
+  return a < z.ra[j] && b < z.rb[j];
+}
+// raw: the padding positions hold some in-range element, zeroed by the caller
+__device__ inline f4 load_slice16_raw(const ZArgs& z, int j, int i, bool acc_pattern, int l16,
+                                      int g4) {
+  const float* F = z.ptr[j] + i * z.si[j];
+  f4 r;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int a = acc_pattern ? 4 * g4 + v : l16, b = acc_pattern ? l16 : 4 * g4 + v;
+    r[v] = F[slice16_ok(z, j, acc_pattern, l16, g4, v) ? a * z.sr[j] + b * z.ss[j] : 0];
+  }
+  return r;
+}
+__device__ inline f4 load_slice16(const ZArgs& z, int j, int i, bool acc_pattern, int l16,
+                                  int g4) {
+  f4 r = load_slice16_raw(z, j, i, acc_pattern, l16, g4);
+#pragma unroll
+  for (int v = 0; v < 4; ++v)
+    if (!slice16_ok(z, j, acc_pattern, l16, g4, v)) r[v] = 0.0f;
+  return r;
+}
+
+__device__ inline f4 mfma_chain4(f4 a, f4 b) {
+  f4 c = {0, 0, 0, 0};
+#pragma unroll
+  for (int q = 0; q < 4; ++q) c = mfma16(a[q], b[q], c);
+  return c;
+}
+
+// The subchain pieces of one lane: the wave's 8 slices G_f(i_f), kept for
+// every outer index (the A pattern when a V follows, else the acc pattern,
+// then T = G_f(i_f)); the chain slices of an outer index, loaded raw (U's
+// first factor in the A pattern, its others in the acc pattern; V's last
+// factor in the acc pattern, its others in the A pattern) with their padding
+// zeroed where used; U^T = F_k^T .. F_1^T and V = F_1 .. F_k in the
+// accumulator layout, each built right to left; and the 16 x 16 block
+// Z(i_f) = U G_f(i_f) V.
+template <int NU, int NV>
+struct ZLane {
+  static constexpr int NF = NU + NV;
+  static constexpr int NS = NF > 0 ? NF : 1;
+  f4 gf[8];
+  unsigned okb;
+  int l16, g4;
+
+  __device__ void init(const ZArgs& z, int wave, int lane) {
+    l16 = lane & 15;
+    g4 = lane >> 4;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int i_f = 8 * wave + u;
+      gf[u] = load_slice16(z, ZMAXF, i_f < z.If ? i_f : z.If - 1, NV == 0, l16, g4);
+      if (i_f >= z.If) gf[u] = f4{0, 0, 0, 0};
+    }
+    okb = 0;
+#pragma unroll
+    for (int j = 0; j < NF; ++j) {
+      const bool accp = j < NU ? j > 0 : j == NF - 1;
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+        if (slice16_ok(z, j, accp, l16, g4, v)) okb |= 1u << (4 * j + v);
+    }
+  }
+  __device__ void load(const ZArgs& z, int o, f4 (&sl)[NS]) const {
+#pragma unroll
+    for (int j = 0; j < NF; ++j) {
+      const int i = (int)(((unsigned)o / z.div[j]) % z.mod[j]);
+      const bool accp = j < NU ? j > 0 : j == NF - 1;
+      sl[j] = load_slice16_raw(z, j, i, accp, l16, g4);
+    }
+  }
+  __device__ void chains(const f4 (&raw)[NS], f4& ut, f4& vv) const {
+    f4 sl[NS];
+#pragma unroll
+    for (int j = 0; j < NF; ++j) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) sl[j][v] = (okb >> (4 * j + v)) & 1u ? raw[j][v] : 0.0f;
+    }
+    if constexpr (NU > 0) {
+      ut = sl[0];
+#pragma unroll
+      for (int j = 1; j < NU; ++j) ut = mfma_chain4(sl[j], ut);
+    }
+    if constexpr (NV > 0) {
+      vv = sl[NF - 1];
+#pragma unroll
+      for (int j = NF - 2; j >= NU; --j) vv = mfma_chain4(sl[j], vv);
+    }
+  }
+  // Z(i_f) for the wave's u-th i_f, accumulator layout: reg v of lane (r, g)
+  // = Z[4 g + v][r]
+  __device__ f4 block(int u, f4 ut, f4 vv) const {
+    f4 t = gf[u];
+    if constexpr (NV > 0) t = mfma_chain4(t, vv);
+    if constexpr (NU > 0) t = mfma_chain4(ut, t);
+    return t;
+  }
+};
+
+template <int NU, int NV>
+__global__ __launch_bounds__(512, 1) void k_mttkrp_z(ZArgs z, const float* __restrict__ X,
+                                                     float* __restrict__ part) {
+  typedef ZLane<NU, NV> ZL;
+  extern __shared__ __align__(16) float zl[];            // [2][256][ZKP]
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int l16 = lane & 15, g4 = lane >> 4;
+  const int mt = wave & 3, sh = wave >> 2;
+  const int row = blockIdx.y * 64 + mt * 16 + l16;
+  const int arow = (row < z.In ? row : z.In - 1) * z.sm;
+  const int o0 = blockIdx.x * z.upw;
+  const int o1 = o0 + z.upw < z.Kout ? o0 + z.upw : z.Kout;
+  const int cnt = o1 - o0;
+  ZL zc;
+  zc.init(z, wave, lane);
+
+  // Z_o of the wave's 8 i_f into LDS buffer b, rows (s, r), i_f contiguous
+  auto zform = [&](int b, f4 ut, f4 vv) {
+    float* zb = zl + b * (256 * ZKP);
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      f4 zz[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) zz[u] = zc.block(4 * h + u, ut, vv);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const f4 w = {zz[0][v], zz[1][v], zz[2][v], zz[3][v]};
+        *(f4*)(zb + ((4 * g4 + v) * 16 + l16) * ZKP + 8 * wave + 4 * h) = w;
+      }
+    }
+  };
+  // X operands of outer index o, unmasked: a row beyond I_n only feeds its
+  // own (unwritten) accumulator row, and an i_f beyond I_f meets a zero Z row
+  auto load_x = [&](int o, float (&x)[16]) {
+    const unsigned ou = (unsigned)o;
+    const float* Xo = X + z.mlo * (long long)(ou % z.Lh) + z.mhi * (long long)(ou / z.Lh) + arow;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int i_f = 16 * g4 + q;
+      x[q] = Xo[(i_f < z.If ? i_f : z.If - 1) * z.sf];
+    }
+  };
+
+  f4 acc[8];
+#pragma unroll
+  for (int t = 0; t < 8; ++t) acc[t] = f4{0, 0, 0, 0};
+  f4 slr[ZL::NS];
+  f4 ut = {0, 0, 0, 0}, vv = {0, 0, 0, 0};
+  float xa[16], xb[16];
+  zc.load(z, o0, slr);
+  zc.chains(slr, ut, vv);
+  zform(0, ut, vv);
+  load_x(o0, xa);
+  zc.load(z, o0 + 1 < o1 ? o0 + 1 : o1 - 1, slr);
+  __syncthreads();
+  // one outer index: form Z of the next one (the last step forms an unused
+  // copy), load the X operands and chain slices of the next ones, multiply
+  // the current X tile by the current Z.  No branches inside, so the loads
+  // stay in flight until the next step.
+  auto step = [&](int j, const float (&xu)[16], float (&xl)[16]) {
+    const int on = o0 + j + 1 < o1 ? o0 + j + 1 : o1 - 1;
+    const int on2 = o0 + j + 2 < o1 ? o0 + j + 2 : o1 - 1;
+    zc.chains(slr, ut, vv);
+    load_x(on, xl);
+    zc.load(z, on2, slr);
+    zform((j + 1) & 1, ut, vv);
+    const float* zb = zl + (j & 1) * (256 * ZKP) + ((8 * sh) * 16 + l16) * ZKP + 16 * g4;
+    // every column tile, valid or not (Z is zero beyond R_{n+1}); the eight
+    // accumulators take turns so consecutive MFMAs are independent
+#pragma unroll
+    for (int qb = 0; qb < 4; ++qb) {
+      f4 b[8];
+#pragma unroll
+      for (int t = 0; t < 8; ++t) b[t] = *(const f4*)(zb + t * 16 * ZKP + 4 * qb);
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+#pragma unroll
+        for (int t = 0; t < 8; ++t) acc[t] = mfma16(xu[4 * qb + u], b[t][u], acc[t]);
+      }
+    }
+    __syncthreads();
+  };
+  for (int j = 0; j < cnt; j += 2) {
+    step(j, xa, xb);
+    if (j + 1 < cnt) step(j + 1, xb, xa);
+  }
+  // this chunk's partial: acc[t] register v of lane (r, g) = row 4 g + v of
+  // the row tile, column r of column tile s = 8 sh + t
+#pragma unroll
+  for (int t = 0; t < 8; ++t) {
+    const int sc = 8 * sh + t;
+    if (sc < z.Rn1 && l16 < z.Rn) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int m = blockIdx.y * 64 + mt * 16 + 4 * g4 + v;
+        if (m < z.In)
+          part[((size_t)blockIdx.x * z.In + m) * z.d + l16 + z.Rn * sc] = acc[t][v];
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Squared residual of the TR model (fit-loss forward) with the same formed
+// subchain blocks, for mode n:
+//   Xhat[m, o, i_f] = sum_{s,r} G_n(m)[r][s] Z_o[i_f][s][r],
+// a 64 x 64 x 256 MFMA product per outer index against the G_n rows held in
+// registers, with Z_o stored i_f-major (one row of 256 (s, r) per i_f) so a
+// lane's B operands are contiguous.  Each workgroup writes its sums of
+// (X - Xhat)^2 and X^2 (FP64 per lane) as one pair.  Waves as in
+// k_mttkrp_z, except that wave w takes the i_f tiles 2 (w / 4) and
+// 2 (w / 4) + 1; K order: lane group g of k-step q takes (s, r) = 64 g + q.
+// ---------------------------------------------------------------------------
+constexpr int ZTP = 260;           // LDS pitch (floats) of one Z row i_f: 256 (s, r) + 4
+
+template <int NU, int NV>
+__global__ __launch_bounds__(512, 1) void k_recon_z(ZArgs z, const float* __restrict__ X,
+                                                    double* __restrict__ wg_out) {
+  typedef ZLane<NU, NV> ZL;
+  extern __shared__ __align__(16) float zt[];            // [2][64][ZTP]
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int l16 = lane & 15, g4 = lane >> 4;
+  const int mt = wave & 3, sh = wave >> 2;
+  const int o0 = blockIdx.x * z.upw;
+  const int o1 = o0 + z.upw < z.Kout ? o0 + z.upw : z.Kout;
+  const int cnt = o1 - o0;
+  ZL zc;
+  zc.init(z, wave, lane);
+  // A operands: G_n(m)[r][s] for (s, r) = 64 g4 + q, zero outside the ranks
+  float ga[64];
+  {
+    const int m = blockIdx.y * 64 + mt * 16 + l16;
+    const int j = ZMAXF + 1;
+    const float* Gn = z.ptr[j] + (m < z.In ? m : z.In - 1) * z.si[j];
+#pragma unroll
+    for (int q = 0; q < 64; ++q) {
+      const int sc = 4 * g4 + (q >> 4), r = q & 15;
+      const bool ok = m < z.In && r < z.Rn && sc < z.Rn1;
+      const float v = Gn[ok ? r * z.sr[j] + sc * z.ss[j] : 0];
+      ga[q] = ok ? v : 0.0f;
+    }
+  }
+  // Z_o of the wave's 8 i_f into LDS buffer b, one row of (s, r) per i_f
+  auto zform = [&](int b, f4 ut, f4 vv) {
+    float* zb = zt + b * (64 * ZTP);
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const f4 w = zc.block(u, ut, vv);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) zb[(8 * wave + u) * ZTP + (4 * g4 + v) * 16 + l16] = w[v];
+    }
+  };
+  // X at the accumulator positions of the wave's two i_f tiles: reg v of
+  // lane (c, g) is row 16 mt + 4 g + v, i_f = 16 (2 sh + h) + c
+  const int mrow0 = blockIdx.y * 64 + mt * 16 + 4 * g4;
+  auto load_x = [&](int o, float (&x)[8]) {
+    const unsigned ou = (unsigned)o;
+    const float* Xo = X + z.mlo * (long long)(ou % z.Lh) + z.mhi * (long long)(ou / z.Lh);
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int i_f = 16 * (2 * sh + h) + l16;
+      const int ic = i_f < z.If ? i_f : z.If - 1;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int m = mrow0 + v < z.In ? mrow0 + v : z.In - 1;
+        x[4 * h + v] = Xo[m * z.sm + ic * z.sf];
+      }
+    }
+  };
+  double err = 0.0, nrm = 0.0;
+  f4 slr[ZL::NS];
+  f4 ut = {0, 0, 0, 0}, vv = {0, 0, 0, 0};
+  float xa[8], xb[8];
+  zc.load(z, o0, slr);
+  zc.chains(slr, ut, vv);
+  zform(0, ut, vv);
+  load_x(o0, xa);
+  zc.load(z, o0 + 1 < o1 ? o0 + 1 : o1 - 1, slr);
+  __syncthreads();
+  auto step = [&](int j, const float (&xu)[8], float (&xl)[8]) {
+    const int on = o0 + j + 1 < o1 ? o0 + j + 1 : o1 - 1;
+    const int on2 = o0 + j + 2 < o1 ? o0 + j + 2 : o1 - 1;
+    zc.chains(slr, ut, vv);
+    load_x(on, xl);
+    zc.load(z, on2, slr);
+    zform((j + 1) & 1, ut, vv);
+    const float* zb = zt + (j & 1) * (64 * ZTP) + (32 * sh + l16) * ZTP + 64 * g4;
+    // two i_f tiles x two halves of K: four independent accumulators
+    f4 acc[2][2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) acc[h][0] = acc[h][1] = f4{0, 0, 0, 0};
+#pragma unroll
+    for (int qb = 0; qb < 8; ++qb) {
+      f4 b[2][2];
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        b[h][0] = *(const f4*)(zb + h * 16 * ZTP + 4 * qb);
+        b[h][1] = *(const f4*)(zb + h * 16 * ZTP + 32 + 4 * qb);
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          acc[h][0] = mfma16(ga[4 * qb + u], b[h][0][u], acc[h][0]);
+          acc[h][1] = mfma16(ga[32 + 4 * qb + u], b[h][1][u], acc[h][1]);
+        }
+      }
+    }
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int i_f = 16 * (2 * sh + h) + l16;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        if (i_f < z.If && mrow0 + v < z.In) {
+          const double x = (double)xu[4 * h + v];
+          const double e = x - (double)(acc[h][0][v] + acc[h][1][v]);
+          err += e * e;
+          nrm += x * x;
+        }
+      }
+    }
+    __syncthreads();
+  };
+  for (int j = 0; j < cnt; j += 2) {
+    step(j, xa, xb);
+    if (j + 1 < cnt) step(j + 1, xb, xa);
+  }
+  // workgroup sums in a fixed order: wave shuffles, then the 8 wave sums
+  for (int off = 32; off > 0; off >>= 1) {
+    err += __shfl_xor(err, off);
+    nrm += __shfl_xor(nrm, off);
+  }
+  double* red = (double*)zt;
+  if (lane == 0) {
+    red[wave] = err;
+    red[8 + wave] = nrm;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    double a = 0.0, b = 0.0;
+    for (int w = 0; w < 8; ++w) {
+      a += red[w];
+      b += red[8 + w];
+    }
+    const int blk = blockIdx.x + gridDim.x * blockIdx.y;
+    wg_out[2 * blk] = a;
+    wg_out[2 * blk + 1] = b;
+  }
+}
+
+// The chain, fast-mode and row cores and the outer-index decoding of a
+// formed-subchain plan (false if an offset would leave 32 bits).
+static bool make_zargs(const Geom& g, const MttkrpPlan& p, const CoreView& cv, ZArgs* zp) {
+  const int N = g.N, n = g.n, f = p.f;
+  ZArgs& z = *zp;
+  z = ZArgs{};
+  z.nU = (f - (n + 1) + N) % N;
+  z.nV = (n - (f + 1) + N) % N;
+  if (z.nU + z.nV > ZMAXF) return false;
+  // index divisor of mode q in the enumeration of the outer indices (the
+  // multi-index of the modes other than n and f, fastest first)
+  auto divisor = [&](int q) -> int64_t {
+    int64_t dv = 1;
+    for (int p2 = 0; p2 < q; ++p2)
+      if (p2 != n && p2 != f) dv *= g.I[p2];
+    return dv;
+  };
+  bool ok = true;
+  auto set_slot = [&](int j, int k) {
+    z.ptr[j] = (const float*)cv.ptr[k];
+    z.si[j] = (int)cv.si[k];
+    z.sr[j] = (int)cv.sr[k];
+    z.ss[j] = (int)cv.ss[k];
+    z.ra[j] = g.R[k];
+    z.rb[j] = g.R[(k + 1) % N];
+    const int64_t span = (g.I[k] - 1) * cv.si[k] + (g.R[k] - 1) * cv.sr[k] +
+                         (g.R[(k + 1) % N] - 1) * cv.ss[k] + 1;
+    ok = ok && span < ((int64_t)1 << 31);
+  };
+  for (int j = 0; j < z.nU + z.nV; ++j) {
+    const int k = j < z.nU ? (n + 1 + j) % N : (f + 1 + (j - z.nU)) % N;
+    set_slot(j, k);
+    z.div[j] = (unsigned)divisor(k);
+    z.mod[j] = (unsigned)g.I[k];
+  }
+  set_slot(ZMAXF, f);
+  set_slot(ZMAXF + 1, n);
+  z.In = (int)g.In;
+  z.If = (int)g.I[f];
+  z.Rn = g.R[n];
+  z.Rn1 = g.R[(n + 1) % N];
+  z.d = g.d;
+  z.sm = (int)p.sm;
+  z.sf = (int)p.sf;
+  if (n == 0) {
+    z.Lh = 1u;
+    z.mlo = 0;
+    z.mhi = g.I[0] * g.I[1];
+  } else {
+    z.Lh = (unsigned)(g.L / g.I[0]);
+    z.mlo = g.I[0];
+    z.mhi = g.L * g.In;
+  }
+  z.upw = (int)p.upw;
+  z.Kout = (int)p.Kout;
+  // 32-bit index arithmetic inside the kernels
+  if (p.Kout >= ((int64_t)1 << 31) || (g.In - 1) * p.sm + (g.I[f] - 1) * p.sf >= ((int64_t)1 << 31))
+    ok = false;
+  return ok;
+}
+
+template <template <int, int> class K, typename... A>
+static hipError_t launch_z(const ZArgs& z, dim3 grid, size_t lds, hipStream_t st, A... args) {
+  void (*fn)(ZArgs, A...) = nullptr;
+  switch (z.nU * 3 + z.nV) {
+    case 0: fn = K<0, 0>::fn; break;
+    case 1: fn = K<0, 1>::fn; break;
+    case 2: fn = K<0, 2>::fn; break;
+    case 3: fn = K<1, 0>::fn; break;
+    case 4: fn = K<1, 1>::fn; break;
+    case 6: fn = K<2, 0>::fn; break;
+    default: return hipErrorInvalidValue;
+  }
+  hipError_t e =
+      hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(fn, grid, dim3(512), lds, st, z, args...);
+  return hipGetLastError();
+}
+template <int NU, int NV> struct MttkrpZ {
+  static constexpr auto fn = k_mttkrp_z<NU, NV>;
+};
+template <int NU, int NV> struct ReconZ {
+  static constexpr auto fn = k_recon_z<NU, NV>;
+};
+
+hipError_t launch_recon_z(const Geom& g, const float* X, const CoreView& cv, double* wg_out,
+                          int max_wg, int* nwg, hipStream_t st) {
+  *nwg = 0;
+  const MttkrpPlan p = plan_mttkrp(g, F32, 0, true);
+  ZArgs z;
+  const int64_t mg = (g.In + 63) / 64;
+  if (!p.zform || (int64_t)p.nsplit * mg > max_wg || !make_zargs(g, p, cv, &z))
+    return hipErrorNotSupported;
+  const dim3 grid(p.nsplit, (unsigned)mg);
+  *nwg = (int)(p.nsplit * mg);
+  return launch_z<ReconZ>(z, grid, (size_t)2 * 64 * ZTP * sizeof(float), st, X, wg_out);
+}
+
+static hipError_t launch_mttkrp_z(const Geom& g, const MttkrpPlan& p, const float* X,
+                                  const CoreView& cv, float* part, hipStream_t st) {
+  ZArgs z;
+  if (!make_zargs(g, p, cv, &z)) return hipErrorInvalidValue;
+  const dim3 grid(p.nsplit, (unsigned)((g.In + 63) / 64));
+  return launch_z<MttkrpZ>(z, grid, (size_t)2 * 256 * ZKP * sizeof(float), st, X, part);
 }
 
 // ---------------------------------------------------------------------------
@@ -639,23 +1170,52 @@ hipError_t launch_gram_E(const double* G, int64_t rows, int Ra, int Rb, double* 
   return hipGetLastError();
 }
 
-// C = A * B (row-major FP64), one output per thread, 16x16 tiles through LDS.
+// C = A * B (row-major FP64) on FP64 MFMAs: one 16x16 output tile per
+// workgroup; wave w takes the w-th quarter of K (lane group g the k = 4j + g
+// of it), with its loads issued 8 k-steps at a time into two alternating
+// accumulators; the four wave sums are added in LDS in a fixed order.
 __global__ __launch_bounds__(256) void k_matmul(const double* __restrict__ A,
                                                 const double* __restrict__ B,
                                                 double* __restrict__ C, int d1, int d2, int d3) {
-  __shared__ double As[16][17], Bs[16][17];
-  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
-  const int row = blockIdx.y * 16 + ty, col = blockIdx.x * 16 + tx;
-  double s = 0.0;
-  for (int k0 = 0; k0 < d2; k0 += 16) {
-    As[ty][tx] = (row < d1 && k0 + tx < d2) ? A[(size_t)row * d2 + k0 + tx] : 0.0;
-    Bs[ty][tx] = (k0 + ty < d2 && col < d3) ? B[(size_t)(k0 + ty) * d3 + col] : 0.0;
-    __syncthreads();
+  __shared__ double red[3][256];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int l16 = lane & 15, g4 = lane >> 4;
+  const int r0 = blockIdx.y * 16, c0 = blockIdx.x * 16;
+  const int kw = ((d2 + 15) / 16) * 4;      // k per wave, a multiple of 4
+  const int kb = wave * kw;
+  const int arow = r0 + l16 < d1 ? r0 + l16 : d1 - 1;
+  const int bcol = c0 + l16 < d3 ? c0 + l16 : d3 - 1;
+  const bool rok = r0 + l16 < d1, cok = c0 + l16 < d3;
+  d4 acc[2] = {d4{0, 0, 0, 0}, d4{0, 0, 0, 0}};
+  for (int j0 = 0; j0 < kw / 4; j0 += 8) {
+    double av[8], bv[8];
 #pragma unroll
-    for (int k = 0; k < 16; ++k) s += As[ty][k] * Bs[k][tx];
-    __syncthreads();
+    for (int u = 0; u < 8; ++u) {
+      const int k = kb + 4 * (j0 + u) + g4;
+      const bool ok = j0 + u < kw / 4 && k < d2;
+      const int kc = k < d2 ? k : d2 - 1;
+      const double a = A[(size_t)arow * d2 + kc], b = B[(size_t)kc * d3 + bcol];
+      av[u] = ok && rok ? a : 0.0;
+      bv[u] = ok && cok ? b : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) acc[u & 1] = mfma16(av[u], bv[u], acc[u & 1]);
   }
-  if (row < d1 && col < d3) C[(size_t)row * d3 + col] = s;
+  d4 s = acc[0] + acc[1];
+  if (wave > 0) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) red[wave - 1][v * 64 + lane] = s[v];
+  }
+  __syncthreads();
+  if (wave == 0) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const double t = ((s[v] + red[0][v * 64 + lane]) + red[1][v * 64 + lane]) +
+                       red[2][v * 64 + lane];
+      const int row = r0 + Acc<double>::row(lane, v), col = c0 + l16;
+      if (row < d1 && col < d3) C[(size_t)row * d3 + col] = t;
+    }
+  }
 }
 
 // Transfer layout of a Gram tensor given in the paper's layout: Z of size
@@ -2124,8 +2684,11 @@ __global__ void k_cast(const void* src, int sdt, void* dst, int ddt, int64_t n) 
     if (sdt == F64 && ddt == F32) {
       ((float*)dst)[i] = (float)((const double*)src)[i];
     } else if (ddt == BF16) {
-      const float f = sdt == F64 ? (float)((const double*)src)[i] : ((const float*)src)[i];
-      ((__hip_bfloat16*)dst)[i] = __float2bfloat16(f);
+      // FP64 data is rounded to bfloat16 once, not through FP32
+      if (sdt == F64)
+        ((uint16_t*)dst)[i] = bf16_bits_rne(((const double*)src)[i]);
+      else
+        ((__hip_bfloat16*)dst)[i] = __float2bfloat16(((const float*)src)[i]);
     } else if (ddt == F64) {
       ((double*)dst)[i] = load_as_double(src, sdt, i);
     } else if (ddt == F32) {

@@ -19,6 +19,8 @@
 
 #include <hip/hip_runtime.h>
 #include <hip/hip_bf16.h>
+
+#include "bf16_round.h"
 #include <stdint.h>
 
 #include "tr_internal.h"
@@ -88,7 +90,7 @@ __device__ inline TM from_double(double x) {
 }
 template <>
 __device__ inline __bf16 from_double<__bf16>(double x) {
-  return (__bf16)(float)x;
+  return __builtin_bit_cast(__bf16, bf16_bits_rne(x));
 }
 
 // cos / sin of 2 pi r / I for the integer r = (a b) mod I.

@@ -1714,6 +1714,8 @@ WsLayout ws_layout(int32_t N, const int64_t* dims, const int32_t* ranks, int32_t
     Geom g = make_geom(N, dims, ranks, k);
     MttkrpPlan p = plan_mttkrp(g, dt);
     partmax = std::max(partmax, mttkrp_partial_bytes(g, p));
+    MttkrpPlan pb = plan_mttkrp(g, dt, 0, true);   // the fit-loss gradients' plan
+    partmax = std::max(partmax, mttkrp_partial_bytes(g, pb));
   }
   w.chain0 = take((size_t)emax * emax * 8);
   w.chain1 = take((size_t)emax * emax * 8);
@@ -1927,15 +1929,21 @@ tr_status tr_fit_loss_fwd(int32_t N, const int64_t* dims, const int32_t* ranks, 
   char* base = (char*)ws;
   Geom g = make_geom(N, dims, ranks, N - 1);
   CoreView cv = colmajor_view(N, dims, ranks, cores);
-  // the temporal core as slice-major FP64 rows for the MFMA product
-  double* gns = (double*)(base + w.slices[N - 1]);
-  const int RaN = ranks[N - 1], RbN = ranks[0];
-  if (launch_core_to_slices(cores[N - 1], dt, 1, RaN, (int64_t)RaN * dims[N - 1], dims[N - 1], RaN,
-                            RbN, gns, st) != hipSuccess)
-    return TR_ERR_DEVICE;
   int nwg = 0;
-  if (launch_recon_err(g, X, dt, cv, dt, gns, (double*)(base + w.wg), &nwg, st) != hipSuccess)
-    return TR_ERR_DEVICE;
+  hipError_t e = hipErrorNotSupported;
+  if (dt == TR_F32)
+    e = launch_recon_z(g, (const float*)X, cv, (double*)(base + w.wg), recon_err_blocks(g), &nwg,
+                       st);
+  if (e == hipErrorNotSupported) {
+    // the temporal core as slice-major FP64 rows for the MFMA product
+    double* gns = (double*)(base + w.slices[N - 1]);
+    const int RaN = ranks[N - 1], RbN = ranks[0];
+    if (launch_core_to_slices(cores[N - 1], dt, 1, RaN, (int64_t)RaN * dims[N - 1], dims[N - 1],
+                              RaN, RbN, gns, st) != hipSuccess)
+      return TR_ERR_DEVICE;
+    e = launch_recon_err(g, X, dt, cv, dt, gns, (double*)(base + w.wg), &nwg, st);
+  }
+  if (e != hipSuccess) return TR_ERR_DEVICE;
   if (launch_sum_pairs((double*)(base + w.wg), nwg, (double*)(base + w.pair), st) != hipSuccess)
     return TR_ERR_DEVICE;
   hipLaunchKernelGGL(k_half_loss, dim3(1), dim3(64), 0, st, (const double*)(base + w.pair),
@@ -1958,7 +1966,7 @@ tr_status tr_fit_loss_bwd(int32_t N, const int64_t* dims, const int32_t* ranks, 
     tr_status c = gram_chain_into(N, dims, ranks, dt, n, cores, Q, base, w, st, n > 0);
     if (c != TR_OK) return c;
     Geom g = make_geom(N, dims, ranks, n);
-    MttkrpPlan p = plan_mttkrp(g, dt);
+    MttkrpPlan p = plan_mttkrp(g, dt, 0, true);
     if (launch_mttkrp(g, p, X, dt, cv, dt, base + w.part, st) != hipSuccess) return TR_ERR_DEVICE;
     if (launch_reduce_solve(base + w.part, p.psize, p.nsplit, g.In, g.d, P, 0, nullptr, nullptr,
                             st) != hipSuccess)

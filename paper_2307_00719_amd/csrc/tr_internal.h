@@ -50,10 +50,14 @@ struct MttkrpPlan {
   int64_t Kout;    // number of outer indices
   int64_t upw;     // outer indices per workgroup
   int64_t sf, sm;  // X strides of i_f and of the row index i_n
+  int zform;       // 1: subchain blocks formed per outer index in LDS (FP32,
+                   // order <= 4, ranks <= 16, I_f <= 64; 64 rows per workgroup)
 };
 
 // max_wg > 0 caps the workgroup count (nsplit * mtiles) at about max_wg.
-MttkrpPlan plan_mttkrp(const Geom& g, int xdtype, int max_wg = 0);
+// bulk: allow the formed-subchain kernel for FP32 operands over many outer
+// indices (FP32 accumulation across the chunk).
+MttkrpPlan plan_mttkrp(const Geom& g, int xdtype, int max_wg = 0, bool bulk = false);
 size_t mttkrp_partial_bytes(const Geom& g, const MttkrpPlan& p);
 
 // ---- launchers (all asynchronous on `st`) --------------------------------
@@ -151,6 +155,12 @@ hipError_t launch_cast(const void* src, int sdt, void* dst, int ddt, int64_t n, 
 hipError_t launch_recon_err(const Geom& gN, const void* X, int xdt, const CoreView& cv,
                             int cdt, const double* GNs, double* wg_out, int* nwg_out,
                             hipStream_t st);
+// Sum of squared residuals and of X^2 for FP32 data and cores through the
+// formed-subchain blocks (orders <= 4, ranks <= 16, I_f <= 64): one pair per
+// workgroup into wg_out (at most max_wg pairs).  hipErrorNotSupported when
+// the shape does not qualify (nothing launched).
+hipError_t launch_recon_z(const Geom& g, const float* X, const CoreView& cv, double* wg_out,
+                          int max_wg, int* nwg, hipStream_t st);
 int recon_err_blocks(const Geom& gN);
 
 // out[0..1] = fixed-order sums of the pairs in wg_out.

@@ -120,3 +120,25 @@ def test_mttkrp_and_gram_chain_entry_points(trlib, dt, dims, ranks):
         eq = max(dev(Q.cpu().numpy(), Qr), dev(Q2.cpu().numpy(), 2 * Qr))
         print(f"[mttkrp {dims} n={n} {dt}] P {ep:.2e} Q {eq:.2e}", flush=True)
         assert ep < tol and eq < 1e-12
+
+
+@pytest.mark.parametrize("dims,ranks", [((37, 45, 24, 25), (5, 7, 3, 6)),
+                                        ((50, 64, 600), (4, 6, 5))])
+def test_fitloss_f32_bulk_shapes(trlib, dims, ranks):
+    """FP32 gradients through the formed-subchain MTTKRP (order <= 4, ranks
+    <= 16, I_f <= 64, at least 512 outer indices per 64-row group): ragged
+    row counts (37, 45, 24, 25; 600 = 9 full 64-row groups + 24), I_f below
+    64 (40-ish fast modes zero padded), unequal ranks, and every chain shape
+    of orders 3 and 4 (U only, V only, both, two factors on one side).
+    Loss within 1e-5 relative, gradients within 1e-4 (parity.dev)."""
+    import torch
+    cores, X = W.random_tr_problem(dims, ranks, 9, noise=0.3)
+    pt = [G + 0.1 * np.random.default_rng(5).standard_normal(G.shape) for G in cores]
+    loss, grads = _run(trlib, X, pt, torch.float32)
+    ref_loss = fitloss.fit_loss(X, pt)
+    ref = fitloss.grad_normal_eq(X, pt)
+    devs = [dev(g, r) for g, r in zip(grads, ref)]
+    print(f"[fitloss bulk {dims}] loss rel {abs(loss - ref_loss) / ref_loss:.2e} grads {devs}",
+          flush=True)
+    assert abs(loss - ref_loss) <= 1e-5 * ref_loss
+    assert max(devs) < 1e-4
