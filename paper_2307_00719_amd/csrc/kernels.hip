@@ -2476,6 +2476,55 @@ __device__ inline bool gram_arrive(unsigned* counter, unsigned total, int tid) {
   return true;
 }
 
+// One 16 x 16 tile of the sketched product (SideArgs::Pout) on a 16-wave
+// workgroup: wave w takes the k-steps w, w + 16, .. (4 samples each), 8 of
+// them with their loads in flight, on FP64 MFMAs; the wave sums are added in
+// LDS in a fixed order.
+__device__ inline void sketch_ptile(const SideArgs& sa, double* lds, int tid, int pt) {
+  constexpr int NW = 16, KB = 8;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
+  const int ar = lane & 15, ak = lane >> 4;
+  const int dp = sa.Rpa * sa.Rpb, nbp = (dp + 15) >> 4;
+  const int rb = pt / nbp, cb = pt - rb * nbp;
+  const int64_t rows = sa.rows_p, rl = rows > 0 ? rows - 1 : 0;
+  const int64_t nks = (rows + 3) / 4;
+  const bool rok = rb * 16 + ar < sa.pIn;
+  const int64_t irow = rok ? rb * 16 + ar : sa.pIn - 1;
+  const int col = min(cb * 16 + ar, dp - 1);
+  d4 acc = {0, 0, 0, 0};
+  for (int64_t k0 = wave; k0 < nks; k0 += KB * NW) {
+    double av[KB], bv[KB];
+#pragma unroll
+    for (int q = 0; q < KB; ++q) {
+      const int64_t ks = k0 + NW * q;
+      const int64_t smp = ks * 4 + ak;
+      const int64_t sc = smp < rows ? smp : rl;
+      int64_t off = irow * sa.xsn;
+      for (int p = 0; p < sa.xN; ++p)
+        if (p != sa.xn) off += (int64_t)sa.idxs[(size_t)p * sa.im + sc] * sa.xstride[p];
+      const double xa = sa.xdt == F32 ? (double)((const float*)sa.Xs)[off]
+                                      : ((const double*)sa.Xs)[off];
+      const double xb = sa.Gp[sc * dp + col] * (sa.Gw ? sa.Gw[sc] : 1.0);
+      const bool ok = smp < rows && ks < nks;
+      av[q] = ok && rok ? xa : 0.0;
+      bv[q] = ok ? xb : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < KB; ++q) acc = mfma16(av[q], bv[q], acc);
+  }
+#pragma unroll
+  for (int v = 0; v < 4; ++v) lds[wave * 256 + Acc<double>::row(lane, v) * 16 + ar] = acc[v];
+  __syncthreads();
+  if (tid < 256) {
+    double sum = 0.0;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) sum += lds[w * 256 + tid];
+    const int64_t r = rb * 16 + (tid >> 4);
+    const int c = cb * 16 + (tid & 15);
+    if (r < sa.pIn && c < dp) sa.Pout[r * dp + c] = sum;
+  }
+}
+
 template <int MAXT>
 __global__ __launch_bounds__(1024) void k_side_mf(SideArgs sa) {
   extern __shared__ double lds[];
@@ -2485,13 +2534,21 @@ __global__ __launch_bounds__(1024) void k_side_mf(SideArgs sa) {
   const int ar = lane & 15, ak = lane >> 4;
   // 1. Gram of the previous core, spread over the grid (one upper-triangle
   //    tile per workgroup); the last workgroup to finish goes on with the
-  //    chain, Q and the inverse while the others exit.
+  //    chain, Q and the inverse while the others exit.  The workgroups past
+  //    the Gram tiles form the sketched product's tiles, which nothing in
+  //    this launch reads.
   if (sa.Gp) {
+    const int nbp = (sa.Rpa * sa.Rpb + 15) >> 4;
+    const int ngram = nbp * (nbp + 1) / 2;
+    if ((int)blockIdx.x >= ngram) {
+      sketch_ptile(sa, lds, tid, blockIdx.x - ngram);
+      return;
+    }
     if (sa.Gw)
       gram_tile<16, true>(sa, lds, tid, blockIdx.x);
     else
       gram_tile<16>(sa, lds, tid, blockIdx.x);
-    if (!gram_arrive(sa.counter, gridDim.x, tid)) return;
+    if (!gram_arrive(sa.counter, (unsigned)ngram, tid)) return;
   }
   side_serial<16, MAXT>(sa, lds, dmax, tid);
 }
@@ -2633,6 +2690,7 @@ static hipError_t launch_side_mf(const SideArgs& a, int nb, hipStream_t st) {
   if (a.Gp) {
     const int nbp = (a.Rpa * a.Rpb + 15) / 16;
     grid = (unsigned)(nbp * (nbp + 1) / 2);
+    if (a.Pout) grid += (unsigned)(((a.pIn + 15) / 16) * nbp);
   }
   hipLaunchKernelGGL(fn, dim3(grid), dim3(1024), lds, st, a);
   return hipGetLastError();
@@ -2643,6 +2701,8 @@ hipError_t launch_side(const SideArgs& a, hipStream_t st) {
   if (d > 256) return hipErrorInvalidValue;
   const int nb = (d + 15) / 16;
   static const bool scalar_gj = getenv("TRSTREAM_SCALAR_GJ") != nullptr;
+  // the sketched product tiles exist in the 16-wave kernel only
+  if (a.Pout && (nb > 12 || scalar_gj || !a.Gp || a.pIn < 1)) return hipErrorInvalidValue;
   if (nb <= 12 && !scalar_gj) {
     // 16 waves over the nb (nb + 1) / 2 upper-triangle tiles
     const int ntri = nb * (nb + 1) / 2;

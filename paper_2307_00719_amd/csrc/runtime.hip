@@ -339,9 +339,17 @@ int64_t prod_dims_except(const tr_stream* s, int skip) {
 
 // Leverage distribution (Lemma on leverage estimation) of `rows` slice-major
 // rows of core k into p.
+// The sketched product P = X_S W A of mode g.n, formed beside the Gram of
+// the same sampled rows A (weights W) by the side kernel (d <= 192).
+struct SketchProduct {
+  const Geom* g;
+  const void* X;
+  double* P;
+};
 tr_status gram_update_invert(tr_stream* s, hipStream_t on, double* M, int Ra, int Rb, double* Q,
                              int accumulate, double* Qinv, const double* A = nullptr,
-                             const double* w = nullptr, int64_t rows = 0);
+                             const double* w = nullptr, int64_t rows = 0,
+                             const SketchProduct* sp = nullptr);
 
 tr_status leverage_probs(tr_stream* s, int k, const double* rows, int64_t I, double* p) {
   const int Ra = s->R[k], Rb = s->R[(k + 1) % s->N], d = Ra * Rb;
@@ -404,8 +412,9 @@ tr_status ensure_temporal_probs(tr_stream* s, int64_t t) {
 // inverse), else by the weighted-Gram kernel.  Launched on stream `on`.
 tr_status gram_update_invert(tr_stream* s, hipStream_t on, double* M, int Ra, int Rb, double* Q,
                              int accumulate, double* Qinv, const double* A, const double* w,
-                             int64_t rows) {
+                             int64_t rows, const SketchProduct* sp) {
   const int d = Ra * Rb;
+  if (sp && (d > 192 || !A)) return poison(s, TR_ERR_UNSUPPORTED, "sketched product tiles");
   if (d <= 192) {
     SideArgs a;
     std::memset(&a, 0, sizeof(a));
@@ -416,6 +425,23 @@ tr_status gram_update_invert(tr_stream* s, hipStream_t on, double* M, int Ra, in
       a.Rpa = d;
       a.Rpb = 1;
       a.Ep = M;
+    }
+    if (sp) {
+      const Geom& g = *sp->g;
+      a.Pout = sp->P;
+      a.Xs = sp->X;
+      a.xdt = s->dt;
+      a.xN = g.N;
+      a.xn = g.n;
+      a.im = (int)s->m;
+      a.idxs = s->idxs;
+      a.pIn = g.In;
+      int64_t acc = 1;
+      for (int q = 0; q < g.N; ++q) {
+        a.xstride[q] = acc;
+        acc *= g.I[q];
+      }
+      a.xsn = a.xstride[g.n];
     }
     a.nfac = 1;
     a.fac[0] = M;
@@ -475,6 +501,18 @@ tr_status sketch_increment(tr_stream* s, int n, const void* Xd, int64_t t, const
   const bool lev = s->sketch == TR_SKETCH_LEVERAGE && s->rescale;
   TR_HIP(launch_sample_rows(g, cv, s->idxs, m, lev ? (const double* const*)s->dprobs : nullptr,
                             wconst, s->SA, s->Sw, s->st));
+  if (g.d <= 192) {
+    // the product's tiles ride in the side kernel beside the Gram
+    TR_HIP(ensure(&s->part, &s->part_bytes, (size_t)g.In * g.d * 8));
+    const SketchProduct spp = {&g, Xd, (double*)s->part};
+    tr_status c = gram_update_invert(s, s->st, s->Zb, s->R[n], s->R[(n + 1) % N], s->Q[n],
+                                     accumulate, Minv_solve ? s->Minv : nullptr, s->SA, s->Sw, m,
+                                     &spp);
+    if (c != TR_OK) return c;
+    TR_HIP(launch_reduce_solve(s->part, 8, 1, g.In, g.d, s->P[n], accumulate,
+                               Minv_solve ? s->Minv : nullptr, s->G[n], s->st));
+    return TR_OK;
+  }
   SketchPlan sp = plan_sketch(g, m, s->dt);
   const size_t pb = (size_t)sp.nsplit * g.In * g.d * sp.psize;
   TR_HIP(ensure(&s->part, &s->part_bytes, pb));
@@ -527,14 +565,24 @@ tr_status sketch_update(tr_stream* s, const void* Xd, int64_t t_new, double* Gne
     const bool lev = s->sketch == TR_SKETCH_LEVERAGE && s->rescale;
     TR_HIP(launch_sample_rows(g, cv, s->idxs, m, lev ? (const double* const*)s->dprobs : nullptr,
                               wconst, s->SA, s->Sw, s->st));
-    SketchPlan sp = plan_sketch(g, m, s->dt);
-    TR_HIP(ensure(&s->part, &s->part_bytes, (size_t)sp.nsplit * g.In * g.d * sp.psize));
-    tr_status c0 = gram_update_invert(s, s->st, s->Zb, s->R[N - 1], s->R[0], nullptr, 0, s->Minv,
-                                      s->SA, s->Sw, m);
-    if (c0 != TR_OK) return c0;
-    TR_HIP(launch_sketch_gemm(g, sp, Xd, s->dt, s->idxs, m, s->SA, s->Sw, s->part, s->st));
-    TR_HIP(launch_reduce_solve(s->part, sp.psize, sp.nsplit, g.In, g.d, nullptr, 0, s->Minv, Gnew,
-                               s->st));
+    if (g.d <= 192) {
+      // the product's tiles ride in the side kernel beside the Gram
+      TR_HIP(ensure(&s->part, &s->part_bytes, (size_t)g.In * g.d * 8));
+      const SketchProduct spp = {&g, Xd, (double*)s->part};
+      tr_status c0 = gram_update_invert(s, s->st, s->Zb, s->R[N - 1], s->R[0], nullptr, 0,
+                                        s->Minv, s->SA, s->Sw, m, &spp);
+      if (c0 != TR_OK) return c0;
+      TR_HIP(launch_reduce_solve(s->part, 8, 1, g.In, g.d, nullptr, 0, s->Minv, Gnew, s->st));
+    } else {
+      SketchPlan sp = plan_sketch(g, m, s->dt);
+      TR_HIP(ensure(&s->part, &s->part_bytes, (size_t)sp.nsplit * g.In * g.d * sp.psize));
+      tr_status c0 = gram_update_invert(s, s->st, s->Zb, s->R[N - 1], s->R[0], nullptr, 0,
+                                        s->Minv, s->SA, s->Sw, m);
+      if (c0 != TR_OK) return c0;
+      TR_HIP(launch_sketch_gemm(g, sp, Xd, s->dt, s->idxs, m, s->SA, s->Sw, s->part, s->st));
+      TR_HIP(launch_reduce_solve(s->part, sp.psize, sp.nsplit, g.In, g.d, nullptr, 0, s->Minv,
+                                 Gnew, s->st));
+    }
   }
   tr_status c;
   if (s->sketch == TR_SKETCH_LEVERAGE) {

@@ -130,6 +130,16 @@ struct SideArgs {
   int* status;         // [0] failure flag, [2] fallback count, [3] this solve fell back
   unsigned* counter;   // arrival counter of the Gram workgroups (zero between launches)
   double* pw;          // 2 d^2 + d doubles of scratch for the pseudo-inverse fallback
+  // Sketched product tiles beside the Gram tiles (k_side_mf; none when Pout
+  // is null): Pout[i * d + c] = sum_s Gw[s] X[xoff(s) + i * xsn] Gp[s * d + c]
+  // over the rows_p samples for i < pIn, in FP64, with
+  // xoff(s) = sum_{q != xn} idxs[q * im + s] * xstride[q] over the xN modes.
+  double* Pout;
+  const void* Xs;
+  int xdt, xN, xn, im;
+  const int* idxs;
+  int64_t pIn, xsn;
+  int64_t xstride[MAXN];
 };
 hipError_t launch_side(const SideArgs& a, hipStream_t st);
 
