@@ -2562,6 +2562,25 @@ __global__ __launch_bounds__(1024) void k_side_mf(SideArgs sa) {
 // other writes, and no workgroup waits for another; the split reduction and
 // solve follow on the same stream.
 // ---------------------------------------------------------------------------
+// MTTKRP workgroup w (of nw) of the fused launch -> (chunk, row tile).
+// Workgroups go to the 8 XCDs round robin, so w and w + 8 share an XCD and
+// its L2: with an even number of row tiles those two take row tiles 2k and
+// 2k + 1 of one chunk, whose rows are adjacent in X when the row index is
+// the unit-stride one (16 FP32 rows fill half of a 128-byte line, which the
+// pair then fetches once).  A last incomplete group of 16 keeps the plain
+// order.
+__device__ inline void mode_tile(int w, int nw, int nsplit, int mtiles, int* chunk, int* mtile) {
+  if (mtiles & 1) {
+    *chunk = w % nsplit;
+    *mtile = w / nsplit;
+    return;
+  }
+  const int unit = w < (nw & ~15) ? (w & ~15) + 2 * (w & 7) + ((w >> 3) & 1) : w;
+  const int pr = unit >> 1;
+  *chunk = pr % nsplit;
+  *mtile = 2 * (pr / nsplit) + (unit & 1);
+}
+
 template <typename T, typename TC, int NJ, int MAXT>
 __global__ __launch_bounds__(256, 2) void k_mode(Geom g, MttkrpPlan p, const T* __restrict__ X,
                                                  CoreView cv,
@@ -2589,8 +2608,9 @@ __global__ __launch_bounds__(256, 2) void k_mode(Geom g, MttkrpPlan p, const T* 
     side_serial<4, MAXT>(sa, lds, dmax, threadIdx.x, pre);
     return;
   }
-  const int w = blockIdx.x - ngram;
-  mttkrp_body<T, TC, NJ>(g, p, X, cv, part, w % p.nsplit, w / p.nsplit, smem);
+  int chunk, mtile;
+  mode_tile(blockIdx.x - ngram, gridDim.x - ngram, p.nsplit, p.mtiles, &chunk, &mtile);
+  mttkrp_body<T, TC, NJ>(g, p, X, cv, part, chunk, mtile, smem);
 }
 
 bool mode_fusable(const Geom& g, const SideArgs& sa) {
