@@ -161,12 +161,16 @@ MttkrpPlan plan_mttkrp(const Geom& g, int xdtype, int max_wg, bool bulk) {
     bool small = N <= 4;
     for (int k = 0; k < N; ++k) small = small && g.R[k] <= 16;
     // one 8-wave workgroup per CU (its two Z buffers take 136 KiB of LDS):
-    // about 256 workgroups of 64 rows, at least two outer indices each
-    const int64_t mg = (g.In + 63) / 64;
+    // about 256 workgroups (fewer under max_wg) of 64 rows, or of 32 or 16
+    // when I_n is that small, at least two outer indices each
+    const int rows_wg = g.In <= 16 ? 16 : (g.In <= 32 ? 32 : 64);
+    const int64_t mg = (g.In + rows_wg - 1) / rows_wg;
     int64_t zc = 256 / mg;
+    if (max_wg > 0 && zc > max_wg / mg) zc = max_wg / mg;
     if (zc < 1) zc = 1;
     if (small && p.Kout >= 2 * zc) {
       p.zform = 1;
+      p.MT = rows_wg;
       p.upw = (p.Kout + zc - 1) / zc;
       p.nsplit = (int)((p.Kout + p.upw - 1) / p.upw);
     }
@@ -547,9 +551,10 @@ hipError_t launch_mttkrp(const Geom& g, const MttkrpPlan& p, const void* X, int 
 // MFMA accumulators across the chunk.  Z of the next outer index is formed
 // while the current one is used (two LDS buffers, one barrier per outer
 // index); the X operands and core slices are loaded one outer index ahead.
-// Workgroup: 8 waves over rows [64 y, 64 y + 64); wave w owns row tile w % 4
-// and the column tiles s in [8 (w / 4), 8 (w / 4) + 8), and forms Z for
-// i_f in [8 w, 8 w + 8).  K order of the main product: lane group g of
+// Workgroup: 8 waves over the 16 MT4 rows [16 MT4 y, 16 MT4 (y + 1)) (MT4 =
+// 4, 2 or 1 row tiles by I_n: the Z blocks cost the same for any number of
+// rows); wave w owns row tile w % MT4 and the 2 MT4 column tiles from
+// 2 MT4 (w / MT4), and forms Z for i_f in [8 w, 8 w + 8).  K order of the main product: lane group g of
 // k-step q takes i_f = 16 g + q, so the 16 Z operands of a lane in one
 // column tile are one contiguous LDS row.
 // Layout facts used (16x16x4 FP32 MFMA): the accumulator register v of lane
@@ -685,16 +690,17 @@ struct ZLane {
   }
 };
 
-template <int NU, int NV>
+template <int NU, int NV, int MT4>
 __global__ __launch_bounds__(512, 1) void k_mttkrp_z(ZArgs z, const float* __restrict__ X,
                                                      float* __restrict__ part) {
   typedef ZLane<NU, NV> ZL;
+  constexpr int NT = 2 * MT4;             // column tiles per wave
   extern __shared__ __align__(16) float zl[];            // [2][256][ZKP]
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int l16 = lane & 15, g4 = lane >> 4;
-  const int mt = wave & 3, sh = wave >> 2;
-  const int row = blockIdx.y * 64 + mt * 16 + l16;
+  const int mt = wave % MT4, tb = (wave / MT4) * NT;
+  const int row = blockIdx.y * 16 * MT4 + mt * 16 + l16;
   const int arow = (row < z.In ? row : z.In - 1) * z.sm;
   const int o0 = blockIdx.x * z.upw;
   const int o1 = o0 + z.upw < z.Kout ? o0 + z.upw : z.Kout;
@@ -729,9 +735,9 @@ __global__ __launch_bounds__(512, 1) void k_mttkrp_z(ZArgs z, const float* __res
     }
   };
 
-  f4 acc[8];
+  f4 acc[NT];
 #pragma unroll
-  for (int t = 0; t < 8; ++t) acc[t] = f4{0, 0, 0, 0};
+  for (int t = 0; t < NT; ++t) acc[t] = f4{0, 0, 0, 0};
   f4 slr[ZL::NS];
   f4 ut = {0, 0, 0, 0}, vv = {0, 0, 0, 0};
   float xa[16], xb[16];
@@ -752,18 +758,18 @@ __global__ __launch_bounds__(512, 1) void k_mttkrp_z(ZArgs z, const float* __res
     load_x(on, xl);
     zc.load(z, on2, slr);
     zform((j + 1) & 1, ut, vv);
-    const float* zb = zl + (j & 1) * (256 * ZKP) + ((8 * sh) * 16 + l16) * ZKP + 16 * g4;
-    // every column tile, valid or not (Z is zero beyond R_{n+1}); the eight
+    const float* zb = zl + (j & 1) * (256 * ZKP) + (tb * 16 + l16) * ZKP + 16 * g4;
+    // every column tile, valid or not (Z is zero beyond R_{n+1}); the
     // accumulators take turns so consecutive MFMAs are independent
 #pragma unroll
     for (int qb = 0; qb < 4; ++qb) {
-      f4 b[8];
+      f4 b[NT];
 #pragma unroll
-      for (int t = 0; t < 8; ++t) b[t] = *(const f4*)(zb + t * 16 * ZKP + 4 * qb);
+      for (int t = 0; t < NT; ++t) b[t] = *(const f4*)(zb + t * 16 * ZKP + 4 * qb);
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
 #pragma unroll
-        for (int t = 0; t < 8; ++t) acc[t] = mfma16(xu[4 * qb + u], b[t][u], acc[t]);
+        for (int t = 0; t < NT; ++t) acc[t] = mfma16(xu[4 * qb + u], b[t][u], acc[t]);
       }
     }
     __syncthreads();
@@ -773,14 +779,14 @@ __global__ __launch_bounds__(512, 1) void k_mttkrp_z(ZArgs z, const float* __res
     if (j + 1 < cnt) step(j + 1, xb, xa);
   }
   // this chunk's partial: acc[t] register v of lane (r, g) = row 4 g + v of
-  // the row tile, column r of column tile s = 8 sh + t
+  // the row tile, column r of column tile s = tb + t
 #pragma unroll
-  for (int t = 0; t < 8; ++t) {
-    const int sc = 8 * sh + t;
+  for (int t = 0; t < NT; ++t) {
+    const int sc = tb + t;
     if (sc < z.Rn1 && l16 < z.Rn) {
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int m = blockIdx.y * 64 + mt * 16 + 4 * g4 + v;
+        const int m = blockIdx.y * 16 * MT4 + mt * 16 + 4 * g4 + v;
         if (m < z.In)
           part[((size_t)blockIdx.x * z.In + m) * z.d + l16 + z.Rn * sc] = acc[t][v];
       }
@@ -1016,8 +1022,10 @@ static hipError_t launch_z(const ZArgs& z, dim3 grid, size_t lds, hipStream_t st
   hipLaunchKernelGGL(fn, grid, dim3(512), lds, st, z, args...);
   return hipGetLastError();
 }
-template <int NU, int NV> struct MttkrpZ {
-  static constexpr auto fn = k_mttkrp_z<NU, NV>;
+template <int MT4> struct MttkrpZT {
+  template <int NU, int NV> struct K {
+    static constexpr auto fn = k_mttkrp_z<NU, NV, MT4>;
+  };
 };
 template <int NU, int NV> struct ReconZ {
   static constexpr auto fn = k_recon_z<NU, NV>;
@@ -1029,7 +1037,7 @@ hipError_t launch_recon_z(const Geom& g, const float* X, const CoreView& cv, dou
   const MttkrpPlan p = plan_mttkrp(g, F32, 0, true);
   ZArgs z;
   const int64_t mg = (g.In + 63) / 64;
-  if (!p.zform || (int64_t)p.nsplit * mg > max_wg || !make_zargs(g, p, cv, &z))
+  if (!p.zform || p.MT != 64 || (int64_t)p.nsplit * mg > max_wg || !make_zargs(g, p, cv, &z))
     return hipErrorNotSupported;
   const dim3 grid(p.nsplit, (unsigned)mg);
   *nwg = (int)(p.nsplit * mg);
@@ -1040,8 +1048,14 @@ static hipError_t launch_mttkrp_z(const Geom& g, const MttkrpPlan& p, const floa
                                   const CoreView& cv, float* part, hipStream_t st) {
   ZArgs z;
   if (!make_zargs(g, p, cv, &z)) return hipErrorInvalidValue;
-  const dim3 grid(p.nsplit, (unsigned)((g.In + 63) / 64));
-  return launch_z<MttkrpZ>(z, grid, (size_t)2 * 256 * ZKP * sizeof(float), st, X, part);
+  const dim3 grid(p.nsplit, (unsigned)((g.In + p.MT - 1) / p.MT));
+  const size_t lds = (size_t)2 * 256 * ZKP * sizeof(float);
+  switch (p.MT) {
+    case 16: return launch_z<MttkrpZT<1>::K>(z, grid, lds, st, X, part);
+    case 32: return launch_z<MttkrpZT<2>::K>(z, grid, lds, st, X, part);
+    case 64: return launch_z<MttkrpZT<4>::K>(z, grid, lds, st, X, part);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -1058,7 +1072,8 @@ __global__ __launch_bounds__(256) void k_reduce_solve(const PT* __restrict__ par
                                                       int64_t In, int d, double* P,
                                                       int accumulate,
                                                       const double* __restrict__ Minv,
-                                                      double* __restrict__ out) {
+                                                      double* __restrict__ out,
+                                                      float* __restrict__ out32) {
   extern __shared__ double sh[];                        // [4][d] wave sums, [d] row
   double* red = sh;
   double* prow = sh + 4 * d;
@@ -1104,13 +1119,16 @@ __global__ __launch_bounds__(256) void k_reduce_solve(const PT* __restrict__ par
     red[q * d + c2] = g0 + g1;
   }
   __syncthreads();
-  for (int c2 = threadIdx.x; c2 < d; c2 += 256)
-    out[(size_t)row * d + c2] = ((red[c2] + red[d + c2]) + red[2 * d + c2]) + red[3 * d + c2];
+  for (int c2 = threadIdx.x; c2 < d; c2 += 256) {
+    const double g = ((red[c2] + red[d + c2]) + red[2 * d + c2]) + red[3 * d + c2];
+    out[(size_t)row * d + c2] = g;
+    if (out32) out32[(size_t)row * d + c2] = (float)g;
+  }
 }
 
 hipError_t launch_reduce_solve(const void* part, int psize, int nsplit, int64_t In, int d,
                                double* P, int accumulate, const double* Minv, double* out,
-                               hipStream_t st) {
+                               hipStream_t st, float* out32) {
   if (In <= 0) return hipSuccess;
   if (In > 0x7fffffff || d <= 0) return hipErrorInvalidValue;
   dim3 grid((unsigned)In);
@@ -1118,10 +1136,10 @@ hipError_t launch_reduce_solve(const void* part, int psize, int nsplit, int64_t 
   if (lds > 65536) return hipErrorInvalidValue;
   if (psize == 8)
     hipLaunchKernelGGL(k_reduce_solve<double>, grid, dim3(256), lds, st, (const double*)part,
-                       nsplit, In, d, P, accumulate, Minv, out);
+                       nsplit, In, d, P, accumulate, Minv, out, out32);
   else
     hipLaunchKernelGGL(k_reduce_solve<float>, grid, dim3(256), lds, st, (const float*)part,
-                       nsplit, In, d, P, accumulate, Minv, out);
+                       nsplit, In, d, P, accumulate, Minv, out, out32);
   return hipGetLastError();
 }
 
@@ -1952,6 +1970,11 @@ constexpr int SIDE_LDS = 8448;
 // allocation: SIDE_LDS plus the spare slot that takes the staging copy's
 // out-of-range stores
 constexpr int SIDE_LDS_ALLOC = SIDE_LDS + 2;
+// The 16-wave side kernel has its compute unit to itself: its budget holds
+// both operands of a 100 x 100 x 100 chain product (order-4 streams with
+// TR-ranks 10), 158 KiB of the 160.
+constexpr int SIDE_LDS_MF = 20200;
+constexpr int SIDE_LDS_MF_ALLOC = SIDE_LDS_MF + 2;
 
 // Serial part of the side step, for a workgroup of NW waves: the ring
 // product of the transfer-layout factors, the Q tiles (assembly,
@@ -1961,6 +1984,8 @@ constexpr int SIDE_LDS_ALLOC = SIDE_LDS + 2;
 template <int NW, int MAXT>
 __device__ inline void side_serial(const SideArgs& sa, double* lds, double* dmax, int tid,
                                    bool pre = false) {
+  // LDS budget in doubles (the allocation has one spare slot past it)
+  constexpr int CAP = NW == 16 ? SIDE_LDS_MF : SIDE_LDS;
   // [0] some pivot test failed, [1] waves done (zeroed here; the barriers of
   // the chain product order this before any use)
   __shared__ int fb_rec[2];
@@ -2033,44 +2058,55 @@ __device__ inline void side_serial(const SideArgs& sa, double* lds, double* dmax
     const int nb1 = (d1 + 15) >> 4, nb3 = (d3 + 15) >> 4, ntile = nb1 * nb3;
     const int d2p = d2 + 1;
     const float rd2 = 1.0f / (float)d2, rnb3 = 1.0f / (float)nb3;
-    const bool staged = d1 * d2p + d2 * d3 <= SIDE_LDS;
+    const bool staged = d1 * d2p + d2 * d3 <= CAP;
     if (staged && pre && j == 1) {
       // M is already in LDS (loaded by prestage_first_factor while the Gram
       // tile was computed): copy F only
       const int n2 = d2 * d3;
-      constexpr int PER = (SIDE_LDS + 64 * NW - 1) / (64 * NW);
-      double x[PER];
+      constexpr int PER = (CAP + 64 * NW - 1) / (64 * NW);
+      constexpr int BATCH = NW == 16 ? 10 : PER;   // loads in flight per thread
+#pragma unroll 1
+      for (int q0 = 0; q0 < PER; q0 += BATCH) {
+        double x[BATCH];
 #pragma unroll
-      for (int q = 0; q < PER; ++q)
-        if (q * 64 * NW < n2) x[q] = coherent_load(F + min(tid + 64 * NW * q, n2 - 1));
+        for (int u = 0; u < BATCH; ++u) {
+          const int q = q0 + u;
+          if (q < PER && q * 64 * NW < n2) x[u] = coherent_load(F + min(tid + 64 * NW * q, n2 - 1));
+        }
 #pragma unroll
-      for (int q = 0; q < PER; ++q) {
-        const int e = tid + 64 * NW * q;
-        if (q * 64 * NW < n2) lds[e < n2 ? d1 * d2p + e : SIDE_LDS] = x[q];
+        for (int u = 0; u < BATCH; ++u) {
+          const int q = q0 + u;
+          const int e = tid + 64 * NW * q;
+          if (q < PER && q * 64 * NW < n2) lds[e < n2 ? d1 * d2p + e : CAP] = x[u];
+        }
       }
       __syncthreads();
     } else if (staged) {
       // [M (padded rows) | F] copied to LDS with all loads in flight at once:
       // one load per element (the source pointer is selected, both sources
       // clamped in range) and one unconditional LDS store (elements past the
-      // end go to the spare slot SIDE_LDS), so the copy has no branches
+      // end go to the spare slot CAP), so the copy has no branches
       const int n1 = d1 * d2, n2 = d2 * d3;
-      constexpr int PER = (SIDE_LDS + 64 * NW - 1) / (64 * NW);
-      double x[PER];
+      constexpr int PER = (CAP + 64 * NW - 1) / (64 * NW);
+      constexpr int BATCH = NW == 16 ? 10 : PER;   // loads in flight per thread
+#pragma unroll 1
+      for (int q0 = 0; q0 < PER; q0 += BATCH) {
+        double x[BATCH];
 #pragma unroll
-      for (int q = 0; q < PER; ++q) {
-        const int e = tid + 64 * NW * q;
-        const double* src = e < n1 ? M + min(e, n1 - 1) : F + min(max(e - n1, 0), n2 - 1);
-        x[q] = coherent_load(src);
-      }
+        for (int u = 0; u < BATCH; ++u) {
+          const int e = tid + 64 * NW * (q0 + u);
+          const double* src = e < n1 ? M + min(e, n1 - 1) : F + min(max(e - n1, 0), n2 - 1);
+          if (q0 + u < PER) x[u] = coherent_load(src);
+        }
 #pragma unroll
-      for (int q = 0; q < PER; ++q) {
-        const int e = tid + 64 * NW * q;
-        const int em = min(e, n1 - 1);
-        const int r = small_div(em, rd2);
-        const int dst = e < n1 ? r * d2p + (em - r * d2)
-                               : (e < n1 + n2 ? d1 * d2p + (e - n1) : SIDE_LDS);
-        lds[dst] = x[q];
+        for (int u = 0; u < BATCH; ++u) {
+          const int e = tid + 64 * NW * (q0 + u);
+          const int em = min(e, n1 - 1);
+          const int r = small_div(em, rd2);
+          const int dst = e < n1 ? r * d2p + (em - r * d2)
+                                 : (e < n1 + n2 ? d1 * d2p + (e - n1) : CAP);
+          if (q0 + u < PER) lds[dst] = x[u];
+        }
       }
       __syncthreads();
     }
@@ -2138,7 +2174,7 @@ __device__ inline void side_serial(const SideArgs& sa, double* lds, double* dmax
     };
     constexpr int RM = (16 + NW - 1) / NW;
     if (ntile <= NW * RM) {
-      const bool keep = j == sa.nfac - 1 && d1 * d3 <= SIDE_LDS;
+      const bool keep = j == sa.nfac - 1 && d1 * d3 <= CAP;
       d4 res[RM];
 #pragma unroll
       for (int t = 0; t < RM; ++t) {
@@ -2229,7 +2265,7 @@ __device__ inline void side_serial(const SideArgs& sa, double* lds, double* dmax
   //    i < K, ColT[i] = tile(i, K)^T and RowB[i] = -tile(i, K)^T.  The block
   //    updates below are those of the full elimination restricted to i <= j.
   const int bstride = 2 * nb * 256 + 512;
-  const bool dbuf = 2 * bstride <= SIDE_LDS;
+  const bool dbuf = 2 * bstride <= CAP;
   const int kq = lane >> 4, cl = lane & 15;
   for (int K = 0; K < nb; ++K) {
     double* Pb = lds + (dbuf ? (K & 1) * bstride : 0);
@@ -2699,7 +2735,7 @@ hipError_t launch_mode(const Geom& g, const MttkrpPlan& p, const void* X, int xd
 
 template <int MAXT>
 static hipError_t launch_side_mf(const SideArgs& a, int nb, hipStream_t st) {
-  const size_t lds = (size_t)SIDE_LDS_ALLOC * sizeof(double);
+  const size_t lds = (size_t)SIDE_LDS_MF_ALLOC * sizeof(double);
   auto fn = k_side_mf<MAXT>;
   if (lds > 65536) {
     hipError_t e = hipFuncSetAttribute((const void*)fn,

@@ -69,6 +69,10 @@ struct tr_stream {
   size_t xf64_bytes = 0;
   void* part = nullptr;
   size_t part_bytes = 0;
+  // FP32 copies of the cores (k < N-1) and of the new temporal rows (N-1)
+  // for the formed-subchain MTTKRP of the FP32-operand two-stream update
+  void* G32[MAXN] = {};
+  size_t G32_bytes[MAXN] = {};
   double* wg = nullptr;
   size_t wg_n = 0;
   double* pair = nullptr;
@@ -271,6 +275,15 @@ tr_status stage_batch(tr_stream* s, const void* X, int xdt, int64_t n, int x_is_
   TR_HIP(launch_cast(dsrc, xdt, s->xcast, s->dt, n, s->st));
   *out = s->xcast;
   return TR_OK;
+}
+
+// Workgroups of the formed-subchain MTTKRP in the two-stream update: the
+// side kernel sets the pace, so the split is sized for about 3.3 MB of
+// partials (fewer partials shorten the reduction after the side kernel),
+// between 64 and 256 workgroups.
+int stream_zwg(const Geom& g) {
+  const int64_t w = (int64_t)3300000 / (g.In * g.d * 4);
+  return (int)std::min<int64_t>(256, std::max<int64_t>(64, w));
 }
 
 tr_status ensure_partials(tr_stream* s, const Geom& g, const MttkrpPlan& p) {
@@ -1214,6 +1227,29 @@ tr_status str_pass(tr_stream* s, const void* Xd, int64_t t_new, double* Gnew) {
   // before it; Z_N^new for n = 0)
   TR_HIP(hipEventRecord(s->ev_fork, s->st));
   TR_HIP(hipStreamWaitEvent(side, s->ev_fork, 0));
+  // FP32 operands: the MTTKRPs that qualify run on formed subchain blocks
+  // (split as stream_zwg says)
+  // (FP32 cores and accumulation); the cores are copied to FP32 once per
+  // pass on the main stream (beside the first side kernel) and each solve
+  // writes the FP32 copy of the rows it produces
+  bool zf[MAXN] = {};
+  bool any_zf = false;
+  if (s->dt == F32) {
+    for (int n = 0; n < N; ++n) {
+      const Geom gz = make_geom(N, gd.data(), s->R, n);
+      zf[n] = plan_mttkrp(gz, F32, stream_zwg(gz), true).zform != 0;
+      any_zf = any_zf || zf[n];
+    }
+  }
+  CoreView cv32 = state_view(s, Gnew);
+  if (any_zf) {
+    for (int k = 0; k < N; ++k) {
+      const int64_t rows = k == N - 1 ? t_new : s->I[k];
+      TR_HIP(ensure(&s->G32[k], &s->G32_bytes[k], (size_t)rows * s->d(k) * sizeof(float)));
+      if (k < N - 1) TR_HIP(launch_cast(s->G[k], F64, s->G32[k], F32, rows * s->d(k), s->st));
+      cv32.ptr[k] = s->G32[k];
+    }
+  }
   for (int j = 0; j < N; ++j) {
     const int n = j == 0 ? N - 1 : j - 1;
     const bool temporal = n == N - 1;
@@ -1222,22 +1258,26 @@ tr_status str_pass(tr_stream* s, const void* Xd, int64_t t_new, double* Gnew) {
     prof_end(s, pr, side);
     if (!temporal) TR_HIP(hipStreamWaitEvent(s->st, s->ev_rs[n == 0 ? N - 1 : n - 1], 0));
     Geom g = make_geom(N, gd.data(), s->R, n);
-    MttkrpPlan p = plan_mttkrp(g, s->dt);
+    MttkrpPlan p = zf[n] ? plan_mttkrp(g, F32, stream_zwg(g), true) : plan_mttkrp(g, s->dt);
     c = ensure_partials(s, g, p);
     if (c != TR_OK) return c;
     const CoreView cv = state_view(s, Gnew);
     pr = prof_begin(s, temporal ? PK_MTT_T : PK_MTT_N);
-    TR_HIP(launch_mttkrp(g, p, Xd, s->dt, cv, F64, s->part, s->st));
+    if (zf[n])
+      TR_HIP(launch_mttkrp(g, p, Xd, F32, cv32, F32, s->part, s->st));
+    else
+      TR_HIP(launch_mttkrp(g, p, Xd, s->dt, cv, F64, s->part, s->st));
     prof_end(s, pr);
     TR_HIP(hipEventRecord(s->ev_inv[n], s->st));
     TR_HIP(hipStreamWaitEvent(side, s->ev_inv[n], 0));
     pr = prof_begin(s, PK_SOLVE, side);
+    float* g32 = any_zf ? (float*)s->G32[n] : nullptr;
     if (temporal)
       TR_HIP(launch_reduce_solve(s->part, p.psize, p.nsplit, g.In, g.d, nullptr, 0,
-                                 s->MinvM[N - 1], Gnew, side));
+                                 s->MinvM[N - 1], Gnew, side, g32));
     else
       TR_HIP(launch_reduce_solve(s->part, p.psize, p.nsplit, g.In, g.d, s->P[n], 1,
-                                 s->MinvM[n], s->G[n], side));
+                                 s->MinvM[n], s->G[n], side, g32));
     prof_end(s, pr, side);
     TR_HIP(hipEventRecord(s->ev_rs[n], side));
   }
@@ -1690,6 +1730,7 @@ void tr_stream_destroy(tr_stream* s) {
     if (s->Q[k]) (void)hipFree(s->Q[k]);
   }
   for (int k = 0; k < MAXN; ++k) {
+    if (s->G32[k]) (void)hipFree(s->G32[k]);
     if (s->probs[k]) (void)hipFree(s->probs[k]);
     if (s->dsign[k]) (void)hipFree(s->dsign[k]);
     if (s->GSc[k]) (void)hipFree(s->GSc[k]);

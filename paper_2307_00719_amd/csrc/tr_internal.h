@@ -39,7 +39,7 @@ enum DType { F64 = 0, F32 = 1, BF16 = 2 };
 // remaining indices.  Workgroup (chunk, mtile) owns rows [16 mtile, +16)
 // and the outer indices [chunk*upw, (chunk+1)*upw).
 struct MttkrpPlan {
-  int MT;          // rows per tile (16)
+  int MT;          // rows per tile (16); rows per workgroup when zform (16, 32, 64)
   int mtiles;      // ceil(In / 16)
   int nsplit;      // number of outer-index chunks (partials)
   int psize;       // bytes per partial element (8 f64 path, 4 f32 path)
@@ -51,7 +51,7 @@ struct MttkrpPlan {
   int64_t upw;     // outer indices per workgroup
   int64_t sf, sm;  // X strides of i_f and of the row index i_n
   int zform;       // 1: subchain blocks formed per outer index in LDS (FP32,
-                   // order <= 4, ranks <= 16, I_f <= 64; 64 rows per workgroup)
+                   // order <= 4, ranks <= 16, I_f <= 64; MT rows per workgroup)
 };
 
 // max_wg > 0 caps the workgroup count (nsplit * mtiles) at about max_wg.
@@ -69,10 +69,10 @@ hipError_t launch_mttkrp(const Geom& g, const MttkrpPlan& p, const void* X, int 
 
 // Sum the split partials (fixed order) into rows; optionally accumulate into
 // and store P; optionally multiply by Minv (d x d) and write rows of
-// out (row stride out_ld, dtype F64).
+// out (FP64), and with out32 also an FP32 copy of them.
 hipError_t launch_reduce_solve(const void* part, int psize, int nsplit, int64_t In, int d,
                                double* P, int accumulate, const double* Minv,
-                               double* out, hipStream_t st);
+                               double* out, hipStream_t st, float* out32 = nullptr);
 
 // E_k[(a + Ra*a'), (b + Rb*b')] = sum_i G(i)[a,b] G(i)[a',b'] for rows
 // i in [0, rows) of a slice-major FP64 core (slice i at G + i*Ra*Rb).

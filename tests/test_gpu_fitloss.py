@@ -122,14 +122,15 @@ def test_mttkrp_and_gram_chain_entry_points(trlib, dt, dims, ranks):
         assert ep < tol and eq < 1e-12
 
 
-@pytest.mark.parametrize("dims,ranks", [((37, 45, 24, 25), (5, 7, 3, 6)),
+@pytest.mark.parametrize("dims,ranks", [((37, 45, 40, 33), (5, 7, 3, 6)),
                                         ((50, 64, 600), (4, 6, 5))])
 def test_fitloss_f32_bulk_shapes(trlib, dims, ranks):
     """FP32 gradients through the formed-subchain MTTKRP (order <= 4, ranks
-    <= 16, I_f <= 64, at least 512 outer indices per 64-row group): ragged
-    row counts (37, 45, 24, 25; 600 = 9 full 64-row groups + 24), I_f below
-    64 (40-ish fast modes zero padded), unequal ranks, and every chain shape
-    of orders 3 and 4 (U only, V only, both, two factors on one side).
+    <= 16, I_f <= 64, at least 32 rows, twice as many outer indices as
+    workgroups): ragged row counts (37, 45, 40, 33; 600 = 9 full 64-row
+    groups + 24), I_f below 64 (37, 45, 50: zero padded), unequal ranks, and
+    every chain shape of orders 3 and 4 (U only, V only, both, two factors
+    on one side).
     Loss within 1e-5 relative, gradients within 1e-4 (parity.dev)."""
     import torch
     cores, X = W.random_tr_problem(dims, ranks, 9, noise=0.3)
