@@ -1081,7 +1081,10 @@ __global__ __launch_bounds__(256) void k_reduce_solve(const PT* __restrict__ par
   const int64_t row = blockIdx.x;
   const size_t stride = (size_t)In * d;
   const PT* __restrict__ src = part + (size_t)row * d;
-  for (int c = c0; c < d; c += 64) {
+  // without the solve the row's columns are split over blockIdx.y in blocks
+  // of 64 (the solve needs the whole row in one workgroup)
+  const int cbeg = Minv ? 0 : blockIdx.y * 64, cend = Minv ? d : min(d, cbeg + 64);
+  for (int c = cbeg + c0; c < cend; c += 64) {
     double sum = 0.0;
     int sp = q;
     for (; sp + 28 < nsplit; sp += 32) {
@@ -1095,7 +1098,7 @@ __global__ __launch_bounds__(256) void k_reduce_solve(const PT* __restrict__ par
     red[q * d + c] = sum;
   }
   __syncthreads();
-  for (int c = threadIdx.x; c < d; c += 256) {
+  for (int c = cbeg + threadIdx.x; c < cend; c += 256) {
     double sum = ((red[c] + red[d + c]) + red[2 * d + c]) + red[3 * d + c];
     if (P) {
       const size_t pi = (size_t)row * d + c;
@@ -1131,7 +1134,7 @@ hipError_t launch_reduce_solve(const void* part, int psize, int nsplit, int64_t 
                                hipStream_t st, float* out32) {
   if (In <= 0) return hipSuccess;
   if (In > 0x7fffffff || d <= 0) return hipErrorInvalidValue;
-  dim3 grid((unsigned)In);
+  dim3 grid((unsigned)In, Minv ? 1u : (unsigned)((d + 63) / 64));
   const size_t lds = (size_t)5 * d * sizeof(double);
   if (lds > 65536) return hipErrorInvalidValue;
   if (psize == 8)
@@ -3079,7 +3082,9 @@ __global__ __launch_bounds__(256) void k_grad_combine(const TC* __restrict__ G, 
   if (blockIdx.y * 64 + wave * 16 >= d) return;
   const int c2c = c2 < d ? c2 : d - 1;
   const int nks = (d + 3) >> 2;
-  d4 acc = {0, 0, 0, 0};
+  // four accumulators taking turns (independent MFMA chains), added in a
+  // fixed order at the end
+  d4 ac[4] = {d4{0, 0, 0, 0}, d4{0, 0, 0, 0}, d4{0, 0, 0, 0}, d4{0, 0, 0, 0}};
   for (int k0 = 0; k0 < nks; k0 += 8) {
     double av[8], bv[8];
 #pragma unroll
@@ -3092,8 +3097,9 @@ __global__ __launch_bounds__(256) void k_grad_combine(const TC* __restrict__ G, 
       bv[q] = ok ? b : 0.0;
     }
 #pragma unroll
-    for (int q = 0; q < 8; ++q) acc = mfma16(av[q], bv[q], acc);
+    for (int q = 0; q < 8; ++q) ac[q & 3] = mfma16(av[q], bv[q], ac[q & 3]);
   }
+  const d4 acc = (ac[0] + ac[1]) + (ac[2] + ac[3]);
   if (c2 >= d) return;
   const int r2 = c2 % Ra, q2 = c2 / Ra;
 #pragma unroll
