@@ -159,6 +159,9 @@ __global__ __launch_bounds__(256) void k_mix_mode(const TI* __restrict__ in, int
   constexpr int KCP = KCH + (M::KPL == 8 ? 8 : 1);
   constexpr int NCT = JT / 16;
   __shared__ __align__(16) TM Bs[JT * KCP];
+  // offset of (plane 0, i = 0) of each of the workgroup's columns
+  // j = a + S c: a + S I c (-1 past the last column), decoded once here
+  __shared__ int64_t colb[JT];
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int64_t J = S * C;
@@ -167,6 +170,11 @@ __global__ __launch_bounds__(256) void k_mix_mode(const TI* __restrict__ in, int
   const int M2 = 2 * (int)I;
   const int nrt = (M2 + 15) / 16;
   const int l16 = lane & 15, g4 = lane >> 4;
+  if (tid < JT) {
+    const int64_t j = j0 + tid;
+    colb[tid] = j < J ? (j % S) + S * I * (j / S) : -1;
+  }
+  __syncthreads();
   ACC acc[RTW][NCT];
 #pragma unroll
   for (int r = 0; r < RTW; ++r)
@@ -185,12 +193,11 @@ __global__ __launch_bounds__(256) void k_mix_mode(const TI* __restrict__ in, int
         jl = e / KCH;
       }
       const int k = kc + kl;
-      const int64_t j = j0 + jl;
+      const int64_t cb = colb[jl];
       double v = 0.0;
-      if (k < K && j < J) {
-        const int pi = k / (int)I, b = k - pi * (int)I;
-        const int64_t a = j % S, c = j / S;
-        v = to_double(in[pi * ips + a + S * (b + I * c)]);
+      if (k < K && cb >= 0) {
+        const int pi = k >= (int)I ? 1 : 0, b = k - pi * (int)I;   // pin <= 2
+        v = to_double(in[pi * ips + cb + S * b]);
       }
       Bs[jl * KCP + kl] = from_double<TM>(v);
     }
@@ -218,15 +225,14 @@ __global__ __launch_bounds__(256) void k_mix_mode(const TI* __restrict__ in, int
     if (rt < nrt) {
 #pragma unroll
       for (int c = 0; c < NCT; ++c) {
-        const int64_t j = j0 + c * 16 + l16;
-        if (j < J) {
-          const int64_t a = j % S, cc = j / S;
+        const int64_t cb = colb[c * 16 + l16];
+        if (cb >= 0) {
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
             const int row = rt * 16 + M::row(lane, v);
             if (row < M2) {
-              const int po = row / (int)I, i = row - po * (int)I;
-              out[po * ops + a + S * (i + I * cc)] = (TO)acc[r][c][v];
+              const int po = row >= (int)I ? 1 : 0, i = row - po * (int)I;
+              out[po * ops + cb + S * i] = (TO)acc[r][c][v];
             }
           }
         }
@@ -284,7 +290,7 @@ hipError_t launch_mix_weights(int64_t I, int pin, const double* D, int cdt, void
 hipError_t launch_mix_mode(const void* in, int idt, int pin, int64_t ips, void* out,
                            int64_t ops, int64_t S, int64_t I, int64_t C, const void* W, int cdt,
                            hipStream_t st) {
-  if (I > 256) return hipErrorInvalidValue;
+  if (I > 256 || pin < 1 || pin > 2) return hipErrorInvalidValue;
   const int Kp = mix_k_padded(I, pin);
   if (cdt == F64) {
     if (idt != F64) return hipErrorInvalidValue;
@@ -615,10 +621,10 @@ SgemmPlan plan_sgemm(const Geom& g, int m, int dB, int cdt) {
   p.mtiles = (int)((g.In + MT - 1) / MT);
   p.psize = cdt == F64 ? 8 : 4;
   p.nblk = (MT / 16) * NB;
-  // K splits: about 512 workgroups, partials at most 4 MiB
+  // K splits: about 512 workgroups, partials at most 16 MiB
   const int chunks = (2 * m + 31) / 32;
   int64_t ns = (512 + p.mtiles - 1) / p.mtiles;
-  const int64_t budget = ((int64_t)4 << 20) / ((int64_t)g.In * dB * p.psize);
+  const int64_t budget = ((int64_t)16 << 20) / ((int64_t)g.In * dB * p.psize);
   if (ns > budget) ns = budget;
   if (ns > chunks) ns = chunks;
   if (ns < 1) ns = 1;

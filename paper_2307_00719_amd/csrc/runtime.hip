@@ -482,11 +482,11 @@ tr_status gram_update_invert(tr_stream* s, hipStream_t on, double* M, int Ra, in
 
 // The sketched Gram's Q update and inverse occupy one compute unit and are
 // latency-bound, and the sketched product does not read what they write: in
-// rSTR-K, whose mixed product, reduction and unmixing take about half as long
-// as the inverse, the inverse goes to the second stream once the Gram is
-// formed on the main one (fork), and the main stream waits for it before the
-// solve (join).  rSTR-U/L keep one stream: their product (about 16 us) does
-// not pay for the two cross-stream waits.
+// rSTR-K, whose mixed product, reduction and unmixing take less time than
+// the inverse, the product chain goes to the second stream (fork) while the
+// caller's stream runs the Gram and the inverse, and then waits for the
+// product chain before the solve (join).  rSTR-U/L keep one stream: their
+// product tiles ride in the side kernel itself.
 tr_status fork_side(tr_stream* s) {
   TR_HIP(hipEventRecord(s->ev_fork, s->st));
   TR_HIP(hipStreamWaitEvent(s->side, s->ev_fork, 0));
@@ -729,21 +729,27 @@ tr_status ksrft_increment(tr_stream* s, int n, const void* xhat, int64_t t, int 
   TR_HIP(ensure(&s->part, &s->part_bytes, (size_t)sp.nsplit * g.In * 2 * d * sp.psize));
   TR_HIP(ensure((void**)&s->Zk, &s->Zk_bytes, (size_t)g.In * 2 * d * sizeof(double)));
   TR_HIP(ensure((void**)&s->dPk, &s->dPk_bytes, (size_t)g.In * d * sizeof(double)));
+  // the mixed product, its reduction and the unmixing on the second stream;
+  // the Gram and the inverse (the longer chain) on the caller's stream,
+  // which the solve then follows with no cross-stream wait of its own
+  // unless the product chain is still running
   {
     tr_status c0 = fork_side(s);
     if (c0 != TR_OK) return c0;
-    c0 = temporal ? gram_update_invert(s, s->side, s->Zb, s->R[n], s->R[(n + 1) % N], nullptr, 0,
-                                       s->Minv, s->Ast, gw, grows)
-                  : gram_update_invert(s, s->side, s->Zb, s->R[n], s->R[(n + 1) % N], s->Q[n],
-                                       accumulate, solve ? s->Minv : nullptr, s->Ast, gw, grows);
-    if (c0 != TR_OK) return c0;
   }
-  TR_HIP(launch_sgemm(g, sp, 2 * d, total, xhat, s->dt, s->idxs, m, s->Bst, s->part, s->st));
+  TR_HIP(launch_sgemm(g, sp, 2 * d, total, xhat, s->dt, s->idxs, m, s->Bst, s->part, s->side));
   TR_HIP(launch_reduce_solve(s->part, sp.psize, sp.nsplit, g.In, 2 * d, s->Zk, 0, nullptr,
-                             nullptr, s->st));
-  TR_HIP(launch_unmix(s->Zk, g.In, d, s->dsign[n], s->dPk, s->st));
+                             nullptr, s->side));
+  TR_HIP(launch_unmix(s->Zk, g.In, d, s->dsign[n], s->dPk, s->side));
   {
-    tr_status c0 = join_side(s);
+    tr_status c0 = temporal
+                       ? gram_update_invert(s, s->st, s->Zb, s->R[n], s->R[(n + 1) % N], nullptr,
+                                            0, s->Minv, s->Ast, gw, grows)
+                       : gram_update_invert(s, s->st, s->Zb, s->R[n], s->R[(n + 1) % N], s->Q[n],
+                                            accumulate, solve ? s->Minv : nullptr, s->Ast, gw,
+                                            grows);
+    if (c0 != TR_OK) return c0;
+    c0 = join_side(s);
     if (c0 != TR_OK) return c0;
   }
   TR_HIP(launch_reduce_solve(s->dPk, 8, 1, g.In, d, temporal ? nullptr : s->P[n], accumulate,
