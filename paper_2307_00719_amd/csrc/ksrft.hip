@@ -111,16 +111,52 @@ hipError_t launch_signs(uint64_t key, int64_t n, double* out, hipStream_t st) {
   return hipGetLastError();
 }
 
+__global__ void k_signs_all(SignsAll a) {
+  const int k = blockIdx.y;
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < a.n[k]) a.out[k][i] = (mix64(a.key[k] + (uint64_t)i) >> 63) == 0 ? 1.0 : -1.0;
+}
+
+hipError_t launch_signs_all(const SignsAll& a, hipStream_t st) {
+  if (a.count < 1 || a.count > MAXN) return hipErrorInvalidValue;
+  int64_t nmax = 1;
+  for (int k = 0; k < a.count; ++k) nmax = a.n[k] > nmax ? a.n[k] : nmax;
+  hipLaunchKernelGGL(k_signs_all, dim3((unsigned)((nmax + 255) / 256), (unsigned)a.count),
+                     dim3(256), 0, st, a);
+  return hipGetLastError();
+}
+
 // ---------------------------------------------------------------------------
 // Mixing matrix of one mode as a real (2I x Kp) row-major matrix acting on
 // stacked planes: real input [[Re W], [Im W]], complex input
 // [[Re W, -Im W], [Im W, Re W]], W = F D; columns past pin*I are zero.
 // ---------------------------------------------------------------------------
+// K of a mixing matrix (pin I) padded to the 64-row staging chunks.
+__host__ __device__ inline int mix_kp(int64_t I, int pin) { return (pin * (int)I + 63) / 64 * 64; }
+
+template <typename TM>
+__device__ inline void mix_weight(int64_t I, int pin, const double* __restrict__ D, int Kp,
+                                  TM* __restrict__ W, int64_t e);
+
 template <typename TM>
 __global__ void k_mix_weights(int64_t I, int pin, const double* __restrict__ D, int Kp,
                               TM* __restrict__ W) {
   const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (e >= 2 * I * Kp) return;
+  if (e < 2 * I * Kp) mix_weight(I, pin, D, Kp, W, e);
+}
+
+template <typename TM>
+__global__ void k_mix_weights_all(MixWeightsAll a) {
+  const int k = blockIdx.y;
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int Kp = mix_kp(a.I[k], a.pin[k]);
+  if (e < 2 * a.I[k] * Kp) mix_weight(a.I[k], a.pin[k], a.D[k], Kp, (TM*)a.W[k], e);
+}
+
+// Entry e (row-major) of the mixing matrix.
+template <typename TM>
+__device__ inline void mix_weight(int64_t I, int pin, const double* __restrict__ D, int Kp,
+                                  TM* __restrict__ W, int64_t e) {
   const int64_t row = e / Kp, col = e - row * Kp;
   double val = 0.0;
   if (col < pin * I) {
@@ -243,10 +279,60 @@ __global__ __launch_bounds__(256) void k_mix_mode(const TI* __restrict__ in, int
 
 static int round_up(int x, int q) { return (x + q - 1) / q * q; }
 
+// Mixing along a short mode (2I <= 16), where the MFMA tiles would be
+// mostly padding: one thread per column j = a + S c, its pin I inputs
+// rounded to the operand type TM (as the tiled kernel rounds its staged
+// operands) against the 2I x Kp matrix, accumulated in the output type.
+template <typename TI, typename TM, typename TO>
+__global__ __launch_bounds__(256) void k_mix_small(const TI* __restrict__ in, int pin,
+                                                   int64_t ips, TO* __restrict__ out,
+                                                   int64_t ops, int64_t S, int I, int64_t C,
+                                                   const TM* __restrict__ W, int Kp) {
+  const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (j >= S * C) return;
+  const int64_t cb = (j % S) + S * I * (j / S);
+  const int K = pin * I;
+  TO x[16];
+#pragma unroll
+  for (int k = 0; k < 16; ++k) {
+    x[k] = TO(0);
+    if (k < K) {
+      const int pi = k >= I ? 1 : 0, b = k - pi * I;
+      const TM v = from_double<TM>(to_double(in[pi * ips + cb + S * b]));
+      x[k] = (TO)(float)v;
+      if constexpr (sizeof(TM) == 8) x[k] = (TO)v;
+    }
+  }
+#pragma unroll
+  for (int row = 0; row < 16; ++row) {
+    if (row < 2 * I) {
+      TO acc = TO(0);
+#pragma unroll
+      for (int k = 0; k < 16; ++k) {
+        TO w = TO(0);
+        if (k < K) {
+          const TM wv = W[row * Kp + k];
+          w = (TO)(float)wv;
+          if constexpr (sizeof(TM) == 8) w = (TO)wv;
+        }
+        acc += w * x[k];
+      }
+      const int po = row >= I ? 1 : 0, i = row - po * I;
+      out[po * ops + cb + S * i] = acc;
+    }
+  }
+}
+
 template <typename TI, typename TM, typename TO, int JT>
 static hipError_t launch_mix_mode_t(const void* in, int pin, int64_t ips, void* out, int64_t ops,
                                     int64_t S, int64_t I, int64_t C, const void* W, int Kp,
                                     hipStream_t st) {
+  if (2 * I <= 16) {
+    hipLaunchKernelGGL((k_mix_small<TI, TM, TO>), dim3((unsigned)((S * C + 255) / 256)),
+                       dim3(256), 0, st, (const TI*)in, pin, ips, (TO*)out, ops, S, (int)I, C,
+                       (const TM*)W, Kp);
+    return hipGetLastError();
+  }
   const int nrt = (int)((2 * I + 15) / 16);
   const int rtw = (nrt + 3) / 4;
   const unsigned grid = (unsigned)((S * C + JT - 1) / JT);
@@ -269,7 +355,7 @@ static hipError_t launch_mix_mode_t(const void* in, int pin, int64_t ips, void* 
   return hipGetLastError();
 }
 
-int mix_k_padded(int64_t I, int pin) { return round_up(pin * (int)I, 64); }
+int mix_k_padded(int64_t I, int pin) { return mix_kp(I, pin); }
 
 hipError_t launch_mix_weights(int64_t I, int pin, const double* D, int cdt, void* W,
                               hipStream_t st) {
@@ -284,6 +370,23 @@ hipError_t launch_mix_weights(int64_t I, int pin, const double* D, int cdt, void
   else
     hipLaunchKernelGGL(k_mix_weights<__bf16>, dim3(grid), dim3(256), 0, st, I, pin, D, Kp,
                        (__bf16*)W);
+  return hipGetLastError();
+}
+
+hipError_t launch_mix_weights_all(const MixWeightsAll& a, int cdt, hipStream_t st) {
+  if (a.count < 1 || a.count > MAXN) return hipErrorInvalidValue;
+  int64_t emax = 1;
+  for (int k = 0; k < a.count; ++k) {
+    const int64_t e = 2 * a.I[k] * mix_kp(a.I[k], a.pin[k]);
+    emax = e > emax ? e : emax;
+  }
+  const dim3 grid((unsigned)((emax + 255) / 256), (unsigned)a.count);
+  if (cdt == F64)
+    hipLaunchKernelGGL(k_mix_weights_all<double>, grid, dim3(256), 0, st, a);
+  else if (cdt == F32)
+    hipLaunchKernelGGL(k_mix_weights_all<float>, grid, dim3(256), 0, st, a);
+  else
+    hipLaunchKernelGGL(k_mix_weights_all<__bf16>, grid, dim3(256), 0, st, a);
   return hipGetLastError();
 }
 

@@ -103,7 +103,7 @@ struct tr_stream {
   double* Ast = nullptr;     // [Re A; Im A], 2m x dmax
   double* Bst = nullptr;     // product operand, 2m x 2 dmax
   double* Sw2 = nullptr;     // 2m weights
-  void* Wmix = nullptr;      // mixing matrix of one mode
+  void* Wmix = nullptr;      // mixing matrices of all modes
   size_t Wmix_bytes = 0;
   void* xh[2] = {};          // mixed batch, 2 planes (ping-pong)
   size_t xh_bytes[2] = {};
@@ -646,11 +646,14 @@ tr_status ksrft_signs(tr_stream* s, int64_t t) {
     s->next_signs_t = 0;
     return TR_OK;
   }
+  SignsAll a = {};
+  a.count = N;
   for (int k = 0; k < N; ++k) {
-    const int64_t n = k == N - 1 ? t : s->I[k];
-    TR_HIP(launch_signs(rng_key(s->seed, (uint64_t)s->step, (uint64_t)k, 1), n, s->dsign[k],
-                        s->st));
+    a.key[k] = rng_key(s->seed, (uint64_t)s->step, (uint64_t)k, 1);
+    a.n[k] = k == N - 1 ? t : s->I[k];
+    a.out[k] = s->dsign[k];
   }
+  TR_HIP(launch_signs_all(a, s->st));
   return TR_OK;
 }
 
@@ -668,17 +671,30 @@ tr_status ksrft_mix(tr_stream* s, const void* Xd, int64_t t, const void** xhat) 
   const size_t xs = s->dt == F64 ? 8 : 4;
   const size_t ws = s->dt == F64 ? 8 : (s->dt == F32 ? 4 : 2);
   for (int b = 0; b < 2; ++b) TR_HIP(ensure(&s->xh[b], &s->xh_bytes[b], 2 * (size_t)total * xs));
-  size_t wneed = 0;
-  for (int k = 0; k < N; ++k)
-    wneed = std::max(wneed, (size_t)2 * dims[k] * mix_k_padded(dims[k], 2) * ws);
+  // the mixing matrices of all modes (mode 0 acts on the real data, the
+  // others on two planes), formed in one launch into consecutive slots
+  MixWeightsAll wa = {};
+  wa.count = N;
+  size_t woff[MAXN], wneed = 0;
+  for (int k = 0; k < N; ++k) {
+    woff[k] = wneed;
+    const int pk = k == 0 ? 1 : 2;
+    wneed += ((size_t)2 * dims[k] * mix_k_padded(dims[k], pk) * ws + 255) / 256 * 256;
+  }
   TR_HIP(ensure(&s->Wmix, &s->Wmix_bytes, wneed));
+  for (int k = 0; k < N; ++k) {
+    wa.I[k] = dims[k];
+    wa.pin[k] = k == 0 ? 1 : 2;
+    wa.D[k] = s->dsign[k];
+    wa.W[k] = (char*)s->Wmix + woff[k];
+  }
+  TR_HIP(launch_mix_weights_all(wa, s->dt, s->st));
   const void* in = Xd;
   int idt = s->dt, pin = 1, cur = 0;
   int64_t S = 1;
   for (int k = 0; k < N; ++k) {
     const int64_t Ik = dims[k], C = total / (S * Ik);
-    TR_HIP(launch_mix_weights(Ik, pin, s->dsign[k], s->dt, s->Wmix, s->st));
-    TR_HIP(launch_mix_mode(in, idt, pin, total, s->xh[cur], total, S, Ik, C, s->Wmix, s->dt,
+    TR_HIP(launch_mix_mode(in, idt, pin, total, s->xh[cur], total, S, Ik, C, wa.W[k], s->dt,
                            s->st));
     in = s->xh[cur];
     idt = s->dt == F64 ? F64 : F32;

@@ -251,12 +251,30 @@ __host__ __device__ inline uint64_t mix64(uint64_t x) {
 
 // n random signs (+1 / -1, FP64) of the stream `key`.
 hipError_t launch_signs(uint64_t key, int64_t n, double* out, hipStream_t st);
+// The signs of up to MAXN streams in one launch (stream k: n[k] signs of
+// key[k] into out[k]).
+struct SignsAll {
+  uint64_t key[MAXN];
+  int64_t n[MAXN];
+  double* out[MAXN];
+  int count;
+};
+hipError_t launch_signs_all(const SignsAll& a, hipStream_t st);
 
 // Mixing matrix of one mode (2I x mix_k_padded(I, pin), row-major, dtype
 // cdt) for a real (pin = 1) or complex (pin = 2, stacked planes) input.
 int mix_k_padded(int64_t I, int pin);
 hipError_t launch_mix_weights(int64_t I, int pin, const double* D, int cdt, void* W,
                               hipStream_t st);
+// The mixing matrices of up to MAXN modes in one launch (mode k into W[k]).
+struct MixWeightsAll {
+  int64_t I[MAXN];
+  int pin[MAXN];
+  const double* D[MAXN];
+  void* W[MAXN];
+  int count;
+};
+hipError_t launch_mix_weights_all(const MixWeightsAll& a, int cdt, hipStream_t st);
 // out (2 planes, dtype F64 for cdt F64, else F32) = W applied along a mode
 // of stride S and size I (C = product of the slower modes) of `in` (pin
 // planes of dtype idt, plane strides ips / ops elements).
