@@ -449,15 +449,19 @@ __global__ __launch_bounds__(256) void k_mix_slices(const double* __restrict__ G
 // per workgroup instead of once per sample; same sum, same order.
 constexpr int MIX_TILE_MAXI = 448;     // (2 + 16) * 448 doubles fit the 64 KiB default
 
-__global__ __launch_bounds__(256) void k_mix_slices_t(const double* __restrict__ G, int I, int d,
-                                                      const double* __restrict__ D,
-                                                      const int* __restrict__ idx, int m,
-                                                      double* __restrict__ GS) {
+__global__ __launch_bounds__(256) void k_mix_slices_t(MixSlicesAll a) {
   extern __shared__ double sm[];
+  const int k = blockIdx.z;
+  const double* __restrict__ G = a.G[k];
+  const double* __restrict__ D = a.D[k];
+  const int* __restrict__ idx = a.idx[k];
+  double* __restrict__ GS = a.GS[k];
+  const int I = a.I[k], d = a.d[k], m = a.m;
   double* tw = sm;                          // [I] cos, [I] sin
   double* dg = sm + 2 * I;                  // [I][16]: D[i] G[i][c0 + j]
   const int tid = threadIdx.x;
   const int c0 = blockIdx.x * 16, s0 = blockIdx.y * 16;
+  if (c0 >= d) return;                      // a narrower core of the batch
   for (int r = tid; r < I; r += 256) twiddle(r, I, &tw[r], &tw[I + r]);
   for (int e = tid; e < I * 16; e += 256) {
     const int i = e >> 4, j = e & 15;
@@ -469,33 +473,66 @@ __global__ __launch_bounds__(256) void k_mix_slices_t(const double* __restrict__
   const int s = s0 + sl, c = c0 + j;
   if (s >= m || c >= d) return;
   const int step = idx[s];
-  double re = 0.0, im = 0.0;
+  // four partial sums over i (independent FMA chains), added in a fixed
+  // order; r = (i step) mod I walks the twiddle table
+  double re[4] = {0, 0, 0, 0}, im[4] = {0, 0, 0, 0};
   int r = 0;
-  for (int i = 0; i < I; ++i) {
+  int i = 0;
+  for (; i + 4 <= I; i += 4) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const double gv = dg[(i + u) * 16 + j];
+      re[u] += tw[r] * gv;
+      im[u] -= tw[I + r] * gv;
+      r += step;
+      if (r >= I) r -= I;
+    }
+  }
+  for (; i < I; ++i) {
     const double gv = dg[i * 16 + j];
-    re += tw[r] * gv;
-    im -= tw[I + r] * gv;
+    re[0] += tw[r] * gv;
+    im[0] -= tw[I + r] * gv;
     r += step;
     if (r >= I) r -= I;
   }
   const double sc = 1.0 / sqrt((double)I);
   const int64_t e = (int64_t)s * d + c;
-  GS[e] = re * sc;
-  GS[(int64_t)m * d + e] = im * sc;
+  GS[e] = ((re[0] + re[1]) + (re[2] + re[3])) * sc;
+  GS[(int64_t)m * d + e] = ((im[0] + im[1]) + (im[2] + im[3])) * sc;
 }
 
 hipError_t launch_mix_slices(const double* G, int64_t I, int d, const double* D, const int* idx,
                              int m, double* GS, hipStream_t st) {
   if (I > 4096) return hipErrorInvalidValue;
   if (I <= MIX_TILE_MAXI) {
-    dim3 grid((unsigned)((d + 15) / 16), (unsigned)((m + 15) / 16));
-    const size_t lds = (size_t)(2 * I + 16 * I) * sizeof(double);
-    hipLaunchKernelGGL(k_mix_slices_t, grid, dim3(256), lds, st, G, (int)I, d, D, idx, m, GS);
-    return hipGetLastError();
+    MixSlicesAll a = {};
+    a.count = 1;
+    a.m = m;
+    a.G[0] = G;
+    a.I[0] = (int)I;
+    a.d[0] = d;
+    a.D[0] = D;
+    a.idx[0] = idx;
+    a.GS[0] = GS;
+    return launch_mix_slices_all(a, st);
   }
   const unsigned grid = (unsigned)(((int64_t)m * d + 255) / 256);
   hipLaunchKernelGGL(k_mix_slices, dim3(grid), dim3(256), (size_t)2 * I * sizeof(double), st, G,
                      I, d, D, idx, m, GS);
+  return hipGetLastError();
+}
+
+hipError_t launch_mix_slices_all(const MixSlicesAll& a, hipStream_t st) {
+  if (a.count < 1 || a.count > MAXN) return hipErrorInvalidValue;
+  int imax = 1, dmax = 1;
+  for (int k = 0; k < a.count; ++k) {
+    if (a.I[k] > MIX_TILE_MAXI || a.I[k] < 1 || a.d[k] < 1) return hipErrorInvalidValue;
+    imax = a.I[k] > imax ? a.I[k] : imax;
+    dmax = a.d[k] > dmax ? a.d[k] : dmax;
+  }
+  dim3 grid((unsigned)((dmax + 15) / 16), (unsigned)((a.m + 15) / 16), (unsigned)a.count);
+  const size_t lds = (size_t)(2 * imax + 16 * imax) * sizeof(double);
+  hipLaunchKernelGGL(k_mix_slices_t, grid, dim3(256), lds, st, a);
   return hipGetLastError();
 }
 

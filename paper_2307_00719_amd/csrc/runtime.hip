@@ -805,9 +805,30 @@ tr_status ksrft_update(tr_stream* s, const void* Xd, int64_t t_new, double* Gnew
   const void* xhat = nullptr;
   c = ksrft_mix(s, Xd, t_new, &xhat);
   if (c != TR_OK) return c;
-  for (int k = 0; k < N - 1; ++k) {
-    c = ksrft_slices(s, k, s->G[k], s->I[k]);
-    if (c != TR_OK) return c;
+  // this step's signs change every core's sampled mixed slices: the
+  // non-temporal ones in one launch
+  {
+    bool tiled = true;
+    for (int k = 0; k < N - 1; ++k) tiled = tiled && s->I[k] <= 448;
+    if (tiled) {
+      MixSlicesAll a = {};
+      a.count = N - 1;
+      a.m = (int)s->m;
+      for (int k = 0; k < N - 1; ++k) {
+        a.G[k] = s->G[k];
+        a.I[k] = (int)s->I[k];
+        a.d[k] = s->d(k);
+        a.D[k] = s->dsign[k];
+        a.idx[k] = s->idxs + (size_t)k * s->m;
+        a.GS[k] = s->GSc[k];
+      }
+      TR_HIP(launch_mix_slices_all(a, s->st));
+    } else {
+      for (int k = 0; k < N - 1; ++k) {
+        c = ksrft_slices(s, k, s->G[k], s->I[k]);
+        if (c != TR_OK) return c;
+      }
+    }
   }
   c = ksrft_increment(s, N - 1, xhat, t_new, 0, true, Gnew);
   if (c != TR_OK) return c;

@@ -284,6 +284,17 @@ hipError_t launch_mix_mode(const void* in, int idt, int pin, int64_t ips, void* 
 // GS (2 planes of m x d) = sampled rows idx of the mixed core (F D) G.
 hipError_t launch_mix_slices(const double* G, int64_t I, int d, const double* D, const int* idx,
                              int m, double* GS, hipStream_t st);
+// The sampled mixed slices of up to MAXN cores in one launch (core k: I[k]
+// slice-major rows of width d[k], at most 448 rows; m samples each).
+struct MixSlicesAll {
+  const double* G[MAXN];
+  const double* D[MAXN];
+  const int* idx[MAXN];
+  double* GS[MAXN];
+  int I[MAXN], d[MAXN];
+  int m, count;
+};
+hipError_t launch_mix_slices_all(const MixSlicesAll& a, hipStream_t st);
 // Complex sampled subchain rows of mode g.n from the sampled mixed slices
 // GS (device array of N pointers): Ast (2m x d), Bst (2m x 2d), w2 (2m).
 hipError_t launch_sample_rows_c(const Geom& g, const double* const* GS, int m, double w,
