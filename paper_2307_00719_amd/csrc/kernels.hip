@@ -1986,7 +1986,7 @@ constexpr int SIDE_LDS_MF_ALLOC = SIDE_LDS_MF + 2;
 // a tile column for the four-wave column-owner form).
 template <int NW, int MAXT>
 __device__ inline void side_serial(const SideArgs& sa, double* lds, double* dmax, int tid,
-                                   bool pre = false) {
+                                   bool pre = false, bool mpre = false) {
   // LDS budget in doubles (the allocation has one spare slot past it)
   constexpr int CAP = NW == 16 ? SIDE_LDS_MF : SIDE_LDS;
   // [0] some pivot test failed, [1] waves done (zeroed here; the barriers of
@@ -2052,9 +2052,10 @@ __device__ inline void side_serial(const SideArgs& sa, double* lds, double* dmax
   // M is always a global pointer (a pointer that may also address LDS would
   // turn every load into a flat load with conservative waits); m_lds says
   // the last product is in LDS instead
-  const double* M = sa.fac[0] ? sa.fac[0] : sa.Ep;
+  // mpre: the Gram workgroups formed the (two-factor) product in cbuf[0]
+  const double* M = mpre ? sa.cbuf[0] : (sa.fac[0] ? sa.fac[0] : sa.Ep);
   bool m_lds = false;
-  for (int j = 1; j < sa.nfac; ++j) {
+  for (int j = 1; j < (mpre ? 1 : sa.nfac); ++j) {
     const double* __restrict__ F = sa.fac[j] ? sa.fac[j] : sa.Ep;
     double* out = sa.cbuf[(j - 1) & 1];
     const int d1 = sa.fr[0], d2 = sa.fc[j - 1], d3 = sa.fc[j];
@@ -2390,7 +2391,8 @@ __device__ inline void side_serial(const SideArgs& sa, double* lds, double* dmax
 // summed in LDS in a fixed order, and the tile and its mirror written in the
 // transfer layout.
 template <int NW, bool WEIGHTED = false>
-__device__ inline void gram_tile(const SideArgs& sa, double* lds, int tid, int tile) {
+__device__ inline void gram_tile(const SideArgs& sa, double* lds, int tid, int tile,
+                                 double* keep = nullptr) {
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
   const int ar = lane & 15, ak = lane >> 4;
   const int Ra = sa.Rpa, Rb = sa.Rpb, dp = Ra * Rb;
@@ -2443,6 +2445,7 @@ __device__ inline void gram_tile(const SideArgs& sa, double* lds, int tid, int t
 #pragma unroll
     for (int w = 0; w < NW; ++w) sum += lds[w * 256 + e];
     const int r = rb * 16 + (e >> 4), c = cb * 16 + (e & 15);
+    if (keep) keep[e] = r < dp && c < dp ? sum : 0.0;
     // weighted: (w x) y and (w y) x may differ in the last bit, so in the
     // diagonal tile only r <= c writes (both positions: exactly symmetric)
     if (r < dp && c < dp && (!WEIGHTED || r <= c)) {
@@ -2601,6 +2604,58 @@ __global__ __launch_bounds__(1024) void k_side_mf(SideArgs sa) {
 // other writes, and no workgroup waits for another; the split reduction and
 // solve follow on the same stream.
 // ---------------------------------------------------------------------------
+// Two-factor chain product M = E_a E_p (E_a the older factor, already in
+// LDS with padded rows; E_p the transfer layout of the Gram being formed)
+// for R_p = 8: Gram index c = a + 8 b, E_p[(a1 + 8 a2)][(b1 + R' b2)] =
+// Gram[a1 + 8 b1][a2 + 8 b2], so the 16 x 16 Gram tile (rb, cb) holds the
+// whole columns b1 in {2 rb, 2 rb + 1}, b2 in {2 cb, 2 cb + 1} of E_p, and
+// its mirror the columns with rb and cb exchanged.  Each Gram workgroup
+// therefore forms those (up to 8) columns of M, one 16-row tile of M per
+// wave on FP64 MFMAs (B operand: column n < 8 of the tile's set, zero
+// beyond), and stores them to cbuf[0] with device-coherent stores before it
+// counts itself in.
+__device__ inline bool mcols_ok(const SideArgs& sa) {
+  return sa.mcols && sa.nfac == 2 && sa.Rpa == 8 && sa.fr[0] == 64 && sa.fc[0] == 64;
+}
+
+__device__ inline void gram_chain_cols(const SideArgs& sa, const double* tl, const double* lds,
+                                       int tid, int tile) {
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
+  const int l16 = lane & 15, g4 = lane >> 4;
+  const int Rb = sa.Rpb, d3 = Rb * Rb, dp = 8 * Rb, nbp = (dp + 15) >> 4;
+  int rb = 0, cb = tile;
+  while (cb >= nbp - rb) {
+    cb -= nbp - rb;
+    ++rb;
+  }
+  cb += rb;
+  // this lane's B column n = l16: tile group (n < 4) or mirror group (n < 8)
+  const int n = l16;
+  const bool mir = n >= 4;
+  const int u = n & 1, v = (n >> 1) & 1;
+  const int b1 = mir ? 2 * cb + u : 2 * rb + u, b2 = mir ? 2 * rb + v : 2 * cb + v;
+  const bool colok = n < (rb == cb ? 4 : 8) && b1 < Rb && b2 < Rb;
+  constexpr int d2p = 65;                   // padded rows of the staged E_a
+  d4 acc = {0, 0, 0, 0};
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const int k = 4 * q + g4;               // k = a1 + 8 a2
+    const int a1 = k & 7, a2 = k >> 3;
+    // tile (rb, cb) entry (a1 + 8 u, a2 + 8 v), or for the mirror group the
+    // tile entry (a2 + 8 v, a1 + 8 u)
+    const int ti = mir ? a2 + 8 * v : a1 + 8 * u, tj = mir ? a1 + 8 * u : a2 + 8 * v;
+    const double bv = colok ? tl[ti * 16 + tj] : 0.0;
+    acc = mfma16(lds[(16 * wave + l16) * d2p + k], bv, acc);
+  }
+  if (colok) {
+#pragma unroll
+    for (int w = 0; w < 4; ++w) {
+      const int row = 16 * wave + Acc<double>::row(lane, w);
+      coherent_store(sa.cbuf[0] + (size_t)row * d3 + b1 + Rb * b2, acc[w]);
+    }
+  }
+}
+
 // MTTKRP workgroup w (of nw) of the fused launch -> (chunk, row tile).
 // Workgroups go to the 8 XCDs round robin, so w and w + 8 share an XCD and
 // its L2: with an even number of row tiles those two take row tiles 2k and
@@ -2634,17 +2689,25 @@ __global__ __launch_bounds__(256, 2) void k_mode(Geom g, MttkrpPlan p, const T* 
     // the MTTKRP waves sharing the compute unit
     __builtin_amdgcn_s_setprio(3);
     double* lds = (double*)smem;
-    bool pre = false;
+    __shared__ double tl[256];
+    bool pre = false, mpre = false;
     if (sa.Gp) {
       FirstFactor ff;
       prestage_first_factor_load(sa, ff, threadIdx.x);
-      gram_tile<4>(sa, lds, threadIdx.x, blockIdx.x);
+      const bool mc = mcols_ok(sa);
+      gram_tile<4>(sa, lds, threadIdx.x, blockIdx.x, mc ? tl : nullptr);
       __syncthreads();
       prestage_first_factor_store(sa, ff, lds, threadIdx.x);
       pre = ff.ok;
+      // (ff.ok holds whenever mcols_ok does: 64 x 64 factors)
+      if (mc && ff.ok) {
+        __syncthreads();
+        gram_chain_cols(sa, tl, lds, threadIdx.x, blockIdx.x);
+        mpre = true;
+      }
       if (!gram_arrive(sa.counter, (unsigned)ngram, threadIdx.x)) return;
     }
-    side_serial<4, MAXT>(sa, lds, dmax, threadIdx.x, pre);
+    side_serial<4, MAXT>(sa, lds, dmax, threadIdx.x, pre, mpre);
     return;
   }
   int chunk, mtile;

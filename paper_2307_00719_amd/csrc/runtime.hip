@@ -1229,6 +1229,7 @@ tr_status str_pass(tr_stream* s, const void* Xd, int64_t t_new, double* Gnew) {
     a.status = s->dstatus;
     a.counter = s->sidecnt;
     a.pw = s->pinvW;
+    a.mcols = 1;                     // used by the fused launch where it applies
     return a;
   };
   auto side_of = [&](int n) {

@@ -130,6 +130,10 @@ struct SideArgs {
   int* status;         // [0] failure flag, [2] fallback count, [3] this solve fell back
   unsigned* counter;   // arrival counter of the Gram workgroups (zero between launches)
   double* pw;          // 2 d^2 + d doubles of scratch for the pseudo-inverse fallback
+  // k_mode, two-factor chains (order 3) with R_p = 8: the Gram workgroups
+  // also form the chain product's columns that their tile determines, so the
+  // side step starts from the finished product (cbuf[0])
+  int mcols;
   // Sketched product tiles beside the Gram tiles (k_side_mf; none when Pout
   // is null): Pout[i * d + c] = sum_s Gw[s] X[xoff(s) + i * xsn] Gp[s * d + c]
   // over the rows_p samples for i < pIn, in FP64, with

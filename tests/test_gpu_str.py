@@ -70,6 +70,9 @@ SHAPES = [
     ((21, 19), (5, 4, 6), 40, 11, 2),
     # Q of 42 x 42 and 49 x 49: three and four ragged 16 x 16 tiles a side
     ((24, 22), (7, 6, 7), 20, 6, 2),
+    # R_p = 8 with R_{p+1} = 7 and 8: the Gram workgroups of the fused launch
+    # also form the chain product's columns (odd R_{p+1}: a partial last tile)
+    ((19, 21), (8, 7, 8), 12, 5, 3),
     # Q of 72 x 72 to 90 x 90 (d > 64): past the fused per-mode launch, so the
     # side kernel (its own Gram tile workgroups, chain, upper-triangle inverse)
     # runs on the second stream
