@@ -1817,27 +1817,30 @@ __device__ inline double coherent_load(const double* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Cross-lane moves of the pivot step, all on the VALU (no LDS round trip):
-// group_bcast<K> gives every lane the value held by the lane of the same
-// column in row group K (lanes 16K..16K+15): a 16-lane-row swap picks rows
-// {K&1, K&1 + 2}, a 32-lane-half swap then the half K&2.  row_bcast<p>
-// gives every lane the value of lane p of its own 16-lane row (DPP row
-// broadcast).  lane_value<L> reads lane L into a wave-uniform value.
-template <int K>
-__device__ inline double group_bcast(double x) {
+// Cross-lane moves of the pivot step, all on the VALU (no LDS round trip).
+// pair_bcast<G> (G even) gives every lane the values held by the lanes of
+// its column in row groups G and G + 1 (lanes 16G.. and 16(G+1)..): an
+// exchange of 32-lane halves keeps half G/2 in both, an exchange of 16-lane
+// rows then separates the two groups.  row_bcast<p> gives every lane the
+// value of lane p of its own 16-lane row (DPP row broadcast; every lane is
+// written, so the old value is arbitrary: passing one that is dead
+// afterwards spares the copy of a constant).  lane_value<L> reads lane L
+// into a wave-uniform value.
+template <int G>
+__device__ inline void pair_bcast(double x, double& r0, double& r1) {
   const unsigned long long u = __builtin_bit_cast(unsigned long long, x);
   const unsigned lo = (unsigned)u, hi = (unsigned)(u >> 32);
-  const auto a = __builtin_amdgcn_permlane16_swap(lo, lo, false, false);
-  const auto b = __builtin_amdgcn_permlane16_swap(hi, hi, false, false);
-  const unsigned lo1 = (K & 1) ? a[1] : a[0], hi1 = (K & 1) ? b[1] : b[0];
-  const auto c = __builtin_amdgcn_permlane32_swap(lo1, lo1, false, false);
-  const auto e = __builtin_amdgcn_permlane32_swap(hi1, hi1, false, false);
-  const unsigned lo2 = (K & 2) ? c[1] : c[0], hi2 = (K & 2) ? e[1] : e[0];
-  return __builtin_bit_cast(double, ((unsigned long long)hi2 << 32) | lo2);
+  const auto a = __builtin_amdgcn_permlane32_swap(lo, lo, false, false);
+  const auto b = __builtin_amdgcn_permlane32_swap(hi, hi, false, false);
+  const unsigned lo1 = (G & 2) ? a[1] : a[0], hi1 = (G & 2) ? b[1] : b[0];
+  const auto c = __builtin_amdgcn_permlane16_swap(lo1, lo1, false, false);
+  const auto e = __builtin_amdgcn_permlane16_swap(hi1, hi1, false, false);
+  r0 = __builtin_bit_cast(double, ((unsigned long long)e[0] << 32) | c[0]);
+  r1 = __builtin_bit_cast(double, ((unsigned long long)e[1] << 32) | c[1]);
 }
 template <int P>
-__device__ inline double row_bcast(double x) {
-  return __builtin_amdgcn_update_dpp(0.0, x, 0x150 + P, 0xf, 0xf, false);
+__device__ inline double row_bcast(double old, double x) {
+  return __builtin_amdgcn_update_dpp(old, x, 0x150 + P, 0xf, 0xf, false);
 }
 template <int L>
 __device__ inline double lane_value(double x) {
@@ -1847,37 +1850,57 @@ __device__ inline double lane_value(double x) {
   return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
 }
 
-// One pivot step p of the in-wave Gauss-Jordan elimination (tile layout:
-// lane l, register v holds T[l/16 + 4v][l%16]).
+// Two pivot steps p, p + 1 (p even) of the in-wave Gauss-Jordan elimination
+// at once, as one step with the 2 x 2 pivot block B = {p, p + 1} (tile
+// layout: lane l, register v holds T[l/16 + 4v][l%16]; rows p and p + 1
+// share register p/4).  With P = T[B][B] = [[a, b], [c, e]]:
+//   T'[B][j] = P^-1 T[B][j],  T'[i][B] = -T[i][B] P^-1,  T'[B][B] = P^-1,
+//   T'[i][j] = T[i][j] - T[i][B] P^-1 T[B][j]          (i, j not in B),
+// which is the result of the two scalar steps.  The cross-lane moves (the
+// latency of the step) are shared by the two pivots: both pivot rows come
+// from one row-pair exchange, the columns from row broadcasts.  In lanes
+// j in B the pivot-row values are replaced by the identity columns, so the
+// same expressions give P^-1 in the pivot rows and -T[i][B] P^-1 in the
+// pivot columns (where x is masked to zero).  The scalar pivots of the
+// unblocked elimination are a and det(P) / a, and are tested as such.
 template <int p>
-__device__ inline void gj16_step(d4& c, int r0, int j, double tol, int nvalid, bool& bad) {
-  const double rowp = group_bcast<(p & 3)>(c[p >> 2]);          // T[p][j]
-  const double piv = lane_value<((p & 3) << 4) | p>(c[p >> 2]);   // T[p][p]
-  double colp[4];
-#pragma unroll
-  for (int v = 0; v < 4; ++v) colp[v] = row_bcast<p>(c[v]);      // T[r0 + 4v][p]
-  if (p < nvalid && !(piv > tol)) bad = true;
-  // 1/piv: hardware reciprocal refined by two Newton steps
-  double ip = __builtin_amdgcn_rcp(piv);
-  ip = fma(fma(-piv, ip, 1.0), ip, ip);
-  ip = fma(fma(-piv, ip, 1.0), ip, ip);
-  const double rs = rowp * ip;
-  // branch-free update (selects, no exec-mask regions): row p is scaled by
-  // 1/piv, column p becomes -x/piv, the pivot 1/piv, the rest x - colp*rs;
-  // only register p/4 holds part of row p
-  const bool cj = j == p;
+__device__ inline void gj16_step2(d4& c, int r0, int j, double tol, int nvalid, bool& bad,
+                                  d4 C0, d4 C1) {
+  constexpr int vp = p >> 2, gp = p & 3, gq = gp + 1;
+  double R0, R1;                                                // T[p][j], T[p+1][j]
+  pair_bcast<gp>(c[vp], R0, R1);
+  const double a = lane_value<(gp << 4) | p>(c[vp]);
+  const double b = lane_value<(gp << 4) | (p + 1)>(c[vp]);
+  const double cc = lane_value<(gq << 4) | p>(c[vp]);
+  const double e = lane_value<(gq << 4) | (p + 1)>(c[vp]);
+  // C0, C1 (the previous step's, dead now) serve as the old values
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
-    const double x = c[v];
-    const double yo = cj ? -x * ip : fma(-colp[v], rs, x);
-    if (v == (p >> 2)) {
-      const double yr = cj ? ip : x * ip;
-      c[v] = r0 == (p & 3) ? yr : yo;
-    } else {
-      c[v] = yo;
-    }
+    C0[v] = row_bcast<p>(C0[v], c[v]);                           // T[r0 + 4v][p]
+    C1[v] = row_bcast<p + 1>(C1[v], c[v]);                       // T[r0 + 4v][p+1]
   }
-  if constexpr (p < 15) gj16_step<p + 1>(c, r0, j, tol, nvalid, bad);
+  const double det = fma(a, e, -(b * cc));
+  if (p < nvalid && !(a > tol)) bad = true;
+  if (p + 1 < nvalid && !(det > tol * a)) bad = true;
+  // 1/det: hardware reciprocal refined by two Newton steps
+  double ip = __builtin_amdgcn_rcp(det);
+  ip = fma(fma(-det, ip, 1.0), ip, ip);
+  ip = fma(fma(-det, ip, 1.0), ip, ip);
+  const bool jb = j == p || j == p + 1;
+  const double S0 = jb ? (j == p ? 1.0 : 0.0) : R0;
+  const double S1 = jb ? (j == p ? 0.0 : 1.0) : R1;
+  const double M0 = fma(e, S0, -(b * S1)) * ip;                 // (P^-1 T[B][j])_0
+  const double M1 = fma(a, S1, -(cc * S0)) * ip;                // (P^-1 T[B][j])_1
+  const double mb = jb ? 0.0 : 1.0;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const double y = fma(-C0[v], M0, fma(-C1[v], M1, c[v] * mb));
+    if (v == vp)
+      c[v] = r0 == gp ? M0 : (r0 == gq ? M1 : y);
+    else
+      c[v] = y;
+  }
+  if constexpr (p < 14) gj16_step2<p + 2>(c, r0, j, tol, nvalid, bad, C0, C1);
 }
 
 // In-place Gauss-Jordan inverse of a 16x16 tile held by one wave in the
@@ -1885,7 +1908,7 @@ __device__ inline void gj16_step(d4& c, int r0, int j, double tol, int nvalid, b
 // not tested.  Returns true if a tested pivot is not above tol.
 __device__ inline bool wave_gj16(d4& c, int lane, double tol, int nvalid) {
   bool bad = false;
-  gj16_step<0>(c, lane >> 4, lane & 15, tol, nvalid, bad);
+  gj16_step2<0>(c, lane >> 4, lane & 15, tol, nvalid, bad, d4{0, 0, 0, 0}, d4{0, 0, 0, 0});
   return bad;
 }
 
