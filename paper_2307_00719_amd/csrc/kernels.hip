@@ -1947,18 +1947,27 @@ __device__ inline void gj_cols16(d4 (&A)[4], double* lds, int lane, int wave, in
     const bool nextp = K + 1 < nb;
     if (wave < nb) {
       if (wave != K) {
-        d4 U = {0, 0, 0, 0};
+        // two accumulators per product (k-steps 0, 1 and 2, 3): a dependent
+        // FP64 MFMA chain costs its full latency per step
+        d4 U0 = {0, 0, 0, 0}, U1 = {0, 0, 0, 0};
 #pragma unroll
-        for (int q = 0; q < 4; ++q) U = mfma16(Sc[K * 256 + q * 64 + lane], A[K][q], U);
+        for (int q = 0; q < 4; q += 2) {
+          U0 = mfma16(Sc[K * 256 + q * 64 + lane], A[K][q], U0);
+          U1 = mfma16(Sc[K * 256 + (q + 1) * 64 + lane], A[K][q + 1], U1);
+        }
+        const d4 U = U0 + U1;
 #pragma unroll
         for (int t = 1; t < 4; ++t) {
           const int i = (K + t) & 3;
           if (i < nb) {
             const double sg = i < K ? 1.0 : -1.0;
-            d4 acc = A[i];
+            d4 acc = A[i], acc1 = {0, 0, 0, 0};
 #pragma unroll
-            for (int q = 0; q < 4; ++q) acc = mfma16(sg * Sc[i * 256 + q * 64 + lane], U[q], acc);
-            A[i] = acc;
+            for (int q = 0; q < 4; q += 2) {
+              acc = mfma16(sg * Sc[i * 256 + q * 64 + lane], U[q], acc);
+              acc1 = mfma16(sg * Sc[i * 256 + (q + 1) * 64 + lane], U[q + 1], acc1);
+            }
+            A[i] = acc + acc1;
             if (t == 1 && nextp) {
               if (wave == K + 1) bad |= wave_gj16(A[i], lane, tol, d - 16 * (K + 1));
 #pragma unroll
@@ -1973,10 +1982,13 @@ __device__ inline void gj_cols16(d4 (&A)[4], double* lds, int lane, int wave, in
           const int i = (K + t) & 3;
           if (i < nb) {
             const double sg = i < K ? 1.0 : -1.0;
-            d4 acc = {0, 0, 0, 0};
+            d4 acc = {0, 0, 0, 0}, acc1 = {0, 0, 0, 0};
 #pragma unroll
-            for (int q = 0; q < 4; ++q) acc = mfma16(sg * Sc[i * 256 + q * 64 + lane], A[K][q], acc);
-            A[i] = acc;
+            for (int q = 0; q < 4; q += 2) {
+              acc = mfma16(sg * Sc[i * 256 + q * 64 + lane], A[K][q], acc);
+              acc1 = mfma16(sg * Sc[i * 256 + (q + 1) * 64 + lane], A[K][q + 1], acc1);
+            }
+            A[i] = acc + acc1;
             if (t == 1 && nextp) {
 #pragma unroll
               for (int v = 0; v < 4; ++v) Sn[wave * 256 + v * 64 + lane] = A[i][v];
@@ -2145,11 +2157,20 @@ __device__ inline void side_serial(const SideArgs& sa, double* lds, double* dmax
       if (staged) {
         const double* Ms = lds;
         const double* Fs = lds + d1 * d2p;
-#pragma unroll 8
-        for (int k0 = 0; k0 < kfull; k0 += 4) {
+        // two accumulators (alternate k-steps) halve the dependent chain
+        d4 acc1 = {0, 0, 0, 0};
+        int k0 = 0;
+#pragma unroll 4
+        for (; k0 + 8 <= kfull; k0 += 8) {
+          const int k = k0 + ak;
+          acc = mfma16(Ms[arow * d2p + k], Fs[k * d3 + bcol], acc);
+          acc1 = mfma16(Ms[arow * d2p + k + 4], Fs[(k + 4) * d3 + bcol], acc1);
+        }
+        if (k0 < kfull) {
           const int k = k0 + ak;
           acc = mfma16(Ms[arow * d2p + k], Fs[k * d3 + bcol], acc);
         }
+        acc += acc1;
       } else {
         int k0 = 0;
         for (; k0 + 32 <= kfull; k0 += 32) {
@@ -2431,10 +2452,10 @@ __device__ inline void gram_tile(const SideArgs& sa, double* lds, int tid, int t
   const double* __restrict__ Gp = sa.Gp;
   const int c1 = min(rb * 16 + ar, dp - 1), c2 = min(cb * 16 + ar, dp - 1);
   // KB k-steps of loads in flight per wave (16 with four waves, 8 with the
-  // 16-wave kernel's register budget); with four waves two accumulators
-  // (even and odd k-steps) halve the dependent MFMA chains
+  // 16-wave kernel's register budget); with four waves four accumulators
+  // (k-steps q mod 4) shorten the dependent MFMA chains
   constexpr int KB = NW <= 4 ? 16 : 8;
-  d4 acc0 = {0, 0, 0, 0}, acc1 = {0, 0, 0, 0};
+  d4 acc0 = {0, 0, 0, 0}, acc1 = {0, 0, 0, 0}, acc2 = {0, 0, 0, 0}, acc3 = {0, 0, 0, 0};
   for (int64_t k0 = wave; k0 < nks; k0 += KB * NW) {
     double av[KB], bv[KB];
 #pragma unroll
@@ -2450,9 +2471,11 @@ __device__ inline void gram_tile(const SideArgs& sa, double* lds, int tid, int t
     }
     if constexpr (NW <= 4) {
 #pragma unroll
-      for (int q = 0; q < KB; q += 2) {
+      for (int q = 0; q < KB; q += 4) {
         acc0 = mfma16(av[q], bv[q], acc0);
         acc1 = mfma16(av[q + 1], bv[q + 1], acc1);
+        acc2 = mfma16(av[q + 2], bv[q + 2], acc2);
+        acc3 = mfma16(av[q + 3], bv[q + 3], acc3);
       }
     } else {
 #pragma unroll
@@ -2461,7 +2484,7 @@ __device__ inline void gram_tile(const SideArgs& sa, double* lds, int tid, int t
   }
 #pragma unroll
   for (int v = 0; v < 4; ++v)
-    lds[wave * 256 + Acc<double>::row(lane, v) * 16 + ar] = acc0[v] + acc1[v];
+    lds[wave * 256 + Acc<double>::row(lane, v) * 16 + ar] = (acc0[v] + acc1[v]) + (acc2[v] + acc3[v]);
   __syncthreads();
   for (int e = tid; e < 256; e += 64 * NW) {
     double sum = 0.0;
@@ -2659,7 +2682,9 @@ __device__ inline void gram_chain_cols(const SideArgs& sa, const double* tl, con
   const int b1 = mir ? 2 * cb + u : 2 * rb + u, b2 = mir ? 2 * rb + v : 2 * cb + v;
   const bool colok = n < (rb == cb ? 4 : 8) && b1 < Rb && b2 < Rb;
   constexpr int d2p = 65;                   // padded rows of the staged E_a
-  d4 acc = {0, 0, 0, 0};
+  // four accumulators (k-steps q mod 4): a dependent FP64 MFMA chain costs
+  // its full latency per step
+  d4 ac[4] = {{0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}};
 #pragma unroll
   for (int q = 0; q < 16; ++q) {
     const int k = 4 * q + g4;               // k = a1 + 8 a2
@@ -2668,8 +2693,9 @@ __device__ inline void gram_chain_cols(const SideArgs& sa, const double* tl, con
     // tile entry (a2 + 8 v, a1 + 8 u)
     const int ti = mir ? a2 + 8 * v : a1 + 8 * u, tj = mir ? a1 + 8 * u : a2 + 8 * v;
     const double bv = colok ? tl[ti * 16 + tj] : 0.0;
-    acc = mfma16(lds[(16 * wave + l16) * d2p + k], bv, acc);
+    ac[q & 3] = mfma16(lds[(16 * wave + l16) * d2p + k], bv, ac[q & 3]);
   }
+  const d4 acc = (ac[0] + ac[1]) + (ac[2] + ac[3]);
   if (colok) {
 #pragma unroll
     for (int w = 0; w < 4; ++w) {
