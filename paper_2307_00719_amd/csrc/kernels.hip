@@ -124,6 +124,7 @@ MttkrpPlan plan_mttkrp(const Geom& g, int xdtype, int max_wg, bool bulk) {
   MttkrpPlan p;
   const int N = g.N;
   p.zform = 0;
+  p.ng = 1;
   p.MT = 16;
   p.mtiles = (int)((g.In + 15) / 16);
   p.psize = (xdtype == F64) ? 8 : 4;
@@ -260,14 +261,19 @@ __device__ inline int64_t outer_offset(const Geom& g, int64_t o) {
 // The K parts are summed in LDS in a fixed order, then U and V are applied
 // in FP64 and the result accumulated over the chunk.
 // ---------------------------------------------------------------------------
-template <typename T, typename TC, int NJ, int BQ = 0>
+template <typename T, typename TC, int NJ, int BQ = 0, int NG = 1>
 __device__ inline void mttkrp_body(const Geom& g, const MttkrpPlan& p, const T* __restrict__ X,
                                    const CoreView& cv, typename Acc<T>::type* __restrict__ part,
                                    int chunk, int mtile, char* smem) {
   typedef typename Acc<T>::type PT;
   typedef typename Acc<T>::vec V4;
   constexpr int KG = 8;                     // k-steps whose loads are issued together
-  const int tid = threadIdx.x, lane = tid & 63;
+  // NG groups of four waves take NG consecutive outer indices of the chunk
+  // at a time, each with its own LDS region; the groups run the same phases
+  // (barriers are workgroup-wide), a group past the chunk's end contributing
+  // zeros
+  const int grp = NG > 1 ? (int)(threadIdx.x >> 8) : 0;
+  const int tid = threadIdx.x & 255, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int N = g.N, n = g.n, f = p.f;
   const int Rn = g.R[n], Rn1 = g.R[n + 1 == N ? 0 : n + 1];
@@ -285,6 +291,9 @@ __device__ inline void mttkrp_body(const Geom& g, const MttkrpPlan& p, const T* 
   const int qV = f + 1 == N ? 0 : f + 1;
   const int wst = 16 * ((Rn1 * Rf1 + 15) / 16);
 
+  if constexpr (NG > 1)
+    smem += grp * ((((size_t)(3 * 256 + 16 * wst) * sizeof(double) +
+                     (size_t)(16 * dfp) * KS * sizeof(PT)) + 15) & ~(size_t)15);
   double* Us = (double*)smem;               // [16][16]
   double* Vs = Us + 256;                    // [16][16]
   double* tmp = Vs + 256;                   // [256]
@@ -330,7 +339,10 @@ __device__ inline void mttkrp_body(const Geom& g, const MttkrpPlan& p, const T* 
     }
   }
 
-  for (int64_t o = o0; o < o1; ++o) {
+  for (int64_t oo = o0; oo < o1; oo += NG) {
+    const bool ovalid = oo + grp < o1;
+    const int64_t o = ovalid ? oo + grp : o1 - 1;
+    const bool mok_o = mok && ovalid;
     const T* __restrict__ Xo = X + outer_offset(g, o);
     if (nU > 0) ring_product_lds<TC>(g, cv, o, qU, nU, Us, tmp, tid);
     if (nV > 0) ring_product_lds<TC>(g, cv, o, qV, nV, Vs, tmp, tid);
@@ -348,7 +360,7 @@ __device__ inline void mttkrp_body(const Geom& g, const MttkrpPlan& p, const T* 
         const bool ok = q < Q && k < If;
         const int kcl = k < If ? k : If - 1;
         const T x = Xo[arow + kcl * sf];
-        av[q] = ok && mok ? x : T(0);
+        av[q] = ok && mok_o ? x : T(0);
       }
 #pragma unroll
       for (int q = 0; q < BQ; ++q) {
@@ -365,7 +377,7 @@ __device__ inline void mttkrp_body(const Geom& g, const MttkrpPlan& p, const T* 
         const bool ok = kc + q < Q && k < If;
         const int kcl = k < If ? k : If - 1;
         const T x = Xo[arow + kcl * sf];
-        av[q] = ok && mok ? x : T(0);
+        av[q] = ok && mok_o ? x : T(0);
 #pragma unroll
         for (int j = 0; j < NJ; ++j) {
           const TC b = Gf[kcl * fsi + boff[j]];
@@ -458,6 +470,25 @@ __device__ inline void mttkrp_body(const Geom& g, const MttkrpPlan& p, const T* 
       }
     }
     __syncthreads();
+  }
+  if constexpr (NG > 1) {
+    // the groups' sums added in group order through the LDS region of
+    // group 1 (free after the loop's last barrier)
+    if (grp == 1) {
+#pragma unroll
+      for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) ((double*)smem)[(t * 4 + v) * 256 + tid] = pacc[t][v];
+    }
+    __syncthreads();
+    if (grp != 0) return;
+    const double* o1s = (const double*)(smem + ((((size_t)(3 * 256 + 16 * wst) * sizeof(double) +
+                                                   (size_t)(16 * dfp) * KS * sizeof(PT)) + 15) &
+                                                 ~(size_t)15));
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) pacc[t][v] += o1s[(t * 4 + v) * 256 + tid];
   }
 #pragma unroll
   for (int t = 0; t < 4; ++t) {
@@ -2724,8 +2755,8 @@ __device__ inline void mode_tile(int w, int nw, int nsplit, int mtiles, int* chu
   *mtile = 2 * (pr / nsplit) + (unit & 1);
 }
 
-template <typename T, typename TC, int NJ, int MAXT>
-__global__ __launch_bounds__(256, 2) void k_mode(Geom g, MttkrpPlan p, const T* __restrict__ X,
+template <typename T, typename TC, int NJ, int MAXT, int NG>
+__global__ __launch_bounds__(256 * NG, 2 / NG) void k_mode(Geom g, MttkrpPlan p, const T* __restrict__ X,
                                                  CoreView cv,
                                                  typename Acc<T>::type* __restrict__ part,
                                                  SideArgs sa) {
@@ -2734,6 +2765,9 @@ __global__ __launch_bounds__(256, 2) void k_mode(Geom g, MttkrpPlan p, const T* 
   const int nbp = (sa.Rpa * sa.Rpb + 15) >> 4;
   const int ngram = sa.Gp ? nbp * (nbp + 1) / 2 : 1;
   if ((int)blockIdx.x < ngram) {
+    // four waves: with 8-wave workgroups the other four end here (a barrier
+    // waits only for the waves that have not ended)
+    if (NG > 1 && threadIdx.x >= 256) return;
     // the side step is the longer chain: its waves take issue priority over
     // the MTTKRP waves sharing the compute unit
     __builtin_amdgcn_s_setprio(3);
@@ -2761,7 +2795,7 @@ __global__ __launch_bounds__(256, 2) void k_mode(Geom g, MttkrpPlan p, const T* 
   }
   int chunk, mtile;
   mode_tile(blockIdx.x - ngram, gridDim.x - ngram, p.nsplit, p.mtiles, &chunk, &mtile);
-  mttkrp_body<T, TC, NJ>(g, p, X, cv, part, chunk, mtile, smem);
+  mttkrp_body<T, TC, NJ, 0, NG>(g, p, X, cv, part, chunk, mtile, smem);
 }
 
 bool mode_fusable(const Geom& g, const SideArgs& sa) {
@@ -2778,12 +2812,27 @@ bool mode_fusable(const Geom& g, const SideArgs& sa) {
 // (modes 1 and 2: 26-28 us of MTTKRP); otherwise (FP32 operands, the
 // temporal mode) one outer index per workgroup, up to four workgroups per
 // compute unit; larger batches keep the plan of about 512 workgroups.
+// Pairs of outer indices on 8-wave workgroups (two groups of four waves,
+// one outer index each at a time) when the plan gives every workgroup at
+// least two and the workgroups fit beside the Gram workgroups one per
+// compute unit (their LDS takes most of one); otherwise 4-wave workgroups.
+static MttkrpPlan pair_groups(MttkrpPlan p, const Geom& g, int ncu, int ngram) {
+  if (getenv("TRSTREAM_NG1") || p.Kout < 2) return p;
+  const int64_t free_cu = ncu - ngram;
+  if (p.upw == 1 && (int64_t)p.mtiles * ((p.Kout + 1) / 2) <= free_cu) {
+    p.upw = 2;
+    p.nsplit = (int)((p.Kout + 1) / 2);
+  }
+  if (p.upw >= 2 && (int64_t)p.nsplit * p.mtiles <= free_cu) p.ng = 2;
+  return p;
+}
+
 MttkrpPlan plan_mode(const Geom& g, int xdtype, const SideArgs& sa, int ncu) {
   const int nbp = (sa.Rpa * sa.Rpb + 15) / 16;
   const int ngram = sa.Gp ? nbp * (nbp + 1) / 2 : 1;
   if (xdtype == F64 && ncu > ngram) {
     const MttkrpPlan p = plan_mttkrp(g, xdtype, ncu - ngram);
-    if (p.upw <= 2) return p;
+    if (p.upw <= 2) return pair_groups(p, g, ncu, ngram);
   }
   MttkrpPlan p = plan_mttkrp(g, xdtype);
   const int64_t wg1 = (int64_t)p.mtiles * p.Kout;   // one outer index per workgroup
@@ -2791,7 +2840,7 @@ MttkrpPlan plan_mode(const Geom& g, int xdtype, const SideArgs& sa, int ncu) {
     p.upw = 1;
     p.nsplit = (int)p.Kout;
   }
-  return p;
+  return pair_groups(p, g, ncu, ngram);
 }
 
 template <typename T, int NJ, int MAXT>
@@ -2804,8 +2853,14 @@ static hipError_t launch_mode_t(const Geom& g, const MttkrpPlan& p, const void* 
   const int wst = 16 * ((Rn1 * Rf1 + 15) / 16);
   const size_t lmt = (size_t)(3 * 256 + 16 * wst) * sizeof(double) +
                      (size_t)(16 * dfp) * p.KS * sizeof(PT);
-  const size_t lds = std::max(lmt, (size_t)SIDE_LDS_ALLOC * sizeof(double));
-  auto fn = k_mode<T, double, NJ, MAXT>;
+  // two groups of four waves (two outer indices at a time) when the plan
+  // says so: per group its own region, and room in the second for the 16
+  // doubles per thread that carry its sums to the first
+  const int ng = p.ng == 2 && p.upw >= 2 ? 2 : 1;
+  const size_t lgrp = (lmt + 15) & ~(size_t)15;
+  const size_t lmg = ng == 2 ? lgrp + std::max(lgrp, (size_t)(16 * 256 * sizeof(double))) : lmt;
+  const size_t lds = std::max(lmg, (size_t)SIDE_LDS_ALLOC * sizeof(double));
+  auto fn = ng == 2 ? k_mode<T, double, NJ, MAXT, 2> : k_mode<T, double, NJ, MAXT, 1>;
   if (lds > 65536) {
     hipError_t e = hipFuncSetAttribute((const void*)fn,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -2814,7 +2869,7 @@ static hipError_t launch_mode_t(const Geom& g, const MttkrpPlan& p, const void* 
   const int nbp = (sa.Rpa * sa.Rpb + 15) / 16;
   const unsigned ngram = sa.Gp ? (unsigned)(nbp * (nbp + 1) / 2) : 1u;
   const unsigned grid = ngram + (unsigned)p.nsplit * (unsigned)p.mtiles;
-  hipLaunchKernelGGL(fn, dim3(grid), dim3(256), lds, st, g, p, (const T*)X, cv,
+  hipLaunchKernelGGL(fn, dim3(grid), dim3(256 * ng), lds, st, g, p, (const T*)X, cv,
                      (typename Acc<T>::type*)part, sa);
   return hipGetLastError();
 }

@@ -50,6 +50,8 @@ struct MttkrpPlan {
   int64_t Kout;    // number of outer indices
   int64_t upw;     // outer indices per workgroup
   int64_t sf, sm;  // X strides of i_f and of the row index i_n
+  int ng;          // fused launch: groups of four waves per workgroup, each
+                   // taking one outer index of a pair at a time (1 or 2)
   int zform;       // 1: subchain blocks formed per outer index in LDS (FP32,
                    // order <= 4, ranks <= 16, I_f <= 64; MT rows per workgroup)
 };
