@@ -311,7 +311,8 @@ def pmc_summary(fetch_dir, write_dir):
         grids = sorted(f_per[dt], key=lambda gsz: len(f_per[dt][gsz]))
         gt, gn = grids[0], grids[-1]         # temporal: one launch per update
         avg = lambda v: sum(v) / len(v)      # noqa: E731
-        rec = {"kernel": "k_mode", "instance": f"k_mode<{'double' if dt == 'f64' else 'float'}, double, 4, 4>",
+        rec = {"kernel": "k_mode",
+               "instance": f"k_mode<{'double' if dt == 'f64' else 'float'}, double, 4, 4, NG> (NG = 1, 2)",
                "workload": f"256x256 x 20-slice batch, TR-ranks 8, {dt} operands",
                "source_hash": kernel_source_hash(),
                "temporal": {"read": avg(f_per[dt][gt]), "write": avg(w_per[dt][gt]),
@@ -353,14 +354,17 @@ def kernel_stats_summary(stats_dir):
     table.sort(key=lambda t: -t["percent"])
 
     def avg(tag):
+        # every instantiation of the fused kernel (4- or 8-wave workgroups),
+        # weighted by its launches
         c = [t for t in table if tag in t["kernel"]]
-        return c[0]["avg_us"] if c else None
+        n = sum(t["calls"] for t in c)
+        return sum(t["avg_us"] * t["calls"] for t in c) / n if n else None
 
     rec = {"source_hash": kernel_source_hash(),
            "workload": "256x256x1000 stream, TR-ranks 8, batches of 20 slices",
-           "f64_kernel": "trk::k_mode<double, double, 4, 4>",
+           "f64_kernel": "trk::k_mode<double, double, 4, 4, NG> (NG = 1, 2)",
            "f64_avg_us": avg("trk::k_mode<double, double"),
-           "f32_kernel": "trk::k_mode<float, double, 4, 4>",
+           "f32_kernel": "trk::k_mode<float, double, 4, 4, NG> (NG = 1, 2)",
            "f32_avg_us": avg("trk::k_mode<float, double"),
            "command": "cd /tmp && export TMPDIR=/tmp && rocprofv3 --kernel-trace --stats -d "
                       "<repo>/gpurun_out/prof_c2 -o c2 --output-format csv -- python3 <repo>/bench.py "
