@@ -124,6 +124,8 @@ MttkrpPlan plan_mttkrp(const Geom& g, int xdtype, int max_wg, bool bulk) {
   MttkrpPlan p;
   const int N = g.N;
   p.zform = 0;
+  p.prv = 0;
+  p.prv_in = 0;
   p.ng = 1;
   p.MT = 16;
   p.mtiles = (int)((g.In + 15) / 16);
@@ -180,7 +182,11 @@ MttkrpPlan plan_mttkrp(const Geom& g, int xdtype, int max_wg, bool bulk) {
 }
 
 size_t mttkrp_partial_bytes(const Geom& g, const MttkrpPlan& p) {
-  return (size_t)p.nsplit * (size_t)g.In * (size_t)g.d * (size_t)p.psize;
+  const size_t b = (size_t)p.nsplit * (size_t)g.In * (size_t)g.d * (size_t)p.psize;
+  if (!p.prv) return b;
+  // one partial row of R_2 R_0 per (row tile, t)
+  const size_t bp = (size_t)p.mtiles * (size_t)p.prv_in * (size_t)(g.R[2] * g.R[0]) * p.psize;
+  return b > bp ? b : bp;
 }
 
 // Index i_q (q != n, f) of outer index o of mode n, in the enumeration of
@@ -287,6 +293,7 @@ __device__ inline void mttkrp_body(const Geom& g, const MttkrpPlan& p, const T* 
   const int kbase = (kslot * 4 + g4) * Q;
   const int nU = (f - (n + 1) + N) % N;
   const int nV = (n - (f + 1) + N) % N;
+  const bool prv = p.prv != 0;
   const int qU = n + 1 == N ? 0 : n + 1;
   const int qV = f + 1 == N ? 0 : f + 1;
   const int wst = 16 * ((Rn1 * Rf1 + 15) / 16);
@@ -344,8 +351,8 @@ __device__ inline void mttkrp_body(const Geom& g, const MttkrpPlan& p, const T* 
     const int64_t o = ovalid ? oo + grp : o1 - 1;
     const bool mok_o = mok && ovalid;
     const T* __restrict__ Xo = X + outer_offset(g, o);
-    if (nU > 0) ring_product_lds<TC>(g, cv, o, qU, nU, Us, tmp, tid);
-    if (nV > 0) ring_product_lds<TC>(g, cv, o, qV, nV, Vs, tmp, tid);
+    if (nU > 0 && !prv) ring_product_lds<TC>(g, cv, o, qU, nU, Us, tmp, tid);
+    if (nV > 0 && !prv) ring_product_lds<TC>(g, cv, o, qV, nV, Vs, tmp, tid);
     // GEMM part: acc[j] = 16 x 16 tile (rows m, columns cslot + CS j) of
     // this wave's K part; the loads of KG k-steps are issued before their
     // MFMAs, and out-of-range k contribute zeros
@@ -419,6 +426,40 @@ __device__ inline void mttkrp_body(const Geom& g, const MttkrpPlan& p, const T* 
       }
     }
     __syncthreads();
+    if (prv) {
+      // order-3 temporal mode in mode 1's geometry: rows are i_1 and the
+      // outer index is t, so P_2[t][r + R_2 s] gets
+      //   sum_m sum_b Y[m][s + R_0 b] G_1(i_1 = m0 + m)[b][r]
+      // over this tile's 16 rows: the slices staged in Ws, one output
+      // column per lane, the four row groups of the workgroup's waves
+      // summed in LDS in a fixed order; one partial row per (row tile, t)
+      const int R0 = g.R[0], R1 = g.R[1], R2 = g.R[2], d12 = R1 * R2, dout = R2 * R0;
+      const TC* __restrict__ G1 = (const TC*)cv.ptr[1];
+      for (int e = tid; e < 16 * d12; e += 256) {
+        const int m = e / d12, k = e - m * d12;
+        const int64_t i = m0 + m < g.In ? m0 + m : g.In - 1;
+        Ws[m * wst + k] = (double)G1[i * cv.si[1] + (k % R1) * cv.sr[1] + (k / R1) * cv.ss[1]];
+      }
+      __syncthreads();
+      const int out = tid & 63, rg = tid >> 6, r = out % R2, sx = out / R2;
+      double acc = 0.0;
+      if (out < dout) {
+#pragma unroll
+        for (int mm = 0; mm < 4; ++mm) {
+          const int m = 4 * rg + mm;
+          for (int b = 0; b < R1; ++b)
+            acc = fma((double)Ys[m * dfp + sx + R0 * b], Ws[m * wst + b + R1 * r], acc);
+        }
+      }
+      Us[rg * 64 + out] = acc;
+      __syncthreads();
+      if (tid < dout && ovalid) {
+        const double v = ((Us[tid] + Us[64 + tid]) + Us[128 + tid]) + Us[192 + tid];
+        part[((size_t)mtile * p.prv_in + o) * dout + tid] = (PT)v;
+      }
+      __syncthreads();
+      continue;
+    }
     // Contraction with U and V on FP64 MFMAs (16x16x4; the K index a or b
     // padded to 16 with zeros, U and V are zero-padded 16 x 16 in LDS):
     //   W_b = Y_b U^T       (W[m][s + Rn1 b] = sum_a U[s][a] Y[m][a + Rf b]),
@@ -471,6 +512,7 @@ __device__ inline void mttkrp_body(const Geom& g, const MttkrpPlan& p, const T* 
     }
     __syncthreads();
   }
+  if (prv) return;
   if constexpr (NG > 1) {
     // the groups' sums added in group order through the LDS region of
     // group 1 (free after the loop's last barrier)

@@ -1247,17 +1247,26 @@ tr_status str_pass(tr_stream* s, const void* Xd, int64_t t_new, double* Gnew) {
       const bool temporal = n == N - 1;
       Geom g = make_geom(N, gd.data(), s->R, n);
       const SideArgs sa = side_of(n);
-      MttkrpPlan p = plan_mode(g, s->dt, sa, s->ncu);
-      c = ensure_partials(s, g, p);
+      // order 3: the temporal MTTKRP runs in mode 1's GEMM geometry (rows
+      // i_1, outer index t; no padding of the batch's rows to 16) with the
+      // slice G_1(i_1) applied per row, one partial per row tile
+      const bool prv = temporal && N == 3 && !getenv("TRSTREAM_NOPRV");
+      const Geom gm = prv ? make_geom(N, gd.data(), s->R, 1) : g;
+      MttkrpPlan p = plan_mode(gm, s->dt, sa, s->ncu);
+      if (prv) {
+        p.prv = 1;
+        p.prv_in = (int)g.In;
+      }
+      c = ensure_partials(s, gm, p);
       if (c != TR_OK) return c;
       const CoreView cv = state_view(s, Gnew);
       pr = prof_begin(s, temporal ? PK_MTT_T : PK_MTT_N);
-      TR_HIP(launch_mode(g, p, Xd, s->dt, cv, F64, s->part, sa, s->st));
+      TR_HIP(launch_mode(gm, p, Xd, s->dt, cv, F64, s->part, sa, s->st));
       prof_end(s, pr);
       pr = prof_begin(s, PK_SOLVE);
       if (temporal)
-        TR_HIP(launch_reduce_solve(s->part, p.psize, p.nsplit, g.In, g.d, nullptr, 0,
-                                   s->MinvM[N - 1], Gnew, s->st));
+        TR_HIP(launch_reduce_solve(s->part, p.psize, prv ? p.mtiles : p.nsplit, g.In, g.d,
+                                   nullptr, 0, s->MinvM[N - 1], Gnew, s->st));
       else
         TR_HIP(launch_reduce_solve(s->part, p.psize, p.nsplit, g.In, g.d, s->P[n], 1,
                                    s->MinvM[n], s->G[n], s->st));

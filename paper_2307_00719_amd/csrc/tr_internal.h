@@ -50,6 +50,10 @@ struct MttkrpPlan {
   int64_t Kout;    // number of outer indices
   int64_t upw;     // outer indices per workgroup
   int64_t sf, sm;  // X strides of i_f and of the row index i_n
+  int prv;         // 1: order-3 temporal MTTKRP in mode 1's GEMM geometry (rows
+                   // i_1, outer index t) with the row-dependent slice G_1(i_1)
+                   // applied per row; partial = row tile, output row = t
+  int prv_in;      // output rows when prv (the batch's slices)
   int ng;          // fused launch: groups of four waves per workgroup, each
                    // taking one outer index of a pair at a time (1 or 2)
   int zform;       // 1: subchain blocks formed per outer index in LDS (FP32,
