@@ -267,7 +267,7 @@ __device__ inline int64_t outer_offset(const Geom& g, int64_t o) {
 // The K parts are summed in LDS in a fixed order, then U and V are applied
 // in FP64 and the result accumulated over the chunk.
 // ---------------------------------------------------------------------------
-template <typename T, typename TC, int NJ, int BQ = 0, int NG = 1>
+template <typename T, typename TC, int NJ, int BQ = 0, int NG = 1, bool PRV = false>
 __device__ inline void mttkrp_body(const Geom& g, const MttkrpPlan& p, const T* __restrict__ X,
                                    const CoreView& cv, typename Acc<T>::type* __restrict__ part,
                                    int chunk, int mtile, char* smem) {
@@ -293,7 +293,7 @@ __device__ inline void mttkrp_body(const Geom& g, const MttkrpPlan& p, const T* 
   const int kbase = (kslot * 4 + g4) * Q;
   const int nU = (f - (n + 1) + N) % N;
   const int nV = (n - (f + 1) + N) % N;
-  const bool prv = p.prv != 0;
+  constexpr bool prv = PRV;
   const int qU = n + 1 == N ? 0 : n + 1;
   const int qV = f + 1 == N ? 0 : f + 1;
   const int wst = 16 * ((Rn1 * Rf1 + 15) / 16);
@@ -426,7 +426,7 @@ __device__ inline void mttkrp_body(const Geom& g, const MttkrpPlan& p, const T* 
       }
     }
     __syncthreads();
-    if (prv) {
+    if constexpr (prv) {
       // order-3 temporal mode in mode 1's geometry: rows are i_1 and the
       // outer index is t, so P_2[t][r + R_2 s] gets
       //   sum_m sum_b Y[m][s + R_0 b] G_1(i_1 = m0 + m)[b][r]
@@ -512,7 +512,7 @@ __device__ inline void mttkrp_body(const Geom& g, const MttkrpPlan& p, const T* 
     }
     __syncthreads();
   }
-  if (prv) return;
+  if constexpr (prv) return;
   if constexpr (NG > 1) {
     // the groups' sums added in group order through the LDS region of
     // group 1 (free after the loop's last barrier)
@@ -2797,7 +2797,7 @@ __device__ inline void mode_tile(int w, int nw, int nsplit, int mtiles, int* chu
   *mtile = 2 * (pr / nsplit) + (unit & 1);
 }
 
-template <typename T, typename TC, int NJ, int MAXT, int NG>
+template <typename T, typename TC, int NJ, int MAXT, int NG, bool PRV>
 __global__ __launch_bounds__(256 * NG, 2 / NG) void k_mode(Geom g, MttkrpPlan p, const T* __restrict__ X,
                                                  CoreView cv,
                                                  typename Acc<T>::type* __restrict__ part,
@@ -2837,7 +2837,7 @@ __global__ __launch_bounds__(256 * NG, 2 / NG) void k_mode(Geom g, MttkrpPlan p,
   }
   int chunk, mtile;
   mode_tile(blockIdx.x - ngram, gridDim.x - ngram, p.nsplit, p.mtiles, &chunk, &mtile);
-  mttkrp_body<T, TC, NJ, 0, NG>(g, p, X, cv, part, chunk, mtile, smem);
+  mttkrp_body<T, TC, NJ, 0, NG, PRV>(g, p, X, cv, part, chunk, mtile, smem);
 }
 
 bool mode_fusable(const Geom& g, const SideArgs& sa) {
@@ -2902,7 +2902,11 @@ static hipError_t launch_mode_t(const Geom& g, const MttkrpPlan& p, const void* 
   const size_t lgrp = (lmt + 15) & ~(size_t)15;
   const size_t lmg = ng == 2 ? lgrp + std::max(lgrp, (size_t)(16 * 256 * sizeof(double))) : lmt;
   const size_t lds = std::max(lmg, (size_t)SIDE_LDS_ALLOC * sizeof(double));
-  auto fn = ng == 2 ? k_mode<T, double, NJ, MAXT, 2> : k_mode<T, double, NJ, MAXT, 1>;
+  // the per-row temporal form only on 8-wave workgroups (the planner's rule)
+  if (p.prv && ng != 2) return hipErrorInvalidValue;
+  auto fn = p.prv ? k_mode<T, double, NJ, MAXT, 2, true>
+                  : (ng == 2 ? k_mode<T, double, NJ, MAXT, 2, false>
+                             : k_mode<T, double, NJ, MAXT, 1, false>);
   if (lds > 65536) {
     hipError_t e = hipFuncSetAttribute((const void*)fn,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);

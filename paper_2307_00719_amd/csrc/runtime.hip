@@ -1250,12 +1250,20 @@ tr_status str_pass(tr_stream* s, const void* Xd, int64_t t_new, double* Gnew) {
       // order 3: the temporal MTTKRP runs in mode 1's GEMM geometry (rows
       // i_1, outer index t; no padding of the batch's rows to 16) with the
       // slice G_1(i_1) applied per row, one partial per row tile
-      const bool prv = temporal && N == 3 && !getenv("TRSTREAM_NOPRV");
-      const Geom gm = prv ? make_geom(N, gd.data(), s->R, 1) : g;
-      MttkrpPlan p = plan_mode(gm, s->dt, sa, s->ncu);
+      // (on 8-wave workgroups: the planner must give outer-index pairs)
+      bool prv = temporal && N == 3 && !getenv("TRSTREAM_NOPRV");
+      Geom gm = g;
+      MttkrpPlan p;
       if (prv) {
-        p.prv = 1;
+        gm = make_geom(N, gd.data(), s->R, 1);
+        p = plan_mode(gm, s->dt, sa, s->ncu);
+        prv = p.ng == 2;
+        p.prv = prv ? 1 : 0;
         p.prv_in = (int)g.In;
+      }
+      if (!prv) {
+        gm = g;
+        p = plan_mode(g, s->dt, sa, s->ncu);
       }
       c = ensure_partials(s, gm, p);
       if (c != TR_OK) return c;
