@@ -299,26 +299,32 @@ def pmc_summary(fetch_dir, write_dir):
         scale = known / (max(copy) * 1024.0)
         per = {}
         for dt, tag in (("f64", "k_mode<double"), ("f32", "k_mode<float")):
-            groups = {}
-            for r in rs:
-                if tag in r["Kernel_Name"]:
-                    groups.setdefault(grid(r), []).append(float(r["Counter_Value"]) * 1024 * scale)
+            # every update is three fused launches, the temporal mode first
+            # (the start's sweeps use the separate MTTKRP kernel), so the
+            # launch's place in dispatch order tells the modes apart
+            ks = sorted((r for r in rs if tag in r["Kernel_Name"]), key=lambda r: int(r["Dispatch_Id"]))
+            groups = {"temporal": [], "non_temporal": [], "grid": {}}
+            for i, r in enumerate(ks):
+                key = "temporal" if i % 3 == 0 else "non_temporal"
+                groups[key].append(float(r["Counter_Value"]) * 1024 * scale)
+                groups["grid"][key] = grid(r)
             per[dt] = groups
         res[cname] = (scale, per)
     for dt in ("f64", "f32"):
         f_scale, f_per = res["FETCH_SIZE"]
         w_scale, w_per = res["WRITE_SIZE"]
-        grids = sorted(f_per[dt], key=lambda gsz: len(f_per[dt][gsz]))
-        gt, gn = grids[0], grids[-1]         # temporal: one launch per update
         avg = lambda v: sum(v) / len(v)      # noqa: E731
         rec = {"kernel": "k_mode",
                "instance": f"k_mode<{'double' if dt == 'f64' else 'float'}, double, 4, 4, NG> (NG = 1, 2)",
                "workload": f"256x256 x 20-slice batch, TR-ranks 8, {dt} operands",
                "source_hash": kernel_source_hash(),
-               "temporal": {"read": avg(f_per[dt][gt]), "write": avg(w_per[dt][gt]),
-                            "launches": len(f_per[dt][gt]), "grid_workitems": gt},
-               "non_temporal": {"read": avg(f_per[dt][gn]), "write": avg(w_per[dt][gn]),
-                                "launches": len(f_per[dt][gn]), "grid_workitems": gn},
+               "temporal": {"read": avg(f_per[dt]["temporal"]), "write": avg(w_per[dt]["temporal"]),
+                            "launches": len(f_per[dt]["temporal"]),
+                            "grid_workitems": f_per[dt]["grid"]["temporal"]},
+               "non_temporal": {"read": avg(f_per[dt]["non_temporal"]),
+                                "write": avg(w_per[dt]["non_temporal"]),
+                                "launches": len(f_per[dt]["non_temporal"]),
+                                "grid_workitems": f_per[dt]["grid"]["non_temporal"]},
                "fetch_scale": f_scale, "write_scale": w_scale}
         rec["read_bytes_per_launch"] = (rec["temporal"]["read"] + 2 * rec["non_temporal"]["read"]) / 3
         rec["write_bytes_per_launch"] = (rec["temporal"]["write"] + 2 * rec["non_temporal"]["write"]) / 3
