@@ -298,9 +298,10 @@ __device__ inline void mttkrp_body(const Geom& g, const MttkrpPlan& p, const T* 
   const int qV = f + 1 == N ? 0 : f + 1;
   const int wst = 16 * ((Rn1 * Rf1 + 15) / 16);
 
-  if constexpr (NG > 1)
-    smem += grp * ((((size_t)(3 * 256 + 16 * wst) * sizeof(double) +
-                     (size_t)(16 * dfp) * KS * sizeof(PT)) + 15) & ~(size_t)15);
+  // bytes of one group's LDS region (the launcher's per-group size)
+  const size_t gbytes = (((size_t)(3 * 256 + 16 * wst) * sizeof(double) +
+                          (size_t)(16 * dfp) * KS * sizeof(PT)) + 15) & ~(size_t)15;
+  if constexpr (NG > 1) smem += grp * gbytes;
   double* Us = (double*)smem;               // [16][16]
   double* Vs = Us + 256;                    // [16][16]
   double* tmp = Vs + 256;                   // [256]
@@ -524,9 +525,7 @@ __device__ inline void mttkrp_body(const Geom& g, const MttkrpPlan& p, const T* 
     }
     __syncthreads();
     if (grp != 0) return;
-    const double* o1s = (const double*)(smem + ((((size_t)(3 * 256 + 16 * wst) * sizeof(double) +
-                                                   (size_t)(16 * dfp) * KS * sizeof(PT)) + 15) &
-                                                 ~(size_t)15));
+    const double* o1s = (const double*)(smem + gbytes);
 #pragma unroll
     for (int t = 0; t < 4; ++t)
 #pragma unroll
